@@ -1,0 +1,278 @@
+"""Seeded synthetic inputs: Ta-like lattices, liquids and neighbour lists.
+
+This module holds no descriptor, energy or force arithmetic.  It builds the
+inputs of the POD path -- positions, periodic cells, full neighbour lists in
+CSR form and coefficient vectors -- from fixed numpy seeds, with the shapes of
+the paper's workloads: BCC tantalum boxes like the 20x20x20 (16,000-atom)
+molecular-dynamics cell of its timing study (Sec. V.A), and mixed BCC / FCC /
+A15 / liquid cells like its training set (Sec. V.A).  The training set itself
+is not reproduced; these synthetic structures only share its shapes.
+
+Neighbour-list contract (what the library expects):
+  * a full list, both directions, sorted by centre atom;
+  * every (i, j, n) with 0 < |r_j + n.cell - r_i| < rcut, n in Z^3;
+  * periodic images are distinct entries, i == j allowed for n != 0;
+  * ``shift`` packs n as three signed bytes (x | y << 8 | z << 16).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+A_TA = 3.31  # BCC lattice constant used for the tantalum-like boxes (angstrom)
+
+
+# --------------------------------------------------------------------------
+# Lattices
+# --------------------------------------------------------------------------
+_BASIS = {
+    "bcc": np.array([[0.0, 0.0, 0.0], [0.5, 0.5, 0.5]]),
+    "fcc": np.array([[0.0, 0.0, 0.0], [0.5, 0.5, 0.0], [0.5, 0.0, 0.5], [0.0, 0.5, 0.5]]),
+    # A15 (Cr3Si type, all sites the same species): 2a + 6c Wyckoff positions
+    "a15": np.array([
+        [0.0, 0.0, 0.0], [0.5, 0.5, 0.5],
+        [0.25, 0.5, 0.0], [0.75, 0.5, 0.0],
+        [0.0, 0.25, 0.5], [0.0, 0.75, 0.5],
+        [0.5, 0.0, 0.25], [0.5, 0.0, 0.75],
+    ]),
+}
+
+
+def lattice(kind: str, n1: int, n2: int, n3: int, a: float):
+    """Sites of an n1 x n2 x n3 supercell of a cubic lattice; returns (pos, cell)."""
+    basis = _BASIS[kind]
+    g = np.stack(np.meshgrid(np.arange(n1), np.arange(n2), np.arange(n3), indexing="ij"), -1)
+    g = g.reshape(-1, 1, 3) + basis[None, :, :]
+    pos = g.reshape(-1, 3) * a
+    cell = np.diag([n1 * a, n2 * a, n3 * a]).astype(np.float64)
+    return pos.astype(np.float64), cell
+
+
+def bcc(n: int, a: float = A_TA):
+    return lattice("bcc", n, n, n, a)
+
+
+def displace(pos, sigma: float, seed: int):
+    rng = np.random.default_rng(seed)
+    return pos + rng.normal(0.0, sigma, size=pos.shape)
+
+
+def remove_sites(pos, n_remove: int, seed: int):
+    rng = np.random.default_rng(seed)
+    keep = np.sort(rng.choice(pos.shape[0], size=pos.shape[0] - n_remove, replace=False))
+    return pos[keep]
+
+
+def random_liquid(n: int, box: float, dmin: float, seed: int, max_tries: int = 200000):
+    """Random sequential insertion of n points in a periodic cube, keeping every
+    periodic distance >= dmin."""
+    rng = np.random.default_rng(seed)
+    pts = np.zeros((0, 3))
+    tries = 0
+    while pts.shape[0] < n:
+        tries += 1
+        if tries > max_tries:
+            raise RuntimeError("random_liquid: packing too dense")
+        x = rng.uniform(0.0, box, size=3)
+        if pts.shape[0]:
+            d = pts - x
+            d -= box * np.round(d / box)
+            if np.min((d * d).sum(1)) < dmin * dmin:
+                continue
+        pts = np.vstack([pts, x])
+    return pts, np.eye(3) * box
+
+
+# --------------------------------------------------------------------------
+# Neighbour lists
+# --------------------------------------------------------------------------
+@dataclass
+class NeighborList:
+    offsets: np.ndarray   # int32 [N+1]
+    nbr_j: np.ndarray     # int32 [P]
+    shift3: np.ndarray    # int32 [P, 3]
+    shift: np.ndarray     # int32 [P], packed signed bytes
+
+    @property
+    def n_pairs(self) -> int:
+        return int(self.offsets[-1])
+
+
+def pack_shift(shift3):
+    s = np.asarray(shift3, dtype=np.int64)
+    if s.size and (s.min() < -128 or s.max() > 127):
+        raise ValueError("image shift outside the signed-byte range")
+    s = s & 0xFF
+    return (s[:, 0] | (s[:, 1] << 8) | (s[:, 2] << 16)).astype(np.int32)
+
+
+def _finish(N, i, j, sh):
+    order = np.lexsort((sh[:, 2], sh[:, 1], sh[:, 0], j, i))
+    i, j, sh = i[order], j[order], sh[order]
+    counts = np.bincount(i, minlength=N)
+    offsets = np.zeros(N + 1, dtype=np.int64)
+    offsets[1:] = np.cumsum(counts)
+    if offsets[-1] > np.iinfo(np.int32).max:
+        raise ValueError("too many pairs for 32-bit offsets")
+    sh = sh.astype(np.int32)
+    return NeighborList(offsets.astype(np.int32), j.astype(np.int32), sh, pack_shift(sh))
+
+
+def neighbor_list(pos, cell, rcut: float) -> NeighborList:
+    """Full neighbour list within rcut (strict) for a periodic cell (rows are
+    lattice vectors) or an open system (cell None)."""
+    from scipy.spatial import cKDTree
+
+    pos = np.asarray(pos, dtype=np.float64)
+    N = pos.shape[0]
+    if N == 0:
+        return _finish(0, np.zeros(0, np.int64), np.zeros(0, np.int64), np.zeros((0, 3), np.int64))
+    if cell is None:
+        tree = cKDTree(pos)
+        sm = tree.sparse_distance_matrix(tree, rcut, output_type="ndarray")
+        i, j = sm["i"].astype(np.int64), sm["j"].astype(np.int64)
+        d = pos[j] - pos[i]
+        r = np.sqrt((d * d).sum(1))
+        keep = (r > 0) & (r < rcut)
+        return _finish(N, i[keep], j[keep], np.zeros((int(keep.sum()), 3), np.int64))
+    cell = np.asarray(cell, dtype=np.float64)
+    diag = np.diag(cell)
+    ortho = np.allclose(cell, np.diag(diag))
+    if ortho and np.all(diag > 2.0 * rcut + 1e-9):
+        # minimum image is unique: periodic KD-tree
+        wrapped = np.mod(pos, diag)
+        wrapped[wrapped >= diag] = 0.0
+        tree = cKDTree(wrapped, boxsize=diag)
+        sm = tree.sparse_distance_matrix(tree, rcut, output_type="ndarray")
+        i, j = sm["i"].astype(np.int64), sm["j"].astype(np.int64)
+        raw = pos[j] - pos[i]
+        n = -np.round(raw / diag).astype(np.int64)
+        d = raw + n * diag
+        r = np.sqrt((d * d).sum(1))
+        keep = (r > 0) & (r < rcut)
+        return _finish(N, i[keep], j[keep], n[keep])
+    # general / small cell: replicate images
+    inv = np.linalg.inv(cell)
+    spacing = 1.0 / np.linalg.norm(inv, axis=0)
+    nimg = np.ceil(rcut / spacing).astype(int) + 1
+    rng = [np.arange(-k, k + 1) for k in nimg]
+    imgs = np.array([[a, b, c] for a in rng[0] for b in rng[1] for c in rng[2]], dtype=np.int64)
+    big = (pos[None, :, :] + (imgs @ cell)[:, None, :]).reshape(-1, 3)
+    tree = cKDTree(big)
+    hits = tree.query_ball_point(pos, rcut)
+    ii, jj, nn = [], [], []
+    for a, lst in enumerate(hits):
+        if not lst:
+            continue
+        lst = np.asarray(lst, dtype=np.int64)
+        im, j = lst // N, lst % N
+        d = big[lst] - pos[a]
+        r = np.sqrt((d * d).sum(1))
+        keep = (r > 0) & (r < rcut)
+        ii.append(np.full(int(keep.sum()), a, np.int64))
+        jj.append(j[keep])
+        nn.append(imgs[im[keep]])
+    if not ii:
+        return _finish(N, np.zeros(0, np.int64), np.zeros(0, np.int64), np.zeros((0, 3), np.int64))
+    return _finish(N, np.concatenate(ii), np.concatenate(jj), np.concatenate(nn))
+
+
+def min_pair_distance(pos, cell, nl: NeighborList) -> float:
+    if nl.n_pairs == 0:
+        return np.inf
+    i = np.repeat(np.arange(pos.shape[0]), np.diff(nl.offsets))
+    cellm = np.zeros((3, 3)) if cell is None else np.asarray(cell)
+    d = pos[nl.nbr_j] + nl.shift3 @ cellm - pos[i]
+    return float(np.sqrt((d * d).sum(1)).min())
+
+
+# --------------------------------------------------------------------------
+# Workloads
+# --------------------------------------------------------------------------
+@dataclass
+class PodSetup:
+    """Radial / angular / body-order parameters of one workload."""
+    rin: float
+    rcut: float
+    L: int
+    K2: int
+    K3: int
+    K4: int
+    P3: int
+    P4: int
+    beta: float = 3.0
+
+    def snapshot_family(self):
+        """Bessel snapshots alpha = 1..L-2 at one beta (kappa = 1) plus
+        inverse-power snapshots gamma = 1, 2 (kappa = 0)."""
+        nb = self.L - 2
+        alpha = np.concatenate([np.arange(1, nb + 1, dtype=float), np.zeros(2)])
+        beta = np.concatenate([np.full(nb, self.beta), np.zeros(2)])
+        gamma = np.concatenate([np.zeros(nb), np.array([1.0, 2.0])])
+        kappa = np.concatenate([np.ones(nb), np.zeros(2)])
+        return alpha, beta, gamma, kappa
+
+    @property
+    def M(self) -> int:
+        ka = _n_partitions3(self.P4) if self.K4 > 0 else 0
+        return 1 + self.K2 + (self.K3 * (self.P3 + 1) if self.K3 else 0) + self.K4 * ka
+
+
+def _n_partitions3(P):
+    return sum(1 for n in range(P + 1) for a in range(n + 1) for b in range(a + 1)
+               if 0 <= n - a - b <= b)
+
+
+@dataclass
+class Workload:
+    name: str
+    pos: np.ndarray
+    cell: np.ndarray | None
+    nl: NeighborList
+    setup: PodSetup
+    c: np.ndarray
+
+    @property
+    def N(self) -> int:
+        return self.pos.shape[0]
+
+
+SETUP_CFG1 = PodSetup(rin=0.5, rcut=5.0, L=6, K2=4, K3=4, K4=0, P3=3, P4=0)
+SETUP_CFG2 = PodSetup(rin=0.5, rcut=5.0, L=8, K2=6, K3=6, K4=6, P3=4, P4=4)
+
+
+def coefficients(M: int, seed: int):
+    return np.random.default_rng(seed).normal(0.0, 1.0, size=M)
+
+
+def config1() -> Workload:
+    """128-atom BCC cell (4x4x4 conventional cells), sigma 0.1, 2+3-body."""
+    pos, cell = bcc(4)
+    pos = displace(pos, 0.1, seed=1)
+    s = SETUP_CFG1
+    nl = neighbor_list(pos, cell, s.rcut)
+    return Workload("bcc4_128_f64_23body", pos, cell, nl, s, coefficients(s.M, seed=2))
+
+
+def config2(rcut: float = 5.0) -> Workload:
+    """20x20x20 BCC box, 1% vacancies (160 sites), sigma 0.15, 2/3/4-body."""
+    pos, cell = bcc(20)
+    pos = remove_sites(pos, 160, seed=3)
+    pos = displace(pos, 0.15, seed=4)
+    s = PodSetup(rin=0.5, rcut=rcut, L=8, K2=6, K3=6, K4=6, P3=4, P4=4)
+    nl = neighbor_list(pos, cell, s.rcut)
+    return Workload(f"bcc20_vac1pct_15840_rc{rcut:g}", pos, cell, nl, s, coefficients(s.M, seed=5))
+
+
+def config4_positions():
+    """30x30x30 BCC box (54,000 atoms), sigma 0.2."""
+    pos, cell = bcc(30)
+    return displace(pos, 0.2, seed=7), cell
+
+
+def small_bcc(n: int = 2, sigma: float = 0.1, seed: int = 11, setup: PodSetup = SETUP_CFG2):
+    pos, cell = bcc(n)
+    pos = displace(pos, sigma, seed)
+    nl = neighbor_list(pos, cell, setup.rcut)
+    return Workload(f"bcc{n}_s{sigma}", pos, cell, nl, setup, coefficients(setup.M, seed + 1))
