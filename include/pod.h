@@ -1,0 +1,149 @@
+/*
+ * pod.h -- C ABI of the MI355X (gfx950) fast proper orthogonal descriptor
+ * library, libpod.so.
+ *
+ * The operations follow N.-C. Nguyen, "Fast proper orthogonal descriptors for
+ * many-body interatomic potentials" (arXiv:2212.14446):
+ *   - radial snapshots Phi_l = f_c(r) psi(r; mu_l)          Sec. II.B, eqs. (3)-(8), (11)
+ *   - POD radial basis R_k = sum_l Q_lk Phi_l                Sec. II.B, eq. (12)
+ *   - atomic basis B_imnl = sum_j R_m(r_ij) A_nl(rhat_ij)    Sec. II.E, eq. (24b)
+ *   - 2/3/4-body descriptors by the fast contractions        Sec. II.E, eqs. (25)-(30a)
+ *   - linear energy E_i = sum_m c_m D_im, E = c . G          Sec. IV.A, eqs. (57a), (58a)
+ *   - forces and virial from the descriptor derivatives      Sec. II.G, eqs. (26c), (24c)
+ *
+ * Conventions shared by every call
+ *   - Descriptor vector of one atom (length M):
+ *       [ 1 | D2_k, k < K2 | D3_mn, m < K3, n = 0..P3 (m-major) | D4_mp, m < K4, p < Ka(P4) (m-major) ]
+ *     with M = 1 + K2 + K3 (P3 + 1) + K4 Ka(P4) (caption of Table 6); the 4-body
+ *     index p runs over (a, b, c), a >= b >= c >= 0, a + b + c <= P4, in the
+ *     order of Table 1.  The 3- and 4-body sums run over all ordered neighbour
+ *     pairs / triples, coincident indices included (eqs. (15), (18a)).
+ *   - Neighbour list (CSR, device memory, int32): offsets[N+1] (offsets[0] = 0,
+ *     offsets[N] = P, non-decreasing), nbr_j[P] in [0, N), shift[P] packing the
+ *     periodic image n as three signed bytes (n_x | n_y << 8 | n_z << 16).
+ *     r_ij = pos[j] + n_x a1 + n_y a2 + n_z a3 - pos[i], a_k the rows of cell.
+ *     The list is full (both directions); every pair must satisfy
+ *     rin < |r_ij| < rcut.  Periodic self-images (i == j, n != 0) are allowed.
+ *   - pos: N x 3 row-major device array in the handle's dtype.
+ *   - cell: 9 doubles in HOST memory, lattice vectors as rows; NULL for an open
+ *     system (all shifts must then be zero).
+ *   - Device pointers are caller-owned; the library never frees them.  All
+ *     compute calls are asynchronous on the handle's HIP stream.
+ *   - Errors: 0 = OK, negative POD_E* codes.  Argument errors are reported by
+ *     the call itself; errors found in the data on the device (a pair outside
+ *     (rin, rcut), a non-finite coordinate, a malformed list) are latched in a
+ *     device error word and reported by pod_check().  Offending pairs or atoms
+ *     are skipped, never read out of bounds.  Nothing aborts across the ABI.
+ *   - One handle per stream; calls on one handle must not overlap.
+ */
+#ifndef POD_H
+#define POD_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define POD_OK 0
+#define POD_EINVAL (-1)      /* invalid argument or parameter */
+#define POD_ERANGE (-2)      /* a pair distance outside (rin, rcut) */
+#define POD_ENONFINITE (-3)  /* a non-finite coordinate */
+#define POD_ENOMEM (-4)      /* device allocation failed */
+#define POD_EHIP (-5)        /* a HIP runtime call failed */
+#define POD_ENOTSUP (-6)     /* parameters beyond what the kernels are built for */
+#define POD_ENEIGH (-7)      /* malformed neighbour list (offsets, index, shift) */
+
+#define POD_F64 0
+#define POD_F32 1
+
+/* Compile-time limits of the kernels. */
+#define POD_MAX_L 16   /* snapshots */
+#define POD_MAX_K 8    /* radial functions, max(K2, K3, K4) */
+#define POD_MAX_P 6    /* angular degree, max(P3, P4) */
+
+/*
+ * Parameters (Sec. II.B-II.D).  One snapshot tuple mu_l = (rin, rcut, alpha_l,
+ * beta_l, gamma_l, kappa_l) per l < L (eq. (11)); psi = kappa phi + (1 - kappa)
+ * varphi with phi = sin(alpha pi x)/(r - rin), varphi = r^-gamma (eq. (3)).
+ * Requirements: 0 <= rin < rcut; 1 <= L <= POD_MAX_L; 0 <= kappa_l <= 1;
+ * beta_l >= 0; 0 <= K2, K3, K4 <= min(L, POD_MAX_K) with at least one > 0;
+ * 0 <= P3, P4 <= POD_MAX_P.  Q: NULL to compute the POD basis (method of
+ * snapshots on n_quad midpoint nodes of (rin, rcut), unit eigenvectors of the
+ * snapshot correlation matrix, decreasing eigenvalue, entry of largest
+ * magnitude positive), or an L x K row-major matrix (K = max(K2, K3, K4)) to
+ * use as given.  All arrays are host memory and are copied.
+ */
+typedef struct pod_params {
+    double rin, rcut;
+    int L;
+    const double* alpha;
+    const double* beta;
+    const double* gamma;
+    const double* kappa;
+    int K2, K3, K4;
+    int P3, P4;
+    int dtype;          /* POD_F64 or POD_F32: type of pos, c, D, E_atom, F */
+    const double* Q;    /* L x K row-major, or NULL */
+    int n_quad;         /* quadrature nodes for the POD basis (>= 2L); 0 = 2000 */
+} pod_params;
+
+typedef struct pod_handle pod_handle;
+
+/* Validate parameters, build the POD basis and tables, upload them.
+ * hip_stream: a hipStream_t (NULL = default stream).  On success *out owns
+ * device memory released by pod_free. */
+int pod_init(const pod_params* p, void* hip_stream, pod_handle** out);
+
+/* Host only (no device call): the POD basis of Sec. II.B, eq. (12) for the
+ * given parameters.  Q: L x L row-major (columns = basis vectors, decreasing
+ * eigenvalue), eigvals: L.  p->Q is ignored. */
+int pod_compute_basis(const pod_params* p, double* Q, double* eigvals);
+
+/* Descriptor counts: *M total; M_by_order[4] = {1, 2-, 3-, 4-body counts}
+ * (either pointer may be NULL). */
+int pod_num_descriptors(const pod_handle* h, int* M, int* M_by_order);
+
+/* The basis in use: Q (L x K row-major, host) and eigvals (L, host; zeros when
+ * Q was supplied by the caller).  Either pointer may be NULL. */
+int pod_get_basis(const pod_handle* h, double* Q, double* eigvals);
+
+/* Per-atom descriptors D (N x M row-major, device, handle dtype), eqs. (12b),
+ * (15), (18a) evaluated by eqs. (24b)-(30a).  N >= 0 atoms, P pairs. */
+int pod_descriptors(pod_handle* h, int N, int P, const void* pos, const double* cell,
+                    const int* offsets, const int* nbr_j, const int* shift, void* D);
+
+/* Linear POD energy and its derivatives (eqs. (57a), (58a), (26c), (24c)).
+ *   c      : M coefficients (device, handle dtype)
+ *   E_atom : N per-atom energies (device, handle dtype) or NULL
+ *   E      : total energy (device, 1 double) or NULL
+ *   F      : N x 3 forces F_n = -dE/dr_n (device, handle dtype) or NULL
+ *   W      : 3 x 3 virial W_ab = -sum_pairs r_ij,a dE_i/dr_ij,b (device,
+ *            9 doubles) or NULL
+ *   G      : M global descriptors G = sum_i D_i = dE/dc (device, M doubles) or NULL
+ * Totals (E, W, G) are accumulated in double on both dtypes. */
+int pod_energy_forces(pod_handle* h, int N, int P, const void* pos, const double* cell,
+                      const int* offsets, const int* nbr_j, const int* shift,
+                      const void* c, void* E_atom, double* E, void* F, double* W, double* G);
+
+/* Diagnostics.  pod_set_kernel_timing(h, n) with n > 0 makes the next n
+ * compute calls record a pair of HIP events on the handle's stream around
+ * their main per-atom kernel (n = 0 switches recording off).
+ * pod_get_kernel_time waits for the stream and returns the summed elapsed
+ * time (ms) and the number of recorded launches, then resets the count. */
+int pod_set_kernel_timing(pod_handle* h, int n);
+int pod_get_kernel_time(pod_handle* h, double* total_ms, int* launches);
+
+/* Wait for the handle's stream, return and clear the device error word
+ * (POD_OK, POD_ERANGE, POD_ENONFINITE or POD_ENEIGH), or POD_EHIP. */
+int pod_check(pod_handle* h);
+
+/* Static description of an error code. */
+const char* pod_strerror(int code);
+
+/* Release the handle (waits for its stream). NULL is allowed. */
+void pod_free(pod_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* POD_H */

@@ -1,0 +1,368 @@
+// Host side of libpod: parameter validation, the POD radial basis (Sec. II.B,
+// eq. (12)), device parameter upload, error reporting and teardown.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "pod.h"
+#include "pod_internal.h"
+#include "pod_tables.h"
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kEpsCut = 1e-6;  // epsilon of the cut-off function, eq. (8)
+
+bool finite(double v) { return std::isfinite(v); }
+
+int validate(const pod_params* p) {
+    if (!p) return POD_EINVAL;
+    if (!finite(p->rin) || !finite(p->rcut) || p->rin < 0.0 || !(p->rin < p->rcut)) return POD_EINVAL;
+    if (p->L < 1) return POD_EINVAL;
+    if (p->L > POD_MAX_L) return POD_ENOTSUP;
+    if (!p->alpha || !p->beta || !p->gamma || !p->kappa) return POD_EINVAL;
+    for (int l = 0; l < p->L; ++l) {
+        if (!finite(p->alpha[l]) || !finite(p->beta[l]) || !finite(p->gamma[l]) || !finite(p->kappa[l]))
+            return POD_EINVAL;
+        if (p->kappa[l] < 0.0 || p->kappa[l] > 1.0 || p->beta[l] < 0.0) return POD_EINVAL;
+    }
+    if (p->K2 < 0 || p->K3 < 0 || p->K4 < 0 || p->P3 < 0 || p->P4 < 0) return POD_EINVAL;
+    const int K = std::max(p->K2, std::max(p->K3, p->K4));
+    if (K < 1 || K > p->L) return POD_EINVAL;
+    if (K > POD_MAX_K) return POD_ENOTSUP;
+    if (p->P3 > POD_MAX_P || p->P4 > POD_MAX_P) return POD_ENOTSUP;
+    if (p->dtype != POD_F64 && p->dtype != POD_F32) return POD_EINVAL;
+    if (p->n_quad != 0 && p->n_quad < 2 * p->L) return POD_EINVAL;
+    if (p->Q) {
+        for (int i = 0; i < p->L * K; ++i)
+            if (!finite(p->Q[i])) return POD_EINVAL;
+    }
+    return POD_OK;
+}
+
+// Snapshot l at distance r (host, double), straight from eqs. (3)-(8).
+double snapshot_host(const pod_params* p, int l, double r) {
+    const double h = p->rcut - p->rin;
+    const double t = (r - p->rin) / h;
+    const double y = 1.0 - t * t * t;
+    const double fc = std::exp(1.0 - 1.0 / std::sqrt(y * y + kEpsCut));
+    double psi = 0.0;
+    const double kap = p->kappa[l];
+    if (kap != 0.0) {
+        const double b = p->beta[l];
+        const double x = (b == 0.0) ? t : std::expm1(-b * t) / std::expm1(-b);
+        psi += kap * std::sin(p->alpha[l] * kPi * x) / (r - p->rin);
+    }
+    if (kap != 1.0) psi += (1.0 - kap) * std::pow(r, -p->gamma[l]);
+    return fc * psi;
+}
+
+// Cyclic Jacobi eigensolver for a small symmetric matrix (row-major, n x n).
+// On return A's diagonal holds the eigenvalues and V (row-major) the
+// eigenvectors as columns.
+void jacobi_eigen(std::vector<double>& A, std::vector<double>& V, int n) {
+    V.assign(static_cast<size_t>(n) * n, 0.0);
+    for (int i = 0; i < n; ++i) V[i * n + i] = 1.0;
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0.0, tot = 0.0;
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                tot += A[i * n + j] * A[i * n + j];
+                if (i != j) off += A[i * n + j] * A[i * n + j];
+            }
+        if (off <= 1e-30 * tot) break;
+        for (int pidx = 0; pidx < n - 1; ++pidx)
+            for (int q = pidx + 1; q < n; ++q) {
+                const double apq = A[pidx * n + q];
+                if (std::fabs(apq) < 1e-300) continue;
+                const double app = A[pidx * n + pidx], aqq = A[q * n + q];
+                const double theta = (aqq - app) / (2.0 * apq);
+                const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+                const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+                for (int k = 0; k < n; ++k) {  // A <- A J (columns p, q)
+                    const double akp = A[k * n + pidx], akq = A[k * n + q];
+                    A[k * n + pidx] = c * akp - s * akq;
+                    A[k * n + q] = s * akp + c * akq;
+                }
+                for (int k = 0; k < n; ++k) {  // A <- J^T A (rows p, q)
+                    const double apk = A[pidx * n + k], aqk = A[q * n + k];
+                    A[pidx * n + k] = c * apk - s * aqk;
+                    A[q * n + k] = s * apk + c * aqk;
+                }
+                for (int k = 0; k < n; ++k) {
+                    const double vkp = V[k * n + pidx], vkq = V[k * n + q];
+                    V[k * n + pidx] = c * vkp - s * vkq;
+                    V[k * n + q] = s * vkp + c * vkq;
+                }
+            }
+    }
+}
+
+int compute_basis(const pod_params* p, std::vector<double>& Q, std::vector<double>& eig) {
+    const int L = p->L;
+    const int nq = p->n_quad > 0 ? p->n_quad : 2000;
+    const double h = (p->rcut - p->rin) / nq;
+    std::vector<double> C(static_cast<size_t>(L) * L, 0.0), phi(L);
+    for (int s = 0; s < nq; ++s) {
+        const double r = p->rin + (s + 0.5) * h;
+        for (int l = 0; l < L; ++l) phi[l] = snapshot_host(p, l, r);
+        for (int a = 0; a < L; ++a)
+            for (int b = 0; b < L; ++b) C[a * L + b] += phi[a] * phi[b];
+    }
+    for (double& v : C) v /= nq;
+    std::vector<double> V;
+    jacobi_eigen(C, V, L);
+    std::vector<int> order(L);
+    for (int i = 0; i < L; ++i) order[i] = i;
+    std::sort(order.begin(), order.end(), [&](int a, int b) { return C[a * L + a] > C[b * L + b]; });
+    Q.assign(static_cast<size_t>(L) * L, 0.0);
+    eig.assign(L, 0.0);
+    for (int k = 0; k < L; ++k) {
+        const int src = order[k];
+        eig[k] = C[src * L + src];
+        int big = 0;
+        for (int l = 1; l < L; ++l)
+            if (std::fabs(V[l * L + src]) > std::fabs(V[big * L + src])) big = l;
+        const double sgn = V[big * L + src] < 0 ? -1.0 : 1.0;
+        for (int l = 0; l < L; ++l) Q[l * L + k] = sgn * V[l * L + src];
+        for (int l = 0; l < L; ++l)
+            if (!std::isfinite(Q[l * L + k])) return POD_EINVAL;
+    }
+    return POD_OK;
+}
+
+template <typename T>
+void fill_params(const pod_handle* h, pod::ParamsT<T>& d) {
+    std::memset(&d, 0, sizeof(d));
+    d.rin = static_cast<T>(h->rin);
+    d.rcut = static_cast<T>(h->rcut);
+    d.inv_h = static_cast<T>(1.0 / (h->rcut - h->rin));
+    d.L = h->L; d.K = h->K; d.K2 = h->K2; d.K3 = h->K3; d.K4 = h->K4;
+    d.P3 = h->P3; d.P4 = h->P4; d.Ka4 = h->Ka4; d.M = h->M; d.PA = h->PA;
+    d.off3 = 1 + h->K2;
+    d.off4 = 1 + h->K2 + h->K3 * (h->P3 + 1) * (h->K3 > 0);
+    // angle-addition plan: within a run of snapshots sharing beta, an integer
+    // alpha not below the previous one is reached by stepping sin/cos(k pi x)
+    double cur_beta = -1.0;
+    int cur_k = 0;
+    for (int l = 0; l < h->L; ++l) {
+        pod::SnapT<T>& s = d.s[l];
+        const double kap = h->kappa[l];
+        s.kappa = static_cast<T>(kap);
+        s.apix = static_cast<T>(h->alpha[l] * kPi);
+        s.gamma = static_cast<T>(h->gamma[l]);
+        s.bessel = kap != 0.0;
+        if (s.bessel) {
+            const double b = h->beta[l];
+            s.bh = static_cast<T>(b / (h->rcut - h->rin));
+            s.inv_em1 = static_cast<T>(b == 0.0 ? 0.0 : 1.0 / std::expm1(-b));
+            if (b != cur_beta) { s.newbeta = 1; cur_beta = b; cur_k = 0; }
+            const double a = h->alpha[l];
+            const bool is_int = a >= 0 && a == std::floor(a) && a <= 64.0;
+            if (is_int && static_cast<int>(a) >= cur_k) {
+                s.steps = static_cast<int>(a) - cur_k;
+                cur_k = static_cast<int>(a);
+            } else {
+                s.steps = -1;
+            }
+        }
+        s.power = 0;
+        if (kap != 1.0) {
+            const double g = h->gamma[l];
+            if (g == std::floor(g) && g >= 1.0 && g <= 16.0) { s.power = 1; s.igamma = static_cast<int>(g); }
+            else s.power = 2;
+        }
+    }
+    for (int l = 0; l < h->L; ++l)
+        for (int k = 0; k < h->K; ++k) d.Q[l][k] = static_cast<T>(h->Q[l * h->K + k]);
+}
+
+}  // namespace
+
+int pod::ensure_scratch(pod_handle* h, size_t bytes) {
+    if (bytes <= h->scratch_bytes) return POD_OK;
+    if (h->d_scratch) {
+        if (hipStreamSynchronize(h->stream) != hipSuccess) return POD_EHIP;
+        (void)hipFree(h->d_scratch);
+        h->d_scratch = nullptr;
+        h->scratch_bytes = 0;
+    }
+    size_t want = bytes + bytes / 4 + 4096;
+    if (hipMalloc(&h->d_scratch, want) != hipSuccess) {
+        h->d_scratch = nullptr;
+        return POD_ENOMEM;
+    }
+    h->scratch_bytes = want;
+    return POD_OK;
+}
+
+void pod::timing_begin(pod_handle* h) {
+    if (2 * (h->ev_used + 1) <= static_cast<int>(h->ev.size()))
+        (void)hipEventRecord(h->ev[2 * h->ev_used], h->stream);
+}
+
+void pod::timing_end(pod_handle* h) {
+    if (2 * (h->ev_used + 1) <= static_cast<int>(h->ev.size())) {
+        (void)hipEventRecord(h->ev[2 * h->ev_used + 1], h->stream);
+        ++h->ev_used;
+    }
+}
+
+namespace {
+void release_events(pod_handle* h) {
+    if (!h->ev.empty()) (void)hipStreamSynchronize(h->stream);
+    for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+    h->ev.clear();
+    h->ev_used = 0;
+}
+}  // namespace
+
+extern "C" {
+
+int pod_set_kernel_timing(pod_handle* h, int n) {
+    if (!h || n < 0 || n > (1 << 20)) return POD_EINVAL;
+    release_events(h);
+    h->ev.reserve(2 * static_cast<size_t>(n));
+    for (int i = 0; i < 2 * n; ++i) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) { release_events(h); return POD_EHIP; }
+        h->ev.push_back(e);
+    }
+    return POD_OK;
+}
+
+int pod_get_kernel_time(pod_handle* h, double* total_ms, int* launches) {
+    if (!h) return POD_EINVAL;
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return POD_EHIP;
+    double tot = 0.0;
+    for (int i = 0; i < h->ev_used; ++i) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, h->ev[2 * i], h->ev[2 * i + 1]) != hipSuccess) return POD_EHIP;
+        tot += ms;
+    }
+    if (total_ms) *total_ms = tot;
+    if (launches) *launches = h->ev_used;
+    h->ev_used = 0;
+    return POD_OK;
+}
+
+int pod_compute_basis(const pod_params* p, double* Q, double* eigvals) {
+    const int rc = validate(p);
+    if (rc != POD_OK) return rc;
+    std::vector<double> q, e;
+    const int r2 = compute_basis(p, q, e);
+    if (r2 != POD_OK) return r2;
+    if (Q) std::memcpy(Q, q.data(), q.size() * sizeof(double));
+    if (eigvals) std::memcpy(eigvals, e.data(), e.size() * sizeof(double));
+    return POD_OK;
+}
+
+int pod_init(const pod_params* p, void* hip_stream, pod_handle** out) {
+    if (!out) return POD_EINVAL;
+    *out = nullptr;
+    int rc = validate(p);
+    if (rc != POD_OK) return rc;
+    pod_handle* h = new (std::nothrow) pod_handle();
+    if (!h) return POD_ENOMEM;
+    h->dtype = p->dtype;
+    h->stream = static_cast<hipStream_t>(hip_stream);
+    h->rin = p->rin; h->rcut = p->rcut; h->L = p->L;
+    h->K2 = p->K2; h->K3 = p->K3; h->K4 = p->K4; h->P3 = p->P3; h->P4 = p->P4;
+    h->K = std::max(p->K2, std::max(p->K3, p->K4));
+    h->PA = std::max(p->K3 > 0 ? p->P3 : 0, p->K4 > 0 ? p->P4 : 0);
+    h->Ka4 = p->K4 > 0 ? pod::n_partitions(p->P4) : 0;
+    h->m_by_order[0] = 1;
+    h->m_by_order[1] = p->K2;
+    h->m_by_order[2] = p->K3 * (p->P3 + 1);
+    h->m_by_order[3] = p->K4 * h->Ka4;
+    h->M = 1 + h->m_by_order[1] + h->m_by_order[2] + h->m_by_order[3];
+    h->alpha.assign(p->alpha, p->alpha + p->L);
+    h->beta.assign(p->beta, p->beta + p->L);
+    h->gamma.assign(p->gamma, p->gamma + p->L);
+    h->kappa.assign(p->kappa, p->kappa + p->L);
+    if (p->Q) {
+        h->Q.assign(p->Q, p->Q + static_cast<size_t>(p->L) * h->K);
+        h->eig.assign(p->L, 0.0);
+    } else {
+        std::vector<double> qfull;
+        rc = compute_basis(p, qfull, h->eig);
+        if (rc != POD_OK) { delete h; return rc; }
+        h->Q.assign(static_cast<size_t>(p->L) * h->K, 0.0);
+        for (int l = 0; l < p->L; ++l)
+            for (int k = 0; k < h->K; ++k) h->Q[l * h->K + k] = qfull[l * p->L + k];
+    }
+    const size_t pbytes = h->dtype == POD_F64 ? sizeof(pod::ParamsT<double>) : sizeof(pod::ParamsT<float>);
+    if (hipMalloc(&h->d_params, pbytes) != hipSuccess) { delete h; return POD_ENOMEM; }
+    if (hipMalloc(reinterpret_cast<void**>(&h->d_err), sizeof(int)) != hipSuccess) {
+        (void)hipFree(h->d_params); delete h; return POD_ENOMEM;
+    }
+    hipError_t e1, e2;
+    if (h->dtype == POD_F64) {
+        pod::ParamsT<double> d; fill_params(h, d);
+        e1 = hipMemcpy(h->d_params, &d, sizeof(d), hipMemcpyHostToDevice);
+    } else {
+        pod::ParamsT<float> d; fill_params(h, d);
+        e1 = hipMemcpy(h->d_params, &d, sizeof(d), hipMemcpyHostToDevice);
+    }
+    e2 = hipMemset(h->d_err, 0, sizeof(int));
+    if (e1 != hipSuccess || e2 != hipSuccess) { pod_free(h); return POD_EHIP; }
+    *out = h;
+    return POD_OK;
+}
+
+int pod_num_descriptors(const pod_handle* h, int* M, int* M_by_order) {
+    if (!h) return POD_EINVAL;
+    if (M) *M = h->M;
+    if (M_by_order)
+        for (int i = 0; i < 4; ++i) M_by_order[i] = h->m_by_order[i];
+    return POD_OK;
+}
+
+int pod_get_basis(const pod_handle* h, double* Q, double* eigvals) {
+    if (!h) return POD_EINVAL;
+    if (Q) std::memcpy(Q, h->Q.data(), h->Q.size() * sizeof(double));
+    if (eigvals) std::memcpy(eigvals, h->eig.data(), h->eig.size() * sizeof(double));
+    return POD_OK;
+}
+
+int pod_check(pod_handle* h) {
+    if (!h) return POD_EINVAL;
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return POD_EHIP;
+    int word = 0;
+    if (hipMemcpy(&word, h->d_err, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return POD_EHIP;
+    if (word != 0 && hipMemset(h->d_err, 0, sizeof(int)) != hipSuccess) return POD_EHIP;
+    if (word & pod::ERR_NEIGH) return POD_ENEIGH;
+    if (word & pod::ERR_NONFINITE) return POD_ENONFINITE;
+    if (word & pod::ERR_RANGE) return POD_ERANGE;
+    return POD_OK;
+}
+
+const char* pod_strerror(int code) {
+    switch (code) {
+        case POD_OK: return "ok";
+        case POD_EINVAL: return "invalid argument";
+        case POD_ERANGE: return "pair distance outside (rin, rcut)";
+        case POD_ENONFINITE: return "non-finite coordinate";
+        case POD_ENOMEM: return "device allocation failed";
+        case POD_EHIP: return "HIP runtime error";
+        case POD_ENOTSUP: return "parameters beyond the compiled kernel limits";
+        case POD_ENEIGH: return "malformed neighbour list";
+        default: return "unknown error";
+    }
+}
+
+void pod_free(pod_handle* h) {
+    if (!h) return;
+    release_events(h);
+    (void)hipStreamSynchronize(h->stream);
+    if (h->d_params) (void)hipFree(h->d_params);
+    if (h->d_err) (void)hipFree(h->d_err);
+    if (h->d_scratch) (void)hipFree(h->d_scratch);
+    delete h;
+}
+
+}  // extern "C"

@@ -1,0 +1,80 @@
+// Internal declarations shared by the host code and the kernels of libpod.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "pod.h"
+
+namespace pod {
+
+constexpr int WAVE = 64;
+
+// Device error word bits (latched with atomicOr, read and cleared by pod_check).
+constexpr int ERR_RANGE = 1;
+constexpr int ERR_NONFINITE = 2;
+constexpr int ERR_NEIGH = 4;
+
+// One snapshot tuple as the kernels evaluate it (Sec. II.B, eqs. (3)-(6)).
+//   bessel  : kappa != 0; phi = sin(alpha pi x)/(r - rin)
+//   newbeta : x(r) must be (re)computed for this snapshot's beta
+//   steps   : >= 0 -> sin/cos(alpha pi x) reached from the previous integer
+//             multiple of pi x by `steps` angle-addition steps; -1 -> direct
+//   power   : kappa != 1; 1 = integer gamma (igamma), 2 = general gamma
+template <typename T>
+struct SnapT {
+    T kappa;
+    T apix;     // alpha * pi
+    T bh;       // beta / (rcut - rin)
+    T inv_em1;  // 1 / expm1(-beta)
+    T gamma;
+    int bessel;
+    int newbeta;
+    int steps;
+    int power;
+    int igamma;
+};
+
+template <typename T>
+struct ParamsT {
+    T rin, rcut, inv_h;
+    int L, K, K2, K3, K4, P3, P4, Ka4, M, PA;
+    int off3, off4;             // first column of the 3- and 4-body blocks in D
+    SnapT<T> s[POD_MAX_L];
+    T Q[POD_MAX_L][POD_MAX_K];  // zero-padded beyond K
+};
+
+// Periodic cell passed by value to the kernels.
+template <typename T>
+struct CellT {
+    T a[9];
+    int periodic;
+};
+
+}  // namespace pod
+
+struct pod_handle {
+    int dtype;
+    hipStream_t stream;
+    double rin, rcut;
+    int L, K2, K3, K4, P3, P4, K, PA, Ka4, M;
+    int m_by_order[4];
+    std::vector<double> alpha, beta, gamma, kappa;
+    std::vector<double> Q;     // L x K row-major
+    std::vector<double> eig;   // L
+    void* d_params;            // ParamsT<T>
+    int* d_err;
+    void* d_scratch;           // block partial sums
+    size_t scratch_bytes;
+    std::vector<hipEvent_t> ev; // kernel timing: 2 events per recorded launch
+    int ev_used;                // launches recorded so far
+};
+
+namespace pod {
+// Grow the handle's scratch buffer to at least `bytes` (POD_OK / POD_ENOMEM).
+int ensure_scratch(pod_handle* h, size_t bytes);
+// Kernel timing around the main per-atom launch (no-ops unless enabled).
+void timing_begin(pod_handle* h);
+void timing_end(pod_handle* h);
+}  // namespace pod

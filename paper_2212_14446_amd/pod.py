@@ -1,0 +1,302 @@
+"""Thin Python binding of libpod.so (C ABI in include/pod.h).
+
+Argument marshalling only: every step of the POD path runs in the HIP
+library.  Tensors are torch CUDA (HIP) tensors; the library works on their
+data pointers on the current torch stream.  There is no CPU fallback: if the
+library is missing or no GPU is present the calls raise.
+
+Function names mirror the C entry points (pod_init, pod_descriptors,
+pod_energy_forces, ...); ``PodModel`` bundles a handle with its parameters.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpod.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "pod.h")
+
+POD_F64, POD_F32 = 0, 1
+POD_MAX_L, POD_MAX_K, POD_MAX_P = 16, 8, 6
+ERRORS = {0: "POD_OK", -1: "POD_EINVAL", -2: "POD_ERANGE", -3: "POD_ENONFINITE", -4: "POD_ENOMEM",
+          -5: "POD_EHIP", -6: "POD_ENOTSUP", -7: "POD_ENEIGH"}
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_vp = ctypes.c_void_p
+
+
+class PodParamsC(ctypes.Structure):
+    _fields_ = [
+        ("rin", ctypes.c_double), ("rcut", ctypes.c_double), ("L", ctypes.c_int),
+        ("alpha", _dp), ("beta", _dp), ("gamma", _dp), ("kappa", _dp),
+        ("K2", ctypes.c_int), ("K3", ctypes.c_int), ("K4", ctypes.c_int),
+        ("P3", ctypes.c_int), ("P4", ctypes.c_int), ("dtype", ctypes.c_int),
+        ("Q", _dp), ("n_quad", ctypes.c_int),
+    ]
+
+
+class PodError(RuntimeError):
+    def __init__(self, code: int, where: str = ""):
+        self.code = code
+        super().__init__(f"{where}: {ERRORS.get(code, code)} ({_strerror(code)})")
+
+
+_lib = None
+
+
+def header_symbols():
+    """Names of the functions declared in include/pod.h."""
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(pod_[a-z0-9_]+)\s*\(", txt)))
+
+
+def lib():
+    """Load libpod.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with python -m paper_2212_14446_amd.build_lib")
+    L = ctypes.CDLL(LIB_PATH)
+    i, P = ctypes.c_int, ctypes.POINTER
+    L.pod_init.argtypes = [P(PodParamsC), _vp, P(_vp)]
+    L.pod_compute_basis.argtypes = [P(PodParamsC), _dp, _dp]
+    L.pod_num_descriptors.argtypes = [_vp, P(i), P(i)]
+    L.pod_get_basis.argtypes = [_vp, _dp, _dp]
+    L.pod_descriptors.argtypes = [_vp, i, i, _vp, _dp, _vp, _vp, _vp, _vp]
+    L.pod_energy_forces.argtypes = [_vp, i, i, _vp, _dp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+    L.pod_check.argtypes = [_vp]
+    L.pod_set_kernel_timing.argtypes = [_vp, i]
+    L.pod_get_kernel_time.argtypes = [_vp, _dp, P(i)]
+    L.pod_strerror.argtypes = [i]
+    L.pod_strerror.restype = ctypes.c_char_p
+    L.pod_free.argtypes = [_vp]
+    L.pod_free.restype = None
+    for name in ("pod_init", "pod_compute_basis", "pod_num_descriptors", "pod_get_basis", "pod_descriptors",
+                 "pod_energy_forces", "pod_check", "pod_set_kernel_timing", "pod_get_kernel_time"):
+        getattr(L, name).restype = i
+    _lib = L
+    return L
+
+
+def _strerror(code):
+    try:
+        return lib().pod_strerror(int(code)).decode()
+    except Exception:  # library not loadable: still produce a message
+        return ERRORS.get(code, "unknown")
+
+
+def _ok(rc, where):
+    if rc != 0:
+        raise PodError(rc, where)
+
+
+def _ptr(t):
+    """Device pointer of a torch tensor (None -> NULL)."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _cell_ptr(cell):
+    if cell is None:
+        return None, None
+    arr = np.ascontiguousarray(np.asarray(cell, dtype=np.float64).reshape(9))
+    return arr, arr.ctypes.data_as(_dp)
+
+
+@dataclass
+class Setup:
+    rin: float
+    rcut: float
+    alpha: np.ndarray
+    beta: np.ndarray
+    gamma: np.ndarray
+    kappa: np.ndarray
+    K2: int
+    K3: int
+    K4: int
+    P3: int
+    P4: int
+
+
+def _params(s: Setup, dtype_code: int, Q=None, n_quad=0):
+    keep = [np.ascontiguousarray(np.asarray(v, dtype=np.float64)) for v in (s.alpha, s.beta, s.gamma, s.kappa)]
+    qarr = None if Q is None else np.ascontiguousarray(np.asarray(Q, dtype=np.float64))
+    p = PodParamsC(float(s.rin), float(s.rcut), len(keep[0]),
+                   *[k.ctypes.data_as(_dp) for k in keep],
+                   int(s.K2), int(s.K3), int(s.K4), int(s.P3), int(s.P4), int(dtype_code),
+                   qarr.ctypes.data_as(_dp) if qarr is not None else None, int(n_quad))
+    return p, (keep, qarr)
+
+
+def pod_compute_basis(setup: Setup, n_quad: int = 0):
+    """Host-only POD basis (no device call): (Q [L, L], eigenvalues [L])."""
+    p, keep = _params(setup, POD_F64, None, n_quad)
+    L = p.L
+    Q = np.zeros((L, L))
+    e = np.zeros(L)
+    _ok(lib().pod_compute_basis(ctypes.byref(p), Q.ctypes.data_as(_dp), e.ctypes.data_as(_dp)), "pod_compute_basis")
+    return Q, e
+
+
+class Handle:
+    def __init__(self, ptr, dtype_code, M, K, L):
+        self.ptr = ptr
+        self.dtype_code = dtype_code
+        self.M = M
+        self.K = K
+        self.L = L
+
+    def __del__(self):
+        try:
+            pod_free(self)
+        except Exception:
+            pass
+
+
+def pod_init(setup: Setup, dtype: str = "f64", Q=None, n_quad: int = 0, stream=None) -> Handle:
+    import torch
+    code = POD_F64 if dtype in ("f64", "float64") else POD_F32
+    p, keep = _params(setup, code, Q, n_quad)
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    h = ctypes.c_void_p()
+    _ok(lib().pod_init(ctypes.byref(p), ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)), "pod_init")
+    M = ctypes.c_int()
+    _ok(lib().pod_num_descriptors(h, ctypes.byref(M), None), "pod_num_descriptors")
+    return Handle(h, code, M.value, max(setup.K2, setup.K3, setup.K4), p.L)
+
+
+def pod_num_descriptors(h: Handle):
+    M = ctypes.c_int()
+    by = (ctypes.c_int * 4)()
+    _ok(lib().pod_num_descriptors(h.ptr, ctypes.byref(M), by), "pod_num_descriptors")
+    return M.value, list(by)
+
+
+def pod_get_basis(h: Handle):
+    Q = np.zeros((h.L, h.K))
+    e = np.zeros(h.L)
+    _ok(lib().pod_get_basis(h.ptr, Q.ctypes.data_as(_dp), e.ctypes.data_as(_dp)), "pod_get_basis")
+    return Q, e
+
+
+def pod_descriptors(h: Handle, N, P, pos, cell, offsets, nbr_j, shift, D):
+    arr, cp = _cell_ptr(cell)
+    _ok(lib().pod_descriptors(h.ptr, int(N), int(P), _ptr(pos), cp, _ptr(offsets), _ptr(nbr_j), _ptr(shift),
+                              _ptr(D)), "pod_descriptors")
+
+
+def pod_energy_forces(h: Handle, N, P, pos, cell, offsets, nbr_j, shift, c, E_atom=None, E=None, F=None, W=None,
+                      G=None):
+    arr, cp = _cell_ptr(cell)
+    _ok(lib().pod_energy_forces(h.ptr, int(N), int(P), _ptr(pos), cp, _ptr(offsets), _ptr(nbr_j), _ptr(shift),
+                                _ptr(c), _ptr(E_atom), _ptr(E), _ptr(F), _ptr(W), _ptr(G)), "pod_energy_forces")
+
+
+def pod_check(h: Handle):
+    _ok(lib().pod_check(h.ptr), "pod_check")
+
+
+def pod_set_kernel_timing(h: Handle, n: int):
+    _ok(lib().pod_set_kernel_timing(h.ptr, int(n)), "pod_set_kernel_timing")
+
+
+def pod_get_kernel_time(h: Handle):
+    ms = ctypes.c_double()
+    n = ctypes.c_int()
+    _ok(lib().pod_get_kernel_time(h.ptr, ctypes.byref(ms), ctypes.byref(n)), "pod_get_kernel_time")
+    return ms.value, n.value
+
+
+def pod_free(h: Handle):
+    if h is not None and h.ptr:
+        lib().pod_free(h.ptr)
+        h.ptr = None
+
+
+# --------------------------------------------------------------------------
+# Convenience wrapper
+# --------------------------------------------------------------------------
+class DeviceNeighbors:
+    """CSR neighbour list resident on the device (int32)."""
+
+    def __init__(self, offsets, nbr_j, shift, device="cuda"):
+        import torch
+        self.offsets = torch.as_tensor(np.asarray(offsets, dtype=np.int32), device=device)
+        self.nbr_j = torch.as_tensor(np.asarray(nbr_j, dtype=np.int32), device=device)
+        self.shift = torch.as_tensor(np.asarray(shift, dtype=np.int32), device=device)
+        self.N = int(self.offsets.numel()) - 1
+        self.P = int(self.nbr_j.numel())
+
+    @classmethod
+    def from_list(cls, nl, device="cuda"):
+        return cls(nl.offsets, nl.nbr_j, nl.shift, device)
+
+
+class PodModel:
+    """A POD handle plus its parameters; tensors in and out live on the GPU."""
+
+    def __init__(self, setup: Setup, dtype: str = "f64", Q=None, n_quad: int = 0, device="cuda"):
+        import torch
+        self.setup = setup
+        self.device = torch.device(device)
+        self.torch_dtype = torch.float64 if dtype in ("f64", "float64") else torch.float32
+        self.h = pod_init(setup, dtype, Q, n_quad)
+        self.M, self.M_by_order = pod_num_descriptors(self.h)
+
+    def basis(self):
+        return pod_get_basis(self.h)
+
+    def _pos(self, pos):
+        import torch
+        return torch.as_tensor(pos, dtype=self.torch_dtype, device=self.device).contiguous()
+
+    def descriptors(self, pos, cell, nbrs: DeviceNeighbors, check=True):
+        import torch
+        pos = self._pos(pos)
+        D = torch.empty((nbrs.N, self.M), dtype=self.torch_dtype, device=self.device)
+        pod_descriptors(self.h, nbrs.N, nbrs.P, pos, cell, nbrs.offsets, nbrs.nbr_j, nbrs.shift, D)
+        if check:
+            pod_check(self.h)
+        return D
+
+    def energy_forces(self, pos, cell, nbrs: DeviceNeighbors, c, forces=True, virial=True, global_desc=True,
+                      per_atom=True, check=True, out=None):
+        import torch
+        pos = self._pos(pos)
+        c = torch.as_tensor(c, dtype=self.torch_dtype, device=self.device).contiguous()
+        if c.numel() != self.M:
+            raise ValueError(f"expected {self.M} coefficients, got {c.numel()}")
+        N = nbrs.N
+        o = out if out is not None else {
+            "E": torch.empty(1, dtype=torch.float64, device=self.device),
+            "E_atom": torch.empty(N, dtype=self.torch_dtype, device=self.device) if per_atom else None,
+            "F": torch.empty((N, 3), dtype=self.torch_dtype, device=self.device) if forces else None,
+            "W": torch.empty((3, 3), dtype=torch.float64, device=self.device) if virial else None,
+            "G": torch.empty(self.M, dtype=torch.float64, device=self.device) if global_desc else None,
+        }
+        pod_energy_forces(self.h, N, nbrs.P, pos, cell, nbrs.offsets, nbrs.nbr_j, nbrs.shift, c,
+                          o["E_atom"], o["E"], o["F"], o["W"], o["G"])
+        if check:
+            pod_check(self.h)
+        return o
+
+    def check(self):
+        pod_check(self.h)
+
+
+def setup_from_workload(s) -> Setup:
+    """Setup of a workloads.PodSetup (snapshot family included)."""
+    a, b, g, k = s.snapshot_family()
+    return Setup(s.rin, s.rcut, a, b, g, k, s.K2, s.K3, s.K4, s.P3, s.P4)

@@ -1,0 +1,154 @@
+"""Edge cases and error paths of the HIP path through the C ABI: empty input,
+atoms without neighbours, open systems, cells smaller than the cut-off
+(periodic self-images), and data errors latched in the device error word."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import Case, colerr, relerr, say
+from oracle import pod_oracle as po
+from paper_2212_14446_amd import pod, workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+S = wl.PodSetup(0.5, 5.0, 8, 4, 4, 4, 3, 3)
+
+
+def _model(dtype="f64"):
+    return pod.PodModel(pod.setup_from_workload(S), dtype)
+
+
+def test_empty_system():
+    say("[gpu] edge: empty system")
+    m = _model()
+    nb = pod.DeviceNeighbors(np.zeros(1, np.int32), np.zeros(0, np.int32), np.zeros(0, np.int32))
+    D = m.descriptors(np.zeros((0, 3)), None, nb)
+    assert D.shape == (0, m.M)
+    c = np.ones(m.M)
+    o = m.energy_forces(np.zeros((0, 3)), None, nb, c)
+    torch.cuda.synchronize()
+    assert o["E"].item() == 0.0
+    assert np.all(o["W"].cpu().numpy() == 0.0) and np.all(o["G"].cpu().numpy() == 0.0)
+
+
+def test_open_system_with_isolated_atoms():
+    rng = np.random.default_rng(3)
+    pos, _ = wl.lattice("bcc", 2, 2, 1, 3.31)
+    pos = pos + rng.normal(0, 0.1, pos.shape)
+    pos = np.vstack([pos, [[40.0, 40.0, 40.0], [-30.0, 0.0, 0.0]]])   # two lone atoms
+    nl = wl.neighbor_list(pos, None, S.rcut)
+    case = Case(pos, None, nl, S, wl.coefficients(S.M, 9), "open_isolated")
+    say(f"[gpu] edge: {case.name}")
+    got = case.run("f64")
+    o = case.oracle_ef()
+    D_ref = case.oracle_descriptors()
+    assert colerr(got["D"], D_ref) < 1e-10
+    assert np.all(got["D"][-2:, 1:] == 0.0) and np.all(got["D"][-2:, 0] == 1.0)
+    assert np.all(got["F"][-2:] == 0.0)
+    assert relerr(got["F"], o["F"]) < 1e-10
+    assert abs(got["E"] - o["E"]) < 1e-10 * abs(o["E"])
+    # open cluster: no net force and no net torque
+    F = got["F"]
+    assert np.abs(F.sum(0)).max() < 1e-10 * np.abs(F).max()
+    assert np.abs(np.cross(pos, F).sum(0)).max() < 1e-9 * np.abs(F).max() * np.abs(pos).max()
+
+
+@pytest.mark.parametrize("n", [1, 2])
+def test_small_cell_self_images(n):
+    pos, cell = wl.bcc(n)
+    pos = wl.displace(pos, 0.1, 5)
+    nl = wl.neighbor_list(pos, cell, S.rcut)
+    case = Case(pos, cell, nl, S, wl.coefficients(S.M, 4), f"bcc{n}_self_images")
+    say(f"[gpu] edge: {case.name} N={pos.shape[0]} P={nl.n_pairs}")
+    got = case.run("f64")
+    o = case.oracle_ef()
+    assert colerr(got["D"], case.oracle_descriptors()) < 1e-10
+    assert relerr(got["F"], o["F"]) < 1e-10
+    assert relerr(got["W"], o["W"]) < 1e-10
+
+
+def test_perfect_lattice_zero_force_and_symmetry():
+    pos, cell = wl.bcc(3)
+    nl = wl.neighbor_list(pos, cell, S.rcut)
+    case = Case(pos, cell, nl, S, wl.coefficients(S.M, 8), "perfect_bcc3")
+    say(f"[gpu] edge: {case.name}")
+    got = case.run("f64")
+    D = got["D"]
+    # identical environments: identical rows (odd-degree columns are zero up
+    # to rounding, so compare against the overall scale)
+    assert np.abs(D - D[:1]).max() < 1e-12 * np.abs(D).max()
+    ref = Case(wl.displace(pos, 0.1, 1), cell, wl.neighbor_list(wl.displace(pos, 0.1, 1), cell, S.rcut), S,
+               case.c).run("f64")["F"]
+    assert np.abs(got["F"]).max() < 1e-11 * np.abs(ref).max()
+
+
+def _small():
+    pos, cell = wl.bcc(2)
+    pos = wl.displace(pos, 0.1, 6)
+    return pos, cell
+
+
+def _raises(code, fn):
+    with pytest.raises(pod.PodError) as ei:
+        fn()
+    assert pod.ERRORS[ei.value.code] == code, ei.value
+
+
+def test_error_pair_beyond_cutoff():
+    pos, cell = _small()
+    nl = wl.neighbor_list(pos, cell, 5.6)      # list built for a larger cut-off
+    m = _model()
+    nb = pod.DeviceNeighbors.from_list(nl)
+    say("[gpu] edge: ERANGE")
+    _raises("POD_ERANGE", lambda: m.descriptors(pos, cell, nb))
+    _raises("POD_ERANGE", lambda: m.energy_forces(pos, cell, nb, np.ones(m.M)))
+    m.check()   # the error word was cleared
+
+
+def test_error_nonfinite_position():
+    pos, cell = _small()
+    nl = wl.neighbor_list(pos, cell, S.rcut)
+    pos = pos.copy()
+    pos[3, 1] = np.nan
+    m = _model()
+    nb = pod.DeviceNeighbors.from_list(nl)
+    say("[gpu] edge: ENONFINITE")
+    _raises("POD_ENONFINITE", lambda: m.energy_forces(pos, cell, nb, np.ones(m.M)))
+
+
+def test_error_bad_neighbor_index_and_offsets():
+    pos, cell = _small()
+    nl = wl.neighbor_list(pos, cell, S.rcut)
+    m = _model()
+    say("[gpu] edge: ENEIGH")
+    bad_j = nl.nbr_j.copy(); bad_j[5] = pos.shape[0] + 3
+    nb = pod.DeviceNeighbors(nl.offsets, bad_j, nl.shift)
+    _raises("POD_ENEIGH", lambda: m.energy_forces(pos, cell, nb, np.ones(m.M)))
+    bad_off = nl.offsets.copy(); bad_off[4] = bad_off[6] + 1   # non-monotone
+    nb = pod.DeviceNeighbors(bad_off, nl.nbr_j, nl.shift)
+    _raises("POD_ENEIGH", lambda: m.descriptors(pos, cell, nb))
+    # open system with a non-zero image shift
+    nb = pod.DeviceNeighbors.from_list(nl)
+    _raises("POD_ENEIGH", lambda: m.descriptors(pos, None, nb))
+
+
+def test_invalid_arguments_rejected_on_host():
+    m = _model()
+    _raises("POD_EINVAL", lambda: pod.pod_descriptors(m.h, -1, 0, None, None, None, None, None, None))
+    pos = torch.zeros((2, 3), dtype=torch.float64, device="cuda")
+    off = torch.zeros(3, dtype=torch.int32, device="cuda")
+    _raises("POD_EINVAL", lambda: pod.pod_energy_forces(m.h, 2, 0, pos, None, off, None, None, None))
+    _raises("POD_EINVAL", lambda: pod.pod_descriptors(m.h, 2, 0, pos, np.array([np.inf] * 9), off, None, None,
+                                                        torch.zeros((2, m.M), dtype=torch.float64, device="cuda")))
+
+
+def test_repeat_calls_agree():
+    pos, cell = _small()
+    nl = wl.neighbor_list(pos, cell, S.rcut)
+    m = _model()
+    nb = pod.DeviceNeighbors.from_list(nl)
+    c = wl.coefficients(S.M, 3)
+    a = m.energy_forces(pos, cell, nb, c)
+    b = m.energy_forces(pos, cell, nb, c)
+    assert a["E"].item() == pytest.approx(b["E"].item(), rel=1e-14)
+    assert relerr(a["F"].cpu().numpy(), b["F"].cpu().numpy()) < 1e-13

@@ -1,0 +1,143 @@
+"""GPU parity of the HIP path against the FP64 oracle (through the C ABI).
+
+Tolerances (normwise relative, max-abs error over max-abs reference):
+  FP64: 1e-10 for every output;
+  FP32: 2e-5 for energies, 1e-4 for forces; descriptors, virial and G are
+        reported and held to looser bounds derived from FP32 rounding.
+"""
+import numpy as np
+import pytest
+
+from gpu_common import Case, colerr, oracle_params, positions_for, relerr, say
+from oracle import pod_oracle as po
+from paper_2212_14446_amd import pod, workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-10
+
+
+def _compare(case, dtype, full=True):
+    pos = positions_for(dtype, case.pos)
+    c = case.c if dtype == "f64" else case.c.astype(np.float32).astype(np.float64)
+    ref_case = case
+    if dtype == "f32":
+        ref_case = Case(pos, case.cell, case.nl, case.setup, c, case.name)
+    say(f"[gpu] case={case.name} dtype={dtype} N={pos.shape[0]} P={case.nl.n_pairs}")
+    got = case.run(dtype, pos=pos) if dtype == "f64" else Case(pos, case.cell, case.nl, case.setup, c,
+                                                               case.name).run(dtype)
+    D_ref = ref_case.oracle_descriptors()
+    o = ref_case.oracle_ef()
+    errs = {
+        "D": colerr(got["D"], D_ref),
+        "E": abs(got["E"] - o["E"]) / max(abs(o["E"]), 1e-300),
+        "E_atom": relerr(got["E_atom"], o["E_atom"]),
+        "F": relerr(got["F"], o["F"]),
+        "W": relerr(got["W"], o["W"]),
+        "G": relerr(got["G"], o["G"]),
+    }
+    say(f"[gpu]   errors {dtype}: " + " ".join(f"{k}={v:.3e}" for k, v in errs.items()))
+    return errs
+
+
+def _assert64(errs):
+    for k, v in errs.items():
+        assert v < TOL64, (k, v)
+
+
+def _assert32(errs):
+    assert errs["E"] < 2e-5 and errs["E_atom"] < 2e-5, errs
+    assert errs["F"] < 1e-4, errs
+    assert errs["W"] < 1e-4 and errs["G"] < 1e-4, errs
+    assert errs["D"] < 1e-3, errs
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    return Case.from_workload(wl.config1())
+
+
+def test_cfg1_f64(cfg1):
+    _assert64(_compare(cfg1, "f64"))
+
+
+def test_cfg1_f64_against_naive_sums(cfg1):
+    atoms = [0, 17, 63, 127]
+    Dn = po.descriptors_naive(cfg1.pos, cfg1.cell, cfg1.nl.offsets.astype(np.int64), cfg1.nl.nbr_j,
+                              cfg1.nl.shift3, cfg1.op, cfg1.Q, atoms)
+    got = cfg1.run("f64")
+    assert colerr(got["D"][atoms], Dn) < TOL64
+
+
+def test_cfg1_f32(cfg1):
+    _assert32(_compare(cfg1, "f32"))
+
+
+# parameter sweep on a 3x3x3 BCC box with 5 vacancies (49 atoms: several
+# workgroups and a ragged last one for every K)
+SWEEP = [
+    # L, K2, K3, K4, P3, P4
+    (6, 4, 4, 0, 3, 0),
+    (8, 6, 6, 6, 4, 4),
+    (8, 1, 0, 0, 0, 0),
+    (8, 0, 3, 0, 2, 0),
+    (8, 2, 2, 3, 1, 5),
+    (8, 5, 3, 2, 6, 2),
+    (9, 7, 7, 7, 3, 3),
+    (10, 8, 8, 8, 2, 2),
+    (8, 3, 2, 2, 5, 6),
+    (8, 2, 0, 4, 0, 3),
+]
+
+
+@pytest.fixture(scope="module")
+def box49():
+    pos, cell = wl.bcc(3)
+    pos = wl.remove_sites(pos, 5, seed=71)
+    pos = wl.displace(pos, 0.12, seed=72)
+    return pos, cell
+
+
+@pytest.mark.parametrize("L,K2,K3,K4,P3,P4", SWEEP)
+def test_sweep_f64(box49, L, K2, K3, K4, P3, P4):
+    pos, cell = box49
+    s = wl.PodSetup(0.5, 5.0, L, K2, K3, K4, P3, P4)
+    nl = wl.neighbor_list(pos, cell, s.rcut)
+    c = wl.coefficients(s.M, seed=100 + L + K2 + 3 * K3 + 5 * K4 + 7 * P3 + 11 * P4)
+    case = Case(pos, cell, nl, s, c, f"sweep_L{L}_K{K2}{K3}{K4}_P{P3}{P4}")
+    _assert64(_compare(case, "f64"))
+
+
+@pytest.mark.parametrize("L,K2,K3,K4,P3,P4", [SWEEP[1], SWEEP[5], SWEEP[8]])
+def test_sweep_f32(box49, L, K2, K3, K4, P3, P4):
+    pos, cell = box49
+    s = wl.PodSetup(0.5, 5.0, L, K2, K3, K4, P3, P4)
+    nl = wl.neighbor_list(pos, cell, s.rcut)
+    c = wl.coefficients(s.M, seed=200 + L + K2 + 3 * K3 + 5 * K4 + 7 * P3 + 11 * P4)
+    case = Case(pos, cell, nl, s, c, f"sweep32_L{L}_K{K2}{K3}{K4}_P{P3}{P4}")
+    _assert32(_compare(case, "f32"))
+
+
+def test_general_snapshot_family_f64(box49):
+    # non-integer alpha, alpha out of order, two betas, mixed kappa,
+    # non-integer gamma and beta = 0: every branch of the radial code
+    pos, cell = box49
+    s = pod.Setup(0.4, 4.8,
+                  np.array([1.0, 2.0, 1.5, 4.0, 3.0, 2.0, 0.0, 1.0]),
+                  np.array([3.0, 3.0, 3.0, 3.0, 3.0, 1.0, 0.0, 0.0]),
+                  np.array([0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 2.5, 1.0]),
+                  np.array([1.0, 1.0, 1.0, 0.6, 1.0, 1.0, 0.0, 1.0]),
+                  5, 4, 3, 3, 3)
+    nl = wl.neighbor_list(pos, cell, s.rcut)
+    M = po.num_descriptors(po.PodParams(s.rin, s.rcut, s.alpha, s.beta, s.gamma, s.kappa,
+                                        s.K2, s.K3, s.K4, s.P3, s.P4))[0]
+    case = Case(pos, cell, nl, s, wl.coefficients(M, seed=5), "general_snapshots")
+    _assert64(_compare(case, "f64"))
+
+
+def test_library_basis_equals_oracle_on_device_handle():
+    s = wl.SETUP_CFG2
+    m = pod.PodModel(pod.setup_from_workload(s), "f64")
+    Q, e = m.basis()
+    Qo, eo = po.pod_basis(oracle_params(s))
+    assert np.max(np.abs(Q - Qo[:, :6])) < 1e-9

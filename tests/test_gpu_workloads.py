@@ -1,0 +1,48 @@
+"""GPU parity at the full benchmark size: the 15,840-atom BCC box with 1%
+vacancies (2/3/4-body, L = 8 -> K = 6, P = 4), every output element against
+the oracle, in the launch configuration the benchmark times."""
+import numpy as np
+import pytest
+
+from gpu_common import Case, colerr, positions_for, relerr, say
+from paper_2212_14446_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cfg2():
+    return Case.from_workload(wl.config2())
+
+
+@pytest.fixture(scope="module")
+def cfg2_ref(cfg2):
+    return cfg2.oracle_descriptors(), cfg2.oracle_ef()
+
+
+def test_cfg2_f64_full(cfg2, cfg2_ref):
+    say(f"[gpu] cfg2 f64 N={cfg2.pos.shape[0]} P={cfg2.nl.n_pairs}")
+    D_ref, o = cfg2_ref
+    got = cfg2.run("f64")
+    errs = {"D": colerr(got["D"], D_ref), "E": abs(got["E"] - o["E"]) / abs(o["E"]),
+            "E_atom": relerr(got["E_atom"], o["E_atom"]), "F": relerr(got["F"], o["F"]),
+            "W": relerr(got["W"], o["W"]), "G": relerr(got["G"], o["G"])}
+    say("[gpu]   " + " ".join(f"{k}={v:.3e}" for k, v in errs.items()))
+    for k, v in errs.items():
+        assert v < 1e-10, (k, v)
+
+
+def test_cfg2_f32_full(cfg2):
+    pos = positions_for("f32", cfg2.pos)
+    c = cfg2.c.astype(np.float32).astype(np.float64)
+    case = Case(pos, cfg2.cell, cfg2.nl, cfg2.setup, c, "cfg2_f32")
+    say(f"[gpu] cfg2 f32 N={pos.shape[0]}")
+    got = case.run("f32")
+    D_ref = case.oracle_descriptors()
+    o = case.oracle_ef()
+    errs = {"D": colerr(got["D"], D_ref), "E": abs(got["E"] - o["E"]) / abs(o["E"]),
+            "E_atom": relerr(got["E_atom"], o["E_atom"]), "F": relerr(got["F"], o["F"]),
+            "W": relerr(got["W"], o["W"]), "G": relerr(got["G"], o["G"])}
+    say("[gpu]   " + " ".join(f"{k}={v:.3e}" for k, v in errs.items()))
+    assert errs["E"] < 2e-5 and errs["E_atom"] < 2e-5
+    assert errs["F"] < 1e-4
