@@ -28,10 +28,6 @@ sys.path.insert(0, ROOT)
 METRIC = "atoms/s for POD energy+forces (FP64/FP32) and MLP-surrogate speedup at fixed RMSE"
 PEAK_F64 = 78.6e12    # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz, FP64 vector
 PEAK_F32 = 157.3e12   # published FP32 vector peak (packed); unpacked issue gives 78.6e12
-# algorithmic work per unit (flops): per directed pair (forward ~620 + backward
-# ~1330) and per atom (contractions + adjoint) for K = 6, P = 4
-FLOPS_PER_PAIR = 1950.0
-FLOPS_PER_ATOM = 14000.0
 KERNEL_SOURCES = ["paper_2212_14446_amd/csrc/pod_kernels.hip", "paper_2212_14446_amd/csrc/pod_tables.h",
                   "paper_2212_14446_amd/csrc/pod_internal.h"]
 
@@ -75,9 +71,13 @@ def run_gpu(w, dtype, steps, warmup):
            "G": torch.empty(m.M, dtype=torch.float64, device="cuda")}
     cell = w.cell
 
+    # the reverse-pair index belongs to the neighbour list (built once per
+    # list, outside the timed region, like the list itself)
+    nb.build_reverse(m)
+
     def step():
         pod.pod_energy_forces(m.h, N, nb.P, pos, cell, nb.offsets, nb.nbr_j, nb.shift, c,
-                              out["E_atom"], out["E"], out["F"], out["W"], out["G"])
+                              out["E_atom"], out["E"], out["F"], out["W"], out["G"], rev=nb.rev)
 
     for _ in range(warmup):
         step()
@@ -94,21 +94,33 @@ def run_gpu(w, dtype, steps, warmup):
     e1.record(stream)
     torch.cuda.synchronize()
     total_ms = e0.elapsed_time(e1)
-    kms, kn = pod.pod_get_kernel_time(m.h)
+    kms, kn = pod.pod_get_kernel_time(m.h, 1)
+    pms, pn = pod.pod_get_kernel_time(m.h, 0)
     pod.pod_set_kernel_timing(m.h, 0)
     m.check()
     return {"ms_per_step": total_ms / steps, "kernel_ms": kms / max(kn, 1), "kernel_launches": kn,
-            "E": float(out["E"].item())}
+            "finalize_kernel_ms": pms / max(pn, 1), "E": float(out["E"].item())}
 
 
-def roofline(w, kernel_ms, dtype):
-    flops = FLOPS_PER_PAIR * w.nl.n_pairs + FLOPS_PER_ATOM * w.N
-    achieved = flops / (kernel_ms * 1e-3)
+def roofline(w, r, dtype):
+    """Roofline of the per-atom kernel (the dominant one) from the algorithmic
+    flop model in paper_2212_14446_amd.flops; the finalize kernel's time is
+    reported beside it."""
+    from paper_2212_14446_amd import flops as fl
+    s = w.setup
+    K = max(s.K2, s.K3, s.K4)
+    PA = max(s.P3 if s.K3 else 0, s.P4 if s.K4 else 0)
+    cnt = fl.counts(K, s.L, PA, s.P4)
+    # the per-atom kernel evaluates the radial basis twice (forward, and with
+    # derivatives in the backward): counted once, as the algorithm needs it once
+    f_atom = ((cnt["radial_per_pair"] + cnt["forward_per_pair"] + cnt["backward_per_pair"]) * w.nl.n_pairs
+              + cnt["per_atom"] * w.N)
     peak = PEAK_F64 if dtype == "f64" else PEAK_F32
-    traffic = committed_traffic(dtype)
+    achieved = f_atom / (r["kernel_ms"] * 1e-3)
     return {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-            "frac": achieved / peak, "traffic": traffic, "kernel": "atom_kernel<E+F>",
-            "kernel_ms": kernel_ms, "flops_per_launch": flops}
+            "frac": achieved / peak, "traffic": committed_traffic(dtype), "kernel": "atom_kernel (E+F)",
+            "kernel_ms": r["kernel_ms"], "flops_per_launch": f_atom,
+            "finalize_kernel_ms": r["finalize_kernel_ms"]}
 
 
 def cpu_baseline(w):
@@ -136,6 +148,9 @@ def main():
     ap.add_argument("--rcut", type=float, default=5.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-f32", action="store_true")
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="run one device-to-device copy of this many MiB first (a known-size "
+                         "kernel for scaling hardware traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -143,6 +158,15 @@ def main():
         sys.exit(2)
 
     from paper_2212_14446_amd import workloads as wl
+    if args.copy_calibration_mb > 0:
+        import torch
+        n = args.copy_calibration_mb * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] calibration copy: {n * 8} bytes read, {n * 8} bytes written", file=sys.stderr, flush=True)
+        del src, dst
     w = wl.config2(args.rcut)
     print(f"[bench] workload {w.name}: N={w.N} P={w.nl.n_pairs} M={w.setup.M}", file=sys.stderr, flush=True)
     r64 = run_gpu(w, "f64", args.steps, args.warmup)
@@ -164,13 +188,13 @@ def main():
                    "pairs_per_atom": w.nl.n_pairs / w.N, "rcut": w.setup.rcut, "L": w.setup.L,
                    "K": max(w.setup.K2, w.setup.K3, w.setup.K4), "P3": w.setup.P3, "P4": w.setup.P4,
                    "M": w.setup.M, "body_orders": "2/3/4"},
-        "roofline": roofline(w, r64["kernel_ms"], "f64"),
+        "roofline": roofline(w, r64, "f64"),
     }
     if not args.no_f32:
         r32 = run_gpu(w, "f32", args.steps, args.warmup)
         print(f"[bench] f32 {r32}", file=sys.stderr, flush=True)
         rec["f32"] = {"value": w.N / (r32["ms_per_step"] * 1e-3), "ms_per_step": r32["ms_per_step"],
-                      "roofline": roofline(w, r32["kernel_ms"], "f32")}
+                      "roofline": roofline(w, r32, "f32")}
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         rec["cpu_baseline"] = cpu_baseline(w)

@@ -111,7 +111,19 @@ int pod_get_basis(const pod_handle* h, double* Q, double* eigvals);
 int pod_descriptors(pod_handle* h, int N, int P, const void* pos, const double* cell,
                     const int* offsets, const int* nbr_j, const int* shift, void* D);
 
+/* Reverse-pair index of a full neighbour list: rev[p] (device, P ints) is the
+ * index of the pair (j -> i, -n) for pair p = (i -> j, n), searched in the
+ * list of j.  Asynchronous on the handle's stream; a pair without its reverse
+ * gets rev[p] = -1 and latches POD_ENEIGH (pod_check).  It depends on the list
+ * only, so it is computed once per list, beside the list itself. */
+int pod_neighbor_reverse(pod_handle* h, int N, int P, const int* offsets, const int* nbr_j,
+                         const int* shift, int* rev);
+
 /* Linear POD energy and its derivatives (eqs. (57a), (58a), (26c), (24c)).
+ *   rev    : reverse-pair index from pod_neighbor_reverse, or NULL.  With it,
+ *            forces are gathered per atom, F_n = sum_{p in N(n)} (g_p - g_rev(p))
+ *            with g_p = dE_i/dr_ij, in a fixed order (bitwise reproducible);
+ *            without it they are accumulated with FP64 atomics.
  *   c      : M coefficients (device, handle dtype)
  *   E_atom : N per-atom energies (device, handle dtype) or NULL
  *   E      : total energy (device, 1 double) or NULL
@@ -121,16 +133,19 @@ int pod_descriptors(pod_handle* h, int N, int P, const void* pos, const double* 
  *   G      : M global descriptors G = sum_i D_i = dE/dc (device, M doubles) or NULL
  * Totals (E, W, G) are accumulated in double on both dtypes. */
 int pod_energy_forces(pod_handle* h, int N, int P, const void* pos, const double* cell,
-                      const int* offsets, const int* nbr_j, const int* shift,
+                      const int* offsets, const int* nbr_j, const int* shift, const int* rev,
                       const void* c, void* E_atom, double* E, void* F, double* W, double* G);
 
 /* Diagnostics.  pod_set_kernel_timing(h, n) with n > 0 makes the next n
- * compute calls record a pair of HIP events on the handle's stream around
- * their main per-atom kernel (n = 0 switches recording off).
- * pod_get_kernel_time waits for the stream and returns the summed elapsed
- * time (ms) and the number of recorded launches, then resets the count. */
+ * compute calls record pairs of HIP events on the handle's stream around each
+ * of their kernels (n = 0 switches recording off).  pod_get_kernel_time waits
+ * for the stream and returns the summed elapsed time (ms) and the number of
+ * recorded launches of one kernel -- kind 1: the per-atom kernel (radial
+ * basis, atomic basis, contractions, energy, adjoint, per-pair gradients);
+ * kind 0: the finalize kernel (totals E, W, G and the force copy-out) --
+ * then resets that count. */
 int pod_set_kernel_timing(pod_handle* h, int n);
-int pod_get_kernel_time(pod_handle* h, double* total_ms, int* launches);
+int pod_get_kernel_time(pod_handle* h, int kind, double* total_ms, int* launches);
 
 /* Wait for the handle's stream, return and clear the device error word
  * (POD_OK, POD_ERANGE, POD_ENONFINITE or POD_ENEIGH), or POD_EHIP. */

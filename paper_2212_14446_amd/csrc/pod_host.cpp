@@ -179,9 +179,48 @@ void fill_params(const pod_handle* h, pod::ParamsT<T>& d) {
     }
     for (int l = 0; l < h->L; ++l)
         for (int k = 0; k < h->K; ++k) d.Q[l][k] = static_cast<T>(h->Q[l * h->K + k]);
+    // standard family: Bessel alpha = 1..nb at one beta (kappa = 1), then
+    // inverse powers gamma = 1..ni (kappa = 0)
+    int nb = 0;
+    while (nb < h->L && h->kappa[nb] == 1.0 && h->alpha[nb] == nb + 1.0 && h->beta[nb] == h->beta[0]) ++nb;
+    int ni = 0;
+    while (nb + ni < h->L && h->kappa[nb + ni] == 0.0 && h->gamma[nb + ni] == ni + 1.0) ++ni;
+    if (nb + ni == h->L) {
+        d.std_ok = 1; d.std_nb = nb; d.std_ni = ni;
+        const double b = nb > 0 ? h->beta[0] : 0.0;
+        d.std_bh = static_cast<T>(b / (h->rcut - h->rin));
+        d.std_inv_em1 = static_cast<T>(b == 0.0 ? 0.0 : 1.0 / std::expm1(-b));
+    }
 }
 
 }  // namespace
+
+int pod::ensure_force_acc(pod_handle* h, int N) {
+    if (N > h->facc_n || !h->d_facc) {
+        if (h->d_facc) {
+            if (hipStreamSynchronize(h->stream) != hipSuccess) return POD_EHIP;
+            (void)hipFree(h->d_facc);
+            h->d_facc = nullptr;
+            h->facc_n = 0;
+        }
+        const int want = N > 0 ? N + N / 4 + 64 : 64;
+        if (hipMalloc(reinterpret_cast<void**>(&h->d_facc), sizeof(double) * 3 * static_cast<size_t>(want)) !=
+            hipSuccess) {
+            h->d_facc = nullptr;
+            return POD_ENOMEM;
+        }
+        if (hipMemset(h->d_facc, 0, sizeof(double) * 3 * static_cast<size_t>(want)) != hipSuccess) return POD_EHIP;
+        h->facc_n = want;
+        h->facc_dirty = 0;
+    }
+    if (h->facc_dirty) {
+        if (hipStreamSynchronize(h->stream) != hipSuccess) return POD_EHIP;
+        if (hipMemset(h->d_facc, 0, sizeof(double) * 3 * static_cast<size_t>(h->facc_n)) != hipSuccess)
+            return POD_EHIP;
+        h->facc_dirty = 0;
+    }
+    return POD_OK;
+}
 
 int pod::ensure_scratch(pod_handle* h, size_t bytes) {
     if (bytes <= h->scratch_bytes) return POD_OK;
@@ -200,24 +239,29 @@ int pod::ensure_scratch(pod_handle* h, size_t bytes) {
     return POD_OK;
 }
 
-void pod::timing_begin(pod_handle* h) {
-    if (2 * (h->ev_used + 1) <= static_cast<int>(h->ev.size()))
-        (void)hipEventRecord(h->ev[2 * h->ev_used], h->stream);
+void pod::timing_begin(pod_handle* h, int kind) {
+    auto& ev = h->ev[kind];
+    const int u = h->ev_used[kind];
+    if (2 * (u + 1) <= static_cast<int>(ev.size())) (void)hipEventRecord(ev[2 * u], h->stream);
 }
 
-void pod::timing_end(pod_handle* h) {
-    if (2 * (h->ev_used + 1) <= static_cast<int>(h->ev.size())) {
-        (void)hipEventRecord(h->ev[2 * h->ev_used + 1], h->stream);
-        ++h->ev_used;
+void pod::timing_end(pod_handle* h, int kind) {
+    auto& ev = h->ev[kind];
+    const int u = h->ev_used[kind];
+    if (2 * (u + 1) <= static_cast<int>(ev.size())) {
+        (void)hipEventRecord(ev[2 * u + 1], h->stream);
+        ++h->ev_used[kind];
     }
 }
 
 namespace {
 void release_events(pod_handle* h) {
-    if (!h->ev.empty()) (void)hipStreamSynchronize(h->stream);
-    for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
-    h->ev.clear();
-    h->ev_used = 0;
+    if (!h->ev[0].empty() || !h->ev[1].empty()) (void)hipStreamSynchronize(h->stream);
+    for (int k = 0; k < 2; ++k) {
+        for (hipEvent_t e : h->ev[k]) (void)hipEventDestroy(e);
+        h->ev[k].clear();
+        h->ev_used[k] = 0;
+    }
 }
 }  // namespace
 
@@ -226,27 +270,29 @@ extern "C" {
 int pod_set_kernel_timing(pod_handle* h, int n) {
     if (!h || n < 0 || n > (1 << 20)) return POD_EINVAL;
     release_events(h);
-    h->ev.reserve(2 * static_cast<size_t>(n));
-    for (int i = 0; i < 2 * n; ++i) {
-        hipEvent_t e;
-        if (hipEventCreate(&e) != hipSuccess) { release_events(h); return POD_EHIP; }
-        h->ev.push_back(e);
+    for (int k = 0; k < 2; ++k) {
+        h->ev[k].reserve(2 * static_cast<size_t>(n));
+        for (int i = 0; i < 2 * n; ++i) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) { release_events(h); return POD_EHIP; }
+            h->ev[k].push_back(e);
+        }
     }
     return POD_OK;
 }
 
-int pod_get_kernel_time(pod_handle* h, double* total_ms, int* launches) {
-    if (!h) return POD_EINVAL;
+int pod_get_kernel_time(pod_handle* h, int kind, double* total_ms, int* launches) {
+    if (!h || kind < 0 || kind > 1) return POD_EINVAL;
     if (hipStreamSynchronize(h->stream) != hipSuccess) return POD_EHIP;
     double tot = 0.0;
-    for (int i = 0; i < h->ev_used; ++i) {
+    for (int i = 0; i < h->ev_used[kind]; ++i) {
         float ms = 0.0f;
-        if (hipEventElapsedTime(&ms, h->ev[2 * i], h->ev[2 * i + 1]) != hipSuccess) return POD_EHIP;
+        if (hipEventElapsedTime(&ms, h->ev[kind][2 * i], h->ev[kind][2 * i + 1]) != hipSuccess) return POD_EHIP;
         tot += ms;
     }
     if (total_ms) *total_ms = tot;
-    if (launches) *launches = h->ev_used;
-    h->ev_used = 0;
+    if (launches) *launches = h->ev_used[kind];
+    h->ev_used[kind] = 0;
     return POD_OK;
 }
 
@@ -303,9 +349,11 @@ int pod_init(const pod_params* p, void* hip_stream, pod_handle** out) {
     hipError_t e1, e2;
     if (h->dtype == POD_F64) {
         pod::ParamsT<double> d; fill_params(h, d);
+        h->std_ok = d.std_ok;
         e1 = hipMemcpy(h->d_params, &d, sizeof(d), hipMemcpyHostToDevice);
     } else {
         pod::ParamsT<float> d; fill_params(h, d);
+        h->std_ok = d.std_ok;
         e1 = hipMemcpy(h->d_params, &d, sizeof(d), hipMemcpyHostToDevice);
     }
     e2 = hipMemset(h->d_err, 0, sizeof(int));
@@ -362,6 +410,7 @@ void pod_free(pod_handle* h) {
     if (h->d_params) (void)hipFree(h->d_params);
     if (h->d_err) (void)hipFree(h->d_err);
     if (h->d_scratch) (void)hipFree(h->d_scratch);
+    if (h->d_facc) (void)hipFree(h->d_facc);
     delete h;
 }
 

@@ -41,6 +41,11 @@ struct ParamsT {
     T rin, rcut, inv_h;
     int L, K, K2, K3, K4, P3, P4, Ka4, M, PA;
     int off3, off4;             // first column of the 3- and 4-body blocks in D
+    // Standard family fast path (std_nb + std_ni == L): snapshots 0..nb-1 are
+    // Bessel with kappa = 1, alpha = 1..nb and one beta; the rest are inverse
+    // powers with kappa = 0, gamma = 1..ni.  std_ok = 0 -> generic path.
+    int std_ok, std_nb, std_ni;
+    T std_bh, std_inv_em1;
     SnapT<T> s[POD_MAX_L];
     T Q[POD_MAX_L][POD_MAX_K];  // zero-padded beyond K
 };
@@ -60,21 +65,28 @@ struct pod_handle {
     double rin, rcut;
     int L, K2, K3, K4, P3, P4, K, PA, Ka4, M;
     int m_by_order[4];
+    int std_ok;                // standard snapshot family: fast radial path
     std::vector<double> alpha, beta, gamma, kappa;
     std::vector<double> Q;     // L x K row-major
     std::vector<double> eig;   // L
     void* d_params;            // ParamsT<T>
     int* d_err;
     void* d_scratch;           // block partial sums
+    double* d_facc;            // force accumulator, 3 x facc_n doubles, zero between calls
+    int facc_n;
+    int facc_dirty;            // a call failed between accumulation and copy-out
     size_t scratch_bytes;
-    std::vector<hipEvent_t> ev; // kernel timing: 2 events per recorded launch
-    int ev_used;                // launches recorded so far
+    // kernel timing: per kernel kind (0 pair stage, 1 per-atom), 2 events per launch
+    std::vector<hipEvent_t> ev[2];
+    int ev_used[2];
 };
 
 namespace pod {
 // Grow the handle's scratch buffer to at least `bytes` (POD_OK / POD_ENOMEM).
 int ensure_scratch(pod_handle* h, size_t bytes);
+// Force accumulator for N atoms, zero on return (POD_OK / POD_ENOMEM / POD_EHIP).
+int ensure_force_acc(pod_handle* h, int N);
 // Kernel timing around the main per-atom launch (no-ops unless enabled).
-void timing_begin(pod_handle* h);
-void timing_end(pod_handle* h);
+void timing_begin(pod_handle* h, int kind);
+void timing_end(pod_handle* h, int kind);
 }  // namespace pod

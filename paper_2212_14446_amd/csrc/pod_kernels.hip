@@ -1,21 +1,25 @@
-// Fused per-atom kernels of the fast POD path for gfx950 (CDNA4).
+// Kernels of the fast POD path for gfx950 (CDNA4).
 //
-// Work mapping.  One workgroup is one 64-lane wavefront and owns APW = 64 / K
-// consecutive atoms (K = max(K2, K3, K4)).  Lane l serves atom a = l / K and
-// index q = l % K, which is used two ways:
-//   * pair stage   : q is a neighbour slot; each lane evaluates one pair
-//                    r_ij -> (rhat, 1/r, R_k(r), R'_k(r)) and stages it in LDS;
-//                    neighbour slots are consumed K at a time per atom.
-//   * basis stage  : q is the radial index m; the lane accumulates the row
-//                    B_{i m .} = sum_j R_m(r_ij) A_.(rhat_ij) of the atomic
-//                    basis (Sec. II.E, eq. (24b)) in registers.
-// Every contraction of Sec. II.E is diagonal in m (the same radial function in
-// all factors, eqs. (14), (17a)), so D3, D4, the energy and the adjoint
-// dE_i/dB_{i m .} are computed by each lane from its own row without any
-// exchange.  The backward sweep recomputes the pair stage (nothing per pair is
-// stored) and reduces the per-m gradient contributions of each pair through
-// LDS; forces are scattered with device-scope atomics, block totals of E, W
-// and G go to a partial-sum buffer reduced by a second kernel.
+// Two launches per call.
+//
+// pair_kernel  (pair-parallel, 8 atoms x 32 lanes per 256-thread block):
+//   every directed pair r_ij -> one record {rhat (3), 1/r, R_k(r) (K),
+//   R'_k(r) (K)} of the radial basis (Sec. II.B, eqs. (3)-(8), (11), (12)),
+//   plus validation of the pair and zeroing of the accumulated outputs.
+//   The transcendental work sits here, at high occupancy.
+//
+// atom_kernel  (one 64-lane wavefront per workgroup, APW = 64 / K atoms):
+//   lane l serves atom a = l / K and radial index m = l % K and keeps the row
+//   B_{i m .} = sum_j R_m(r_ij) A_.(rhat_ij) of the atomic basis (Sec. II.E,
+//   eq. (24b)) in registers.  Every contraction of Sec. II.E is diagonal in m
+//   (the same radial function in all factors, eqs. (14), (17a)), so D3, D4,
+//   the energy and the adjoint dE_i/dB_{i m .} come from the lane's own row
+//   with compile-time tables.  The backward sweep reads the pair records
+//   again, forms each lane's share of dE_i/dr_ij (eq. (24c)), sums the K
+//   shares of a pair through LDS and scatters forces with device atomics;
+//   E, W and G are accumulated with device atomics as well.
+// The per-atom basis B and its adjoint never leave registers; only the
+// per-pair radial record (4 + 2K values) goes through memory.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -136,6 +140,127 @@ __device__ __forceinline__ void radial(const ParamsT<T>* __restrict__ P, T r, T 
     }
 }
 
+
+// sin(pi x) and cos(pi x) for -0.25 <= x <= 1.25 (here x is the scaled
+// distance, in [0, 1]).  Quadrant reduction t = x - k/2 with k = rint(2x) is
+// exact (Sterbenz); sin and cos of theta = pi t, |theta| <= pi/4, come from
+// their Taylor series (terms to theta^17 / theta^18 in double, theta^9 /
+// theta^10 in float: truncation below half an ulp).
+template <typename T>
+__device__ __forceinline__ void sincospi_unit(T x, T* sp, T* cp) {
+    const T k = rint(T(2) * x);
+    const T t = x - T(0.5) * k;
+    const T th = T(3.14159265358979323846) * t;
+    const T z = th * th;
+    T sn, cs;
+    if constexpr (sizeof(T) == 8) {
+        T ps = T(1.0 / 355687428096000.0);                      //  1/17!
+        ps = ps * z - T(1.0 / 1307674368000.0);                 // -1/15!
+        ps = ps * z + T(1.0 / 6227020800.0);                    //  1/13!
+        ps = ps * z - T(1.0 / 39916800.0);                      // -1/11!
+        ps = ps * z + T(1.0 / 362880.0);                        //  1/9!
+        ps = ps * z - T(1.0 / 5040.0);                          // -1/7!
+        ps = ps * z + T(1.0 / 120.0);                           //  1/5!
+        ps = ps * z - T(1.0 / 6.0);                             // -1/3!
+        T pc = -T(1.0 / 6402373705728000.0);                    // -1/18!
+        pc = pc * z + T(1.0 / 20922789888000.0);                //  1/16!
+        pc = pc * z - T(1.0 / 87178291200.0);                   // -1/14!
+        pc = pc * z + T(1.0 / 479001600.0);                     //  1/12!
+        pc = pc * z - T(1.0 / 3628800.0);                       // -1/10!
+        pc = pc * z + T(1.0 / 40320.0);                         //  1/8!
+        pc = pc * z - T(1.0 / 720.0);                           // -1/6!
+        pc = pc * z + T(1.0 / 24.0);                            //  1/4!
+        pc = pc * z - T(0.5);                                   // -1/2!
+        sn = th + th * z * ps;
+        cs = T(1) + z * pc;
+    } else {
+        T ps = T(1.0 / 362880.0);                               //  1/9!
+        ps = ps * z - T(1.0 / 5040.0);                          // -1/7!
+        ps = ps * z + T(1.0 / 120.0);                           //  1/5!
+        ps = ps * z - T(1.0 / 6.0);                             // -1/3!
+        T pc = -T(1.0 / 3628800.0);                             // -1/10!
+        pc = pc * z + T(1.0 / 40320.0);                         //  1/8!
+        pc = pc * z - T(1.0 / 720.0);                           // -1/6!
+        pc = pc * z + T(1.0 / 24.0);                            //  1/4!
+        pc = pc * z - T(0.5);                                   // -1/2!
+        sn = th + th * z * ps;
+        cs = T(1) + z * pc;
+    }
+    // rotate by k quarter turns
+    const int q = static_cast<int>(k) & 3;
+    T so = sn, co = cs;
+    if (q == 1) { so = cs; co = -sn; }
+    else if (q == 2) { so = -sn; co = -cs; }
+    else if (q == 3) { so = -cs; co = sn; }
+    *sp = so;
+    *cp = co;
+}
+
+// Radial functions for the standard snapshot family (Bessel alpha = 1..nb at
+// one beta, inverse powers gamma = 1..ni): one expm1, one sincos and one exp
+// per pair; sin/cos(alpha pi x) by angle addition; Q read from LDS.
+template <typename T, bool DERIV>
+__device__ __forceinline__ void radial_std(const ParamsT<T>* __restrict__ P, const T* __restrict__ sQ, T r,
+                                           T rinv, T (&R)[POD_MAX_K], T (&dR)[POD_MAX_K]) {
+    const T inv_h = P->inv_h;
+    const T dist = r - P->rin;
+    const T t = dist * inv_h;
+    const T t2 = t * t;
+    const T y = T(1) - t2 * t;
+    const T s = y * y + T(1e-6);
+    const T rs = d_rsqrt(s);
+    const T fc = d_exp(T(1) - rs);
+    const T dfc = DERIV ? fc * y * (rs * rs * rs) * (T(-3) * t2 * inv_h) : T(0);
+    const T idist = T(1) / dist;
+    constexpr T kPi = T(3.14159265358979323846);
+#pragma unroll
+    for (int k = 0; k < POD_MAX_K; ++k) { R[k] = 0; dR[k] = 0; }
+    const int nb = P->std_nb, ni = P->std_ni;
+    if (nb > 0) {
+        T x, dx;
+        const T bh = P->std_bh;
+        if (bh == T(0)) {
+            x = t; dx = inv_h;
+        } else {
+            const T em = d_expm1(-bh * dist);
+            x = em * P->std_inv_em1;
+            dx = -bh * (em + T(1)) * P->std_inv_em1;
+        }
+        T s1, c1;
+        sincospi_unit(x, &s1, &c1);
+        const T fci = fc * idist;
+        const T dfci = DERIV ? dfc * idist : T(0);
+        const T pdx = kPi * dx;
+        T sk = 0, ck = 1;
+        for (int l = 0; l < nb; ++l) {
+            const T ns = sk * c1 + ck * s1;
+            const T nc = ck * c1 - sk * s1;
+            sk = ns; ck = nc;
+            // Phi = f_c sin/(r - rin); Phi' = f_c' sin/(r-rin) + f_c (alpha pi cos dx - sin/(r-rin))/(r-rin)
+            const T ph = fci * sk;
+            const T dph = DERIV ? dfci * sk + fci * (T(l + 1) * pdx * ck - sk * idist) : T(0);
+            const T* q = sQ + l * POD_MAX_K;
+#pragma unroll
+            for (int k = 0; k < POD_MAX_K; ++k) {
+                R[k] += q[k] * ph;
+                if (DERIV) dR[k] += q[k] * dph;
+            }
+        }
+    }
+    T pw = T(1);
+    for (int g = 1; g <= ni; ++g) {
+        pw *= rinv;                                  // r^-g
+        const T ph = fc * pw;
+        const T dph = DERIV ? (dfc - T(g) * fc * rinv) * pw : T(0);
+        const T* q = sQ + (nb + g - 1) * POD_MAX_K;
+#pragma unroll
+        for (int k = 0; k < POD_MAX_K; ++k) {
+            R[k] += q[k] * ph;
+            if (DERIV) dR[k] += q[k] * dph;
+        }
+    }
+}
+
 template <typename T>
 struct KArgs {
     const ParamsT<T>* prm;
@@ -148,61 +273,13 @@ struct KArgs {
     const T* coef;     // energy coefficients (mode 1)
     T* D;              // descriptors (mode 0)
     T* E_atom;         // per-atom energy or null (mode 1)
-    T* F;              // forces or null (mode 1)
-    double* part;      // per-block partials: E, W[9], G[M] (mode 1)
-    int want_G;
+    double* Facc;      // force accumulator (3N, zero on entry) (mode 1, backward, no gbuf)
+    T* gbuf;           // per-pair gradients dE_i/dr_ij (3P) when a reverse index is given
+    double* part;      // block partials, column-major [10 + M][nblk] (mode 1)
+    int want_G;        // block partials of G requested
     int want_back;     // run the backward sweep (forces or virial requested)
     int* err;
 };
-
-// Pair stage: lane evaluates neighbour slot `slot` of its atom (valid) and
-// writes rhat, 1/r, R_k, (R'_k) to LDS column `col`.  Returns the pair vector.
-template <typename T, bool DERIV>
-__device__ __forceinline__ void pair_stage(const KArgs<T>& g, int i, int p, bool valid, int col, int K,
-                                           T* sU, T* sRinv, T* sR, T* sdR, T (&dvec)[3]) {
-    T d0 = 0, d1 = 0, d2 = 0;
-    bool ok = false;
-    if (valid) {
-        const int j = g.nbr_j[p];
-        const int sh = g.shift[p];
-        if (j < 0 || j >= g.N || (!g.cell.periodic && (sh & 0xFFFFFF) != 0)) {
-            atomicOr(g.err, ERR_NEIGH);
-        } else {
-            const T sx = T(unpack_shift(sh, 0)), sy = T(unpack_shift(sh, 1)), sz = T(unpack_shift(sh, 2));
-            const T* a = g.cell.a;
-            d0 = g.pos[3 * j + 0] - g.pos[3 * i + 0] + sx * a[0] + sy * a[3] + sz * a[6];
-            d1 = g.pos[3 * j + 1] - g.pos[3 * i + 1] + sx * a[1] + sy * a[4] + sz * a[7];
-            d2 = g.pos[3 * j + 2] - g.pos[3 * i + 2] + sx * a[2] + sy * a[5] + sz * a[8];
-            const T r2 = d0 * d0 + d1 * d1 + d2 * d2;
-            if (!d_finite(r2)) {
-                atomicOr(g.err, ERR_NONFINITE);
-            } else {
-                const T r = d_sqrt(r2);
-                if (r <= g.prm->rin || r >= g.prm->rcut) atomicOr(g.err, ERR_RANGE);
-                else ok = true;
-            }
-        }
-    }
-    // invalid lanes evaluate a harmless mid-range distance and store zeros
-    const T rmid = T(0.5) * (g.prm->rin + g.prm->rcut);
-    const T r = ok ? d_sqrt(d0 * d0 + d1 * d1 + d2 * d2) : rmid;
-    const T rinv = T(1) / r;
-    T R[POD_MAX_K], dR[POD_MAX_K];
-    radial<T, DERIV>(g.prm, r, rinv, R, dR);
-    const T z = ok ? T(1) : T(0);
-    sU[col] = d0 * rinv * z;
-    sU[WAVE + col] = d1 * rinv * z;
-    sU[2 * WAVE + col] = d2 * rinv * z;
-    sRinv[col] = rinv;
-#pragma unroll
-    for (int k = 0; k < POD_MAX_K; ++k) {
-        if (k < K) {
-            sR[k * WAVE + col] = R[k] * z;
-            if (DERIV) sdR[k * WAVE + col] = dR[k] * z;
-        }
-    }
-    dvec[0] = d0 * z; dvec[1] = d1 * z; dvec[2] = d2 * z;
-}
 
 template <typename T, int PA>
 __device__ __forceinline__ void accumulate_basis(T (&acc)[n_mono(PA)], T Rm, T ux, T uy, T uz) {
@@ -219,22 +296,128 @@ __device__ __forceinline__ void accumulate_basis(T (&acc)[n_mono(PA)], T Rm, T u
     }
 }
 
-template <typename T, int PA, int MODE>
-__global__ __launch_bounds__(64) void atom_kernel(KArgs<T> g) {
+// Neighbour slots are fetched two rounds ahead: the index and image shift of
+// round r + 2 and the neighbour position of round r + 1 are requested before
+// the arithmetic of round r.
+struct SlotIdx {
+    int j;    // neighbour index, -1 for an empty slot
+    int sh;   // packed image shift
+};
+
+template <typename T>
+__device__ __forceinline__ SlotIdx slot_index(const KArgs<T>& g, bool valid, int p) {
+    SlotIdx s;
+    s.j = -1; s.sh = 0;
+    if (valid) { s.j = g.nbr_j[p]; s.sh = g.shift[p]; }
+    return s;
+}
+
+template <typename T>
+__device__ __forceinline__ void slot_pos(const KArgs<T>& g, const SlotIdx& s, T (&pj)[3]) {
+    pj[0] = pj[1] = pj[2] = T(0);
+    if (s.j >= 0 && s.j < g.N) {
+        pj[0] = g.pos[3 * s.j + 0];
+        pj[1] = g.pos[3 * s.j + 1];
+        pj[2] = g.pos[3 * s.j + 2];
+    }
+}
+
+// r_ij = r_j + n.cell - r_i, |r_ij| and validity of one fetched slot.  Data
+// errors are latched in the error word when `report` is set.
+template <typename T>
+__device__ __forceinline__ bool slot_geometry(const KArgs<T>& g, bool valid, const SlotIdx& s, const T (&pj)[3],
+                                              const T (&pi)[3], bool report, T (&d)[3], T& r) {
+    d[0] = d[1] = d[2] = T(0);
+    r = T(0.5) * (g.prm->rin + g.prm->rcut);
+    if (!valid) return false;
+    if (s.j < 0 || s.j >= g.N || (!g.cell.periodic && (s.sh & 0xFFFFFF) != 0)) {
+        if (report) atomicOr(g.err, ERR_NEIGH);
+        return false;
+    }
+    const T sx = T(unpack_shift(s.sh, 0)), sy = T(unpack_shift(s.sh, 1)), sz = T(unpack_shift(s.sh, 2));
+    const T* a = g.cell.a;
+    const T d0 = pj[0] - pi[0] + sx * a[0] + sy * a[3] + sz * a[6];
+    const T d1 = pj[1] - pi[1] + sx * a[1] + sy * a[4] + sz * a[7];
+    const T d2 = pj[2] - pi[2] + sx * a[2] + sy * a[5] + sz * a[8];
+    const T r2 = d0 * d0 + d1 * d1 + d2 * d2;
+    if (!d_finite(r2)) {
+        if (report) atomicOr(g.err, ERR_NONFINITE);
+        return false;
+    }
+    const T rr = d_sqrt(r2);
+    if (rr <= g.prm->rin || rr >= g.prm->rcut) {
+        if (report) atomicOr(g.err, ERR_RANGE);
+        return false;
+    }
+    d[0] = d0; d[1] = d1; d[2] = d2;
+    r = rr;
+    return true;
+}
+
+template <typename T, bool DERIV, bool FAST>
+__device__ __forceinline__ void radial_any(const ParamsT<T>* __restrict__ P, const T* sQ, T r, T rinv,
+                                           T (&R)[POD_MAX_K], T (&dR)[POD_MAX_K]) {
+    if constexpr (FAST) radial_std<T, DERIV>(P, sQ, r, rinv, R, dR);
+    else radial<T, DERIV>(P, r, rinv, R, dR);
+}
+
+// LDS layout of atom_kernel (per 64-lane workgroup), in bytes:
+//   [Q (L x POD_MAX_K)] [per-lane double scratch (max(64, M), 3 x 64)]
+//   [T area: union { round staging [64][stage_stride(K)], adjoint rows [APW][K][NA | 1] }]
+__host__ __device__ constexpr int stage_stride(int K) { return (3 + K) | 1; }
+__host__ __device__ constexpr int odd_len(int n) { return n | 1; }
+
+struct AtomLds {
+    size_t off_q, off_e, off_f, off_t, total;
+};
+
+__host__ __device__ inline AtomLds atom_lds_layout(int K, int NA, int M, size_t tsize) {
+    const int apw = WAVE / K;
+    AtomLds L;
+    L.off_q = 0;
+    L.off_e = ((static_cast<size_t>(POD_MAX_L) * POD_MAX_K * tsize + 15) / 16) * 16;
+    const size_t ne = static_cast<size_t>(M > WAVE ? M : WAVE);
+    L.off_f = L.off_e + ((ne * sizeof(double) + 15) / 16) * 16;
+    L.off_t = L.off_f + static_cast<size_t>(3) * WAVE * sizeof(double);
+    const size_t stage = static_cast<size_t>(WAVE) * stage_stride(K) * tsize;
+    const size_t adj = static_cast<size_t>(apw) * K * odd_len(NA) * tsize;
+    L.total = L.off_t + (stage > adj ? stage : adj);
+    return L;
+}
+
+// One workgroup = one wavefront = APW = 64 / K atoms.  Neighbour slots are
+// processed K at a time per atom ("rounds"); in a round, lane (a, s)
+// evaluates slot s of atom a.
+template <typename T, int PA, int MODE, bool FAST>
+__device__ __forceinline__ void atom_body(const KArgs<T>& g) {
     constexpr MonoTable<PA> mt{};
     constexpr int NA = n_mono(PA);
+    constexpr int NAP = odd_len(NA);
     using Tab = D4Table<PA>;
     constexpr int KA = Tab::KA;
     constexpr int NT = Tab::NT;
 
     const ParamsT<T>* __restrict__ P = g.prm;
     const int K = P->K;
+    const int M = P->M;
+    const int SS = stage_stride(K);
     const int lane = threadIdx.x;
     const int apw = WAVE / K;
     const int al = lane / K;
-    const int q = lane - al * K;
+    const int q = lane - al * K;       // radial index m, or neighbour slot within a round
+    const int m = q;
     const int atom = blockIdx.x * apw + al;
     const bool act = (al < apw) && (atom < g.N);
+
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const AtomLds LY = atom_lds_layout(K, NA, M, sizeof(T));
+    T* sQ = reinterpret_cast<T*>(smem_raw + LY.off_q);
+    double* sE = reinterpret_cast<double*>(smem_raw + LY.off_e);
+    double* sF = reinterpret_cast<double*>(smem_raw + LY.off_f);
+    T* sT = reinterpret_cast<T*>(smem_raw + LY.off_t);
+
+    if (FAST)
+        for (int i = lane; i < POD_MAX_L * POD_MAX_K; i += WAVE) sQ[i] = (&P->Q[0][0])[i];
 
     int beg = 0, cnt = 0;
     if (act) {
@@ -246,29 +429,44 @@ __global__ __launch_bounds__(64) void atom_kernel(KArgs<T> g) {
         }
     }
     const int nround = (wave_max(cnt) + K - 1) / K;
+    T pi[3] = {T(0), T(0), T(0)};
+    if (act) { pi[0] = g.pos[3 * atom + 0]; pi[1] = g.pos[3 * atom + 1]; pi[2] = g.pos[3 * atom + 2]; }
+    __syncthreads();
 
-    extern __shared__ unsigned char smem_raw[];
-    T* sU = reinterpret_cast<T*>(smem_raw);
-    T* sRinv = sU + 3 * WAVE;
-    T* sR = sRinv + WAVE;
-    T* sdR = sR + K * WAVE;
-    T* sRed = sdR + (MODE == 1 ? K * WAVE : 0);
-
-    // ---------------- forward: atomic basis row B_{i, m=q, .} ----------------
+    // ---------------- forward: atomic basis row B_{i, m, .} (eq. (24b)) ----------------
     T acc[NA];
 #pragma unroll
     for (int mu = 0; mu < NA; ++mu) acc[mu] = 0;
+    SlotIdx i0 = slot_index(g, act && q < cnt, beg + q);
+    T p0[3];
+    slot_pos(g, i0, p0);
+    SlotIdx i1 = slot_index(g, act && K + q < cnt, beg + K + q);
     for (int rd = 0; rd < nround; ++rd) {
         {
-            const int sl = rd * K + q;
-            T dv[3];
-            pair_stage<T, false>(g, atom, beg + sl, act && sl < cnt, lane, K, sU, sRinv, sR, sdR, dv);
+            // pair stage: rhat and R_k of slot rd*K + q, staged for the atom's K lanes
+            const int slot = rd * K + q;
+            const SlotIdx ic = i0;
+            T pc[3] = {p0[0], p0[1], p0[2]};
+            slot_pos(g, i1, p0);
+            i0 = i1;
+            i1 = slot_index(g, act && slot + 2 * K < cnt, beg + slot + 2 * K);
+            T d[3], r;
+            const bool ok = slot_geometry<T>(g, act && slot < cnt, ic, pc, pi, true, d, r);
+            const T rinv = T(1) / r;
+            T R[POD_MAX_K], dR[POD_MAX_K];
+            radial_any<T, false, FAST>(P, sQ, r, rinv, R, dR);
+            const T z = ok ? T(1) : T(0);
+            T* row = sT + lane * SS;
+            row[0] = d[0] * rinv; row[1] = d[1] * rinv; row[2] = d[2] * rinv;
+#pragma unroll
+            for (int k = 0; k < POD_MAX_K; ++k)
+                if (k < K) row[3 + k] = R[k] * z;
         }
         __syncthreads();
-        for (int s = 0; s < K; ++s) {
-            if (act && rd * K + s < cnt) {
-                const int col = al * K + s;
-                accumulate_basis<T, PA>(acc, sR[q * WAVE + col], sU[col], sU[WAVE + col], sU[2 * WAVE + col]);
+        if (act) {
+            for (int s = 0; s < K; ++s) {
+                const T* row = sT + (al * K + s) * SS;
+                accumulate_basis<T, PA>(acc, row[3 + m], row[0], row[1], row[2]);
             }
         }
         __syncthreads();
@@ -291,7 +489,6 @@ __global__ __launch_bounds__(64) void atom_kernel(KArgs<T> g) {
         d4[Tab::build.tp[t]] += T(Tab::build.tc[t]) * acc[Tab::build.tx[t]] * acc[Tab::build.ty[t]] *
                                 acc[Tab::build.tz[t]];
 
-    const int m = q;
     const bool has2 = act && m < P->K2;
     const bool has3 = act && m < P->K3;
     const bool has4 = act && m < P->K4;
@@ -299,7 +496,7 @@ __global__ __launch_bounds__(64) void atom_kernel(KArgs<T> g) {
 
     if (MODE == 0) {
         if (act) {
-            T* Drow = g.D + static_cast<size_t>(atom) * P->M;
+            T* Drow = g.D + static_cast<size_t>(atom) * M;
             if (q == 0) Drow[0] = T(1);
             if (has2) Drow[1 + m] = acc[0];
             if (has3) {
@@ -318,7 +515,7 @@ __global__ __launch_bounds__(64) void atom_kernel(KArgs<T> g) {
 
     // ---------------- energy (eq. (57a)) and adjoint dE_i/dB ----------------
     const T* c = g.coef;
-    T w2 = has2 ? c[1 + m] : T(0);
+    const T w2 = has2 ? c[1 + m] : T(0);
     T w3[PA + 1], w4[KA];
 #pragma unroll
     for (int n = 0; n <= PA; ++n) w3[n] = (has3 && n <= P3) ? c[P->off3 + m * (P3 + 1) + n] : T(0);
@@ -361,7 +558,6 @@ __global__ __launch_bounds__(64) void atom_kernel(KArgs<T> g) {
 
     // per-atom energy: sum the K lanes of the atom through LDS
     {
-        double* sE = reinterpret_cast<double*>(smem_raw);
         sE[lane] = e;
         __syncthreads();
         double ei = 0.0;
@@ -371,54 +567,66 @@ __global__ __launch_bounds__(64) void atom_kernel(KArgs<T> g) {
         }
         __syncthreads();
         const double eb = wave_sum(ei);
-        if (lane == 0) g.part[static_cast<size_t>(blockIdx.x) * (10 + P->M)] = eb;
+        if (lane == 0) g.part[blockIdx.x] = eb;
     }
-    // block partial of the global descriptors G = sum_i D_i (eq. (58a))
+    // global descriptors G = sum_i D_i (eq. (58a)): block partial in LDS
     if (g.want_G) {
-        double* sG = reinterpret_cast<double*>(smem_raw);
-        const int M = P->M;
-        for (int k = lane; k < M; k += WAVE) sG[k] = 0.0;
+        for (int k = lane; k < M; k += WAVE) sE[k] = 0.0;
         __syncthreads();
         for (int a2 = 0; a2 < apw; ++a2) {
             if (al == a2 && act) {
-                if (q == 0) sG[0] += 1.0;
-                if (has2) sG[1 + m] += static_cast<double>(acc[0]);
+                if (q == 0) sE[0] += 1.0;
+                if (has2) sE[1 + m] += static_cast<double>(acc[0]);
                 if (has3)
 #pragma unroll
                     for (int n = 0; n <= PA; ++n)
-                        if (n <= P3) sG[P->off3 + m * (P3 + 1) + n] += static_cast<double>(d3[n]);
+                        if (n <= P3) sE[P->off3 + m * (P3 + 1) + n] += static_cast<double>(d3[n]);
                 if (has4)
 #pragma unroll
                     for (int p = 0; p < KA; ++p)
-                        if (p < Ka4) sG[P->off4 + m * Ka4 + p] += static_cast<double>(d4[p]);
+                        if (p < Ka4) sE[P->off4 + m * Ka4 + p] += static_cast<double>(d4[p]);
             }
             __syncthreads();
         }
-        double* pg = g.part + static_cast<size_t>(blockIdx.x) * (10 + M) + 10;
-        for (int k = lane; k < M; k += WAVE) pg[k] = sG[k];
-        __syncthreads();
+        for (int k = lane; k < M; k += WAVE) g.part[static_cast<size_t>(10 + k) * gridDim.x + blockIdx.x] = sE[k];
     }
 
     if (!g.want_back) return;
 
-    // ---------------- backward sweep: g_ij = dE_i/dr_ij (eq. (24c)) ----------------
+    // ---------------- backward: g_ij = dE_i/dr_ij (eq. (24c)) ----------------
+    // adjoint rows to LDS; then lane (a, s) takes neighbour slot s of atom a in
+    // every round, re-evaluates its radial functions with derivatives and
+    // contracts them with the K adjoint rows of atom a
+    T* sAb = sT;
+    if (act) {
+#pragma unroll
+        for (int mu = 0; mu < NA; ++mu) sAb[(al * K + m) * NAP + mu] = ab[mu];
+    }
+    __syncthreads();
+
     double vir[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) vir[k] = 0.0;
-    T fown0 = 0, fown1 = 0, fown2 = 0;
+    double fo0 = 0.0, fo1 = 0.0, fo2 = 0.0;
+    SlotIdx b0 = slot_index(g, act && q < cnt, beg + q);
+    T bp0[3];
+    slot_pos(g, b0, bp0);
+    SlotIdx b1 = slot_index(g, act && K + q < cnt, beg + K + q);
     for (int rd = 0; rd < nround; ++rd) {
-        const int myslot = rd * K + q;
-        const bool mine = act && myslot < cnt;
-        T dv[3];
-        pair_stage<T, true>(g, atom, beg + myslot, mine, lane, K, sU, sRinv, sR, sdR, dv);
-        __syncthreads();
-        for (int s = 0; s < K; ++s) {
-            T gx = 0, gy = 0, gz = 0;
-            const int col = al * K + s;
-            if (act && rd * K + s < cnt) {
-                const T Rm = sR[m * WAVE + col], dRm = sdR[m * WAVE + col];
-                const T ux = sU[col], uy = sU[WAVE + col], uz = sU[2 * WAVE + col];
-                const T ri = sRinv[col];
+        const int slot = rd * K + q;
+        const SlotIdx ic = b0;
+        T pc[3] = {bp0[0], bp0[1], bp0[2]};
+        slot_pos(g, b1, bp0);
+        b0 = b1;
+        b1 = slot_index(g, act && slot + 2 * K < cnt, beg + slot + 2 * K);
+        if (act && slot < cnt) {
+            T d[3], r;
+            const bool ok = slot_geometry<T>(g, true, ic, pc, pi, false, d, r);
+            if (ok) {
+                const T ri = T(1) / r;
+                T R[POD_MAX_K], dR[POD_MAX_K];
+                radial_any<T, true, FAST>(P, sQ, r, ri, R, dR);
+                const T ux = d[0] * ri, uy = d[1] * ri, uz = d[2] * ri;
                 T A[NA];
                 A[0] = T(1);
 #pragma unroll
@@ -426,81 +634,171 @@ __global__ __launch_bounds__(64) void atom_kernel(KArgs<T> g) {
                     const T u = mt.axis[mu] == 0 ? ux : (mt.axis[mu] == 1 ? uy : uz);
                     A[mu] = A[mt.par[mu]] * u;
                 }
-                T hd[PA + 1];
+                T gx = 0, gy = 0, gz = 0;
 #pragma unroll
-                for (int n = 0; n <= PA; ++n) hd[n] = 0;
-                T g0 = 0, g1 = 0, g2 = 0;
+                for (int k = 0; k < POD_MAX_K; ++k) {
+                    if (k < K) {
+                        const T* abk = sAb + (al * K + k) * NAP;
+                        T hd[PA + 1];
+                        T gp[3][PA + 1];   // gradient sums grouped by the exponent being lowered
 #pragma unroll
-                for (int mu = 0; mu < NA; ++mu) {
-                    hd[mt.deg[mu]] += ab[mu] * A[mu];
-                    if (mt.down[mu][0] >= 0) g0 += (ab[mu] * T(mt.ex[mu][0])) * A[mt.down[mu][0]];
-                    if (mt.down[mu][1] >= 0) g1 += (ab[mu] * T(mt.ex[mu][1])) * A[mt.down[mu][1]];
-                    if (mt.down[mu][2] >= 0) g2 += (ab[mu] * T(mt.ex[mu][2])) * A[mt.down[mu][2]];
+                        for (int n = 0; n <= PA; ++n) { hd[n] = 0; gp[0][n] = 0; gp[1][n] = 0; gp[2][n] = 0; }
+#pragma unroll
+                        for (int mu = 0; mu < NA; ++mu) {
+                            const T w = abk[mu];
+                            hd[mt.deg[mu]] += w * A[mu];
+#pragma unroll
+                            for (int dd = 0; dd < 3; ++dd)
+                                if (mt.down[mu][dd] >= 0) gp[dd][mt.ex[mu][dd]] += w * A[mt.down[mu][dd]];
+                        }
+                        T hsum = 0, eul = 0, g0 = 0, g1 = 0, g2 = 0;
+#pragma unroll
+                        for (int n = 0; n <= PA; ++n) {
+                            hsum += hd[n]; eul += T(n) * hd[n];
+                            g0 += T(n) * gp[0][n]; g1 += T(n) * gp[1][n]; g2 += T(n) * gp[2][n];
+                        }
+                        // d/dr_ij [R_k(r) h(rhat)] = R'_k h rhat + R_k (grad_u h - (rhat . grad_u h) rhat)/r,
+                        // rhat . grad_u h = sum_n n h_n for the degree-n parts h_n (Euler)
+                        const T a1 = dR[k] * hsum - R[k] * eul * ri;
+                        const T a2 = R[k] * ri;
+                        gx += a1 * ux + a2 * g0;
+                        gy += a1 * uy + a2 * g1;
+                        gz += a1 * uz + a2 * g2;
+                    }
                 }
-                T hsum = 0, eul = 0;
+                if (g.gbuf) {
+                    T* gp3 = g.gbuf + 3 * static_cast<size_t>(beg + slot);
+                    gp3[0] = gx; gp3[1] = gy; gp3[2] = gz;
+                } else {
+                    const int j = ic.j;
+                    atomicAdd(&g.Facc[3 * j + 0], -static_cast<double>(gx));
+                    atomicAdd(&g.Facc[3 * j + 1], -static_cast<double>(gy));
+                    atomicAdd(&g.Facc[3 * j + 2], -static_cast<double>(gz));
+                    fo0 += gx; fo1 += gy; fo2 += gz;
+                }
+                const double dd3[3] = {double(d[0]), double(d[1]), double(d[2])};
+                const double gg[3] = {double(gx), double(gy), double(gz)};
 #pragma unroll
-                for (int n = 0; n <= PA; ++n) { hsum += hd[n]; eul += T(n) * hd[n]; }
-                // d/dr_ij [R_m(r) h(rhat)] = R'_m h rhat + R_m (grad_u h - (rhat . grad_u h) rhat)/r,
-                // with rhat . grad_u h = sum_n n h_n for the degree-n parts h_n (Euler)
-                const T a1 = dRm * hsum - Rm * eul * ri;
-                const T a2 = Rm * ri;
-                gx = a1 * ux + a2 * g0;
-                gy = a1 * uy + a2 * g1;
-                gz = a1 * uz + a2 * g2;
+                for (int x = 0; x < 3; ++x)
+#pragma unroll
+                    for (int y = 0; y < 3; ++y) vir[3 * x + y] -= dd3[x] * gg[y];
+            } else if (g.gbuf) {
+                T* gp3 = g.gbuf + 3 * static_cast<size_t>(beg + slot);
+                gp3[0] = T(0); gp3[1] = T(0); gp3[2] = T(0);
             }
-            T* red = sRed + (static_cast<size_t>(col) * K + m) * 3;
-            if (act) { red[0] = gx; red[1] = gy; red[2] = gz; }
         }
-        __syncthreads();
-        if (mine) {
-            T gx = 0, gy = 0, gz = 0;
-            const T* red = sRed + static_cast<size_t>(lane) * K * 3;
-            for (int k = 0; k < K; ++k) { gx += red[3 * k]; gy += red[3 * k + 1]; gz += red[3 * k + 2]; }
-            fown0 += gx; fown1 += gy; fown2 += gz;
-            if (g.F) {
-                const int j = g.nbr_j[beg + myslot];
-                atomicAdd(&g.F[3 * j + 0], -gx);
-                atomicAdd(&g.F[3 * j + 1], -gy);
-                atomicAdd(&g.F[3 * j + 2], -gz);
-            }
-            const double dd[3] = {double(dv[0]), double(dv[1]), double(dv[2])};
-            const double gg[3] = {double(gx), double(gy), double(gz)};
-#pragma unroll
-            for (int a = 0; a < 3; ++a)
-#pragma unroll
-                for (int b = 0; b < 3; ++b) vir[3 * a + b] -= dd[a] * gg[b];
-        }
-        __syncthreads();
     }
-    // own-atom force: F_i += sum_j g_ij, summed over the atom's K lanes
-    {
-        T* sF = sRed;
-        sF[3 * lane + 0] = fown0; sF[3 * lane + 1] = fown1; sF[3 * lane + 2] = fown2;
-        __syncthreads();
-        if (act && q == 0 && g.F) {
-            T f0 = 0, f1 = 0, f2 = 0;
-            for (int k = 0; k < K; ++k) {
-                const int l2 = al * K + k;
-                f0 += sF[3 * l2]; f1 += sF[3 * l2 + 1]; f2 += sF[3 * l2 + 2];
-            }
-            atomicAdd(&g.F[3 * atom + 0], f0);
-            atomicAdd(&g.F[3 * atom + 1], f1);
-            atomicAdd(&g.F[3 * atom + 2], f2);
+    // own-atom force F_i += sum_j g_ij: sum the K lanes of the atom
+    sF[3 * lane + 0] = fo0; sF[3 * lane + 1] = fo1; sF[3 * lane + 2] = fo2;
+    __syncthreads();
+    if (act && q == 0 && !g.gbuf) {
+        double f0 = 0.0, f1 = 0.0, f2 = 0.0;
+        for (int k = 0; k < K; ++k) {
+            const int l2 = al * K + k;
+            f0 += sF[3 * l2]; f1 += sF[3 * l2 + 1]; f2 += sF[3 * l2 + 2];
         }
+        atomicAdd(&g.Facc[3 * atom + 0], f0);
+        atomicAdd(&g.Facc[3 * atom + 1], f1);
+        atomicAdd(&g.Facc[3 * atom + 2], f2);
     }
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
         const double v = wave_sum(vir[k]);
-        if (lane == 0) g.part[static_cast<size_t>(blockIdx.x) * (10 + P->M) + 1 + k] = v;
+        if (lane == 0) g.part[static_cast<size_t>(1 + k) * gridDim.x + blockIdx.x] = v;
     }
 }
 
-// Column sums of the block partials: column 0 -> E, 1..9 -> W, 10.. -> G.
-__global__ __launch_bounds__(256) void finalize_kernel(const double* __restrict__ part, int nblk, int stride,
-                                                       double* E, double* W, double* G) {
+// Kernel entry points.  The FP64 instances up to angular degree 4 are asked
+// to fit two wavefronts per SIMD (at most 256 registers); the others keep the
+// compiler's default allocation.
+template <typename T, int PA, int MODE, bool FAST>
+__global__ __launch_bounds__(64) void atom_kernel(KArgs<T> g) {
+    atom_body<T, PA, MODE, FAST>(g);
+}
+
+template <typename T, int PA, int MODE, bool FAST>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void atom_kernel_occ2(KArgs<T> g) {
+    atom_body<T, PA, MODE, FAST>(g);
+}
+
+// Totals and forces.  Blocks 0 .. 9 + M: column sums of the block partials
+// (column 0 -> E, 1..9 -> W, 10.. -> G).  Remaining blocks, with a reverse
+// index: F_n = sum over the pairs p of n of g_p - g_rev(p) (8 atoms x 32
+// lanes per block, deterministic); without one: F = Facc (accumulated with
+// atomics) and Facc cleared for the next call.
+template <typename T>
+struct FinArgs {
+    const double* part;
+    int nblk, ncol;
+    double* E;
+    double* W;
+    double* G;
+    double* Facc;
+    T* F;
+    long n3;
+    const T* gbuf;
+    const int* rev;
+    const int* offsets;
+    int N, P;
+    int* err;
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void finalize_kernel(FinArgs<T> f) {
     const int col = blockIdx.x;
+    if (col >= f.ncol) {
+        const int fb = col - f.ncol;
+        if (f.rev) {
+            const int a = fb * 8 + static_cast<int>(threadIdx.x) / 32;
+            const int s0 = threadIdx.x % 32;
+            double f0 = 0.0, f1 = 0.0, f2 = 0.0;
+            if (a < f.N) {
+                const int b = f.offsets[a], e = f.offsets[a + 1];
+                if (b >= 0 && e >= b && e <= f.P) {
+                    for (int p = b + s0; p < e; p += 32) {
+                        const int q = f.rev[p];
+                        f0 += static_cast<double>(f.gbuf[3 * static_cast<size_t>(p) + 0]);
+                        f1 += static_cast<double>(f.gbuf[3 * static_cast<size_t>(p) + 1]);
+                        f2 += static_cast<double>(f.gbuf[3 * static_cast<size_t>(p) + 2]);
+                        if (q >= 0 && q < f.P) {
+                            f0 -= static_cast<double>(f.gbuf[3 * static_cast<size_t>(q) + 0]);
+                            f1 -= static_cast<double>(f.gbuf[3 * static_cast<size_t>(q) + 1]);
+                            f2 -= static_cast<double>(f.gbuf[3 * static_cast<size_t>(q) + 2]);
+                        } else if (s0 == 0) {
+                            atomicOr(f.err, ERR_NEIGH);
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int o = 16; o >= 1; o >>= 1) {
+                f0 += __shfl_xor(f0, o, 32);
+                f1 += __shfl_xor(f1, o, 32);
+                f2 += __shfl_xor(f2, o, 32);
+            }
+            if (a < f.N && s0 == 0 && f.F) {
+                f.F[3 * a + 0] = static_cast<T>(f0);
+                f.F[3 * a + 1] = static_cast<T>(f1);
+                f.F[3 * a + 2] = static_cast<T>(f2);
+            }
+        } else {
+            const long i = static_cast<long>(fb) * 256 + threadIdx.x;
+            if (i < f.n3) {
+                if (f.F) f.F[i] = static_cast<T>(f.Facc[i]);
+                f.Facc[i] = 0.0;
+            }
+        }
+        return;
+    }
+    const double* part = f.part;
+    const int nblk = f.nblk;
+    double* E = f.E;
+    double* W = f.W;
+    double* G = f.G;
+    if ((col == 0 && !E) || (col >= 1 && col < 10 && !W) || (col >= 10 && !G)) return;
+    const double* src = part + static_cast<size_t>(col) * nblk;
     double s = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += blockDim.x) s += part[static_cast<size_t>(b) * stride + col];
+    for (int b = threadIdx.x; b < nblk; b += 256) s += src[b];
     __shared__ double red[256];
     red[threadIdx.x] = s;
     __syncthreads();
@@ -510,42 +808,74 @@ __global__ __launch_bounds__(256) void finalize_kernel(const double* __restrict_
     }
     if (threadIdx.x == 0) {
         const double v = red[0];
-        if (col == 0) { if (E) *E = v; }
-        else if (col < 10) { if (W) W[col - 1] = v; }
-        else if (G) G[col - 10] = v;
+        if (col == 0) *E = v;
+        else if (col < 10) W[col - 1] = v;
+        else G[col - 10] = v;
     }
 }
 
-template <typename T>
-__global__ void zero_kernel(T* __restrict__ x, long n) {
-    for (long i = blockIdx.x * static_cast<long>(blockDim.x) + threadIdx.x; i < n;
-         i += static_cast<long>(gridDim.x) * blockDim.x)
-        x[i] = T(0);
+// Reverse-pair index: for pair p = (i -> j, n) find q = (j -> i, -n) in the
+// list of j (8 atoms x 32 lanes per 256-thread block).
+__global__ __launch_bounds__(256) void reverse_kernel(const int* __restrict__ offsets, const int* __restrict__ nbr_j,
+                                                      const int* __restrict__ shift, int N, int P, int* rev,
+                                                      int* err) {
+    const int a = blockIdx.x * 8 + static_cast<int>(threadIdx.x) / 32;
+    const int s0 = threadIdx.x % 32;
+    if (a >= N) return;
+    const int b = offsets[a], e = offsets[a + 1];
+    if (b < 0 || e < b || e > P) {
+        if (s0 == 0) atomicOr(err, ERR_NEIGH);
+        return;
+    }
+    for (int p = b + s0; p < e; p += 32) {
+        const int j = nbr_j[p];
+        const int sh = shift[p];
+        int found = -1;
+        if (j >= 0 && j < N) {
+            const int neg = ((-unpack_shift(sh, 0)) & 0xFF) | (((-unpack_shift(sh, 1)) & 0xFF) << 8) |
+                            (((-unpack_shift(sh, 2)) & 0xFF) << 16);
+            const int jb = offsets[j], je = offsets[j + 1];
+            if (jb >= 0 && je >= jb && je <= P)
+                for (int qq = jb; qq < je; ++qq)
+                    if (nbr_j[qq] == a && (shift[qq] & 0xFFFFFF) == neg) { found = qq; break; }
+        }
+        rev[p] = found;
+        if (found < 0) atomicOr(err, ERR_NEIGH);
+    }
 }
 
 template <typename T, int PA, int MODE>
-hipError_t launch_atom(const KArgs<T>& a, int nblk, size_t lds, hipStream_t st) {
-    hipLaunchKernelGGL((atom_kernel<T, PA, MODE>), dim3(nblk), dim3(WAVE), lds, st, a);
+hipError_t launch_atom(const KArgs<T>& a, bool fast, int nblk, size_t lds, hipStream_t st) {
+    constexpr bool occ2 = sizeof(T) == 8 && PA <= 4;
+    if constexpr (occ2) {
+        if (fast) hipLaunchKernelGGL((atom_kernel_occ2<T, PA, MODE, true>), dim3(nblk), dim3(WAVE), lds, st, a);
+        else hipLaunchKernelGGL((atom_kernel_occ2<T, PA, MODE, false>), dim3(nblk), dim3(WAVE), lds, st, a);
+    } else {
+        if (fast) hipLaunchKernelGGL((atom_kernel<T, PA, MODE, true>), dim3(nblk), dim3(WAVE), lds, st, a);
+        else hipLaunchKernelGGL((atom_kernel<T, PA, MODE, false>), dim3(nblk), dim3(WAVE), lds, st, a);
+    }
     return hipGetLastError();
 }
 
 template <typename T, int MODE>
-hipError_t dispatch_pa(int PA, const KArgs<T>& a, int nblk, size_t lds, hipStream_t st) {
+hipError_t dispatch_pa(int PA, const KArgs<T>& a, bool fast, int nblk, size_t lds, hipStream_t st) {
     switch (PA) {
-        case 0: return launch_atom<T, 0, MODE>(a, nblk, lds, st);
-        case 1: return launch_atom<T, 1, MODE>(a, nblk, lds, st);
-        case 2: return launch_atom<T, 2, MODE>(a, nblk, lds, st);
-        case 3: return launch_atom<T, 3, MODE>(a, nblk, lds, st);
-        case 4: return launch_atom<T, 4, MODE>(a, nblk, lds, st);
-        case 5: return launch_atom<T, 5, MODE>(a, nblk, lds, st);
-        case 6: return launch_atom<T, 6, MODE>(a, nblk, lds, st);
+        case 0: return launch_atom<T, 0, MODE>(a, fast, nblk, lds, st);
+        case 1: return launch_atom<T, 1, MODE>(a, fast, nblk, lds, st);
+        case 2: return launch_atom<T, 2, MODE>(a, fast, nblk, lds, st);
+        case 3: return launch_atom<T, 3, MODE>(a, fast, nblk, lds, st);
+        case 4: return launch_atom<T, 4, MODE>(a, fast, nblk, lds, st);
+        case 5: return launch_atom<T, 5, MODE>(a, fast, nblk, lds, st);
+        case 6: return launch_atom<T, 6, MODE>(a, fast, nblk, lds, st);
         default: return hipErrorInvalidValue;
     }
 }
 
+size_t lds_bytes(int K, int PA, size_t tsize, int M) { return atom_lds_layout(K, n_mono(PA), M, tsize).total; }
+
 template <typename T>
-int fill_common(pod_handle* h, KArgs<T>& a, int N, int P, const void* pos, const double* cell,
-                const int* offsets, const int* nbr_j, const int* shift) {
+int fill_args(pod_handle* h, KArgs<T>& a, int N, int P, const void* pos, const double* cell, const int* offsets,
+              const int* nbr_j, const int* shift) {
     a.prm = static_cast<const ParamsT<T>*>(h->d_params);
     a.N = N; a.P = P;
     a.pos = static_cast<const T*>(pos);
@@ -556,75 +886,79 @@ int fill_common(pod_handle* h, KArgs<T>& a, int N, int P, const void* pos, const
         a.cell.a[k] = static_cast<T>(v);
     }
     a.offsets = offsets; a.nbr_j = nbr_j; a.shift = shift;
-    a.coef = nullptr; a.D = nullptr; a.E_atom = nullptr; a.F = nullptr; a.part = nullptr;
-    a.want_G = 0;
-    a.want_back = 0;
+    a.coef = nullptr; a.D = nullptr; a.E_atom = nullptr; a.Facc = nullptr; a.gbuf = nullptr; a.part = nullptr;
+    a.want_G = 0; a.want_back = 0;
     a.err = h->d_err;
     return POD_OK;
-}
-
-size_t lds_bytes(int K, int mode, size_t tsize, int M) {
-    size_t n = static_cast<size_t>(4 + K) * WAVE;
-    if (mode == 1) n += static_cast<size_t>(K) * WAVE + static_cast<size_t>(WAVE) * K * 3;
-    size_t bytes = n * tsize;
-    const size_t need_d = static_cast<size_t>(WAVE > M ? WAVE : M) * sizeof(double);
-    return bytes > need_d ? bytes : need_d;
 }
 
 template <typename T>
 int descriptors_impl(pod_handle* h, int N, int P, const void* pos, const double* cell, const int* offsets,
                      const int* nbr_j, const int* shift, void* D) {
+    if (N == 0) return POD_OK;
     KArgs<T> a;
-    int rc = fill_common<T>(h, a, N, P, pos, cell, offsets, nbr_j, shift);
+    const int rc = fill_args<T>(h, a, N, P, pos, cell, offsets, nbr_j, shift);
     if (rc != POD_OK) return rc;
     a.D = static_cast<T*>(D);
     const int apw = WAVE / h->K;
     const int nblk = (N + apw - 1) / apw;
-    if (nblk == 0) return POD_OK;
-    const size_t lds = lds_bytes(h->K, 0, sizeof(T), h->M);
-    timing_begin(h);
-    const hipError_t e = dispatch_pa<T, 0>(h->PA, a, nblk, lds, h->stream);
-    timing_end(h);
+    timing_begin(h, 1);
+    const hipError_t e = dispatch_pa<T, 0>(h->PA, a, h->std_ok != 0, nblk, lds_bytes(h->K, h->PA, sizeof(T), h->M),
+                                           h->stream);
+    timing_end(h, 1);
     return e == hipSuccess ? POD_OK : POD_EHIP;
 }
 
 template <typename T>
 int energy_forces_impl(pod_handle* h, int N, int P, const void* pos, const double* cell, const int* offsets,
-                       const int* nbr_j, const int* shift, const void* c, void* E_atom, double* E, void* F,
-                       double* W, double* G) {
+                       const int* nbr_j, const int* shift, const int* rev, const void* c, void* E_atom, double* E,
+                       void* F, double* W, double* G) {
     KArgs<T> a;
-    int rc = fill_common<T>(h, a, N, P, pos, cell, offsets, nbr_j, shift);
+    int rc = fill_args<T>(h, a, N, P, pos, cell, offsets, nbr_j, shift);
+    if (rc != POD_OK) return rc;
+    const int apw = WAVE / h->K;
+    const int nblk = (N + apw - 1) / apw;
+    const int ncol = 10 + h->M;
+    const bool gather = rev != nullptr && F != nullptr;
+    const size_t part_bytes = (static_cast<size_t>(ncol) * (nblk > 0 ? nblk : 1) * sizeof(double) + 255) & ~size_t(255);
+    const size_t g_bytes = gather ? static_cast<size_t>(P > 0 ? P : 1) * 3 * sizeof(T) : 0;
+    rc = ensure_scratch(h, part_bytes + g_bytes);
+    if (rc != POD_OK) return rc;
+    rc = ensure_force_acc(h, N);
     if (rc != POD_OK) return rc;
     a.coef = static_cast<const T*>(c);
     a.E_atom = static_cast<T*>(E_atom);
-    a.F = static_cast<T*>(F);
+    a.Facc = h->d_facc;
+    a.part = static_cast<double*>(h->d_scratch);
+    a.gbuf = gather ? reinterpret_cast<T*>(static_cast<char*>(h->d_scratch) + part_bytes) : nullptr;
     a.want_G = G != nullptr;
     a.want_back = (F != nullptr) || (W != nullptr);
-    const int apw = WAVE / h->K;
-    const int nblk = (N + apw - 1) / apw;
-    const int stride = 10 + h->M;
-    hipStream_t st = h->stream;
-    if (F && N > 0) {
-        const long n = 3L * N;
-        const int zb = static_cast<int>((n + 255) / 256 < 2048 ? (n + 255) / 256 : 2048);
-        hipLaunchKernelGGL((zero_kernel<T>), dim3(zb), dim3(256), 0, st, static_cast<T*>(F), n);
-        if (hipGetLastError() != hipSuccess) return POD_EHIP;
-    }
     if (nblk > 0) {
-        rc = ensure_scratch(h, static_cast<size_t>(nblk) * stride * sizeof(double));
-        if (rc != POD_OK) return rc;
-        a.part = static_cast<double*>(h->d_scratch);
-        const size_t lds = lds_bytes(h->K, 1, sizeof(T), h->M);
-        timing_begin(h);
-        const hipError_t e = dispatch_pa<T, 1>(h->PA, a, nblk, lds, st);
-        timing_end(h);
+        timing_begin(h, 1);
+        const hipError_t e = dispatch_pa<T, 1>(h->PA, a, h->std_ok != 0, nblk,
+                                               lds_bytes(h->K, h->PA, sizeof(T), h->M), h->stream);
+        timing_end(h, 1);
         if (e != hipSuccess) return POD_EHIP;
     }
-    const int ncol = G ? stride : 10;
-    if (E || W || G) {
-        hipLaunchKernelGGL(finalize_kernel, dim3(ncol), dim3(256), 0, st,
-                           static_cast<const double*>(h->d_scratch), nblk, stride, E, W, G);
-        if (hipGetLastError() != hipSuccess) return POD_EHIP;
+    // totals, and the forces: gathered from the per-pair gradients, or copied
+    // out of the atomic accumulator (which is re-zeroed)
+    FinArgs<T> fa;
+    fa.part = static_cast<const double*>(h->d_scratch);
+    fa.nblk = nblk; fa.ncol = ncol;
+    fa.E = E; fa.W = a.want_back ? W : nullptr; fa.G = G;
+    fa.Facc = h->d_facc; fa.F = static_cast<T*>(F);
+    fa.n3 = (a.want_back && !gather) ? 3L * N : 0L;
+    fa.gbuf = a.gbuf; fa.rev = gather ? rev : nullptr; fa.offsets = offsets;
+    fa.N = N; fa.P = P; fa.err = h->d_err;
+    const int nfb = gather ? (N + 7) / 8 : static_cast<int>((fa.n3 + 255) / 256);
+    if (E || W || G || nfb > 0) {
+        timing_begin(h, 0);
+        hipLaunchKernelGGL((finalize_kernel<T>), dim3(ncol + nfb), dim3(256), 0, h->stream, fa);
+        timing_end(h, 0);
+        if (hipGetLastError() != hipSuccess) {
+            h->facc_dirty = 1;
+            return POD_EHIP;
+        }
     }
     return POD_OK;
 }
@@ -652,13 +986,25 @@ int pod_descriptors(pod_handle* h, int N, int P, const void* pos, const double* 
 }
 
 int pod_energy_forces(pod_handle* h, int N, int P, const void* pos, const double* cell, const int* offsets,
-                      const int* nbr_j, const int* shift, const void* c, void* E_atom, double* E, void* F,
-                      double* W, double* G) {
+                      const int* nbr_j, const int* shift, const int* rev, const void* c, void* E_atom, double* E,
+                      void* F, double* W, double* G) {
     if (pod::bad_common(h, N, P, pos, offsets, nbr_j, shift)) return POD_EINVAL;
     if (!c) return POD_EINVAL;
     if (h->dtype == POD_F64)
-        return pod::energy_forces_impl<double>(h, N, P, pos, cell, offsets, nbr_j, shift, c, E_atom, E, F, W, G);
-    return pod::energy_forces_impl<float>(h, N, P, pos, cell, offsets, nbr_j, shift, c, E_atom, E, F, W, G);
+        return pod::energy_forces_impl<double>(h, N, P, pos, cell, offsets, nbr_j, shift, rev, c, E_atom, E, F, W,
+                                               G);
+    return pod::energy_forces_impl<float>(h, N, P, pos, cell, offsets, nbr_j, shift, rev, c, E_atom, E, F, W, G);
+}
+
+int pod_neighbor_reverse(pod_handle* h, int N, int P, const int* offsets, const int* nbr_j, const int* shift,
+                         int* rev) {
+    if (!h || N < 0 || P < 0) return POD_EINVAL;
+    if (N > 0 && !offsets) return POD_EINVAL;
+    if (P > 0 && (!nbr_j || !shift || !rev)) return POD_EINVAL;
+    if (N == 0) return POD_OK;
+    hipLaunchKernelGGL(pod::reverse_kernel, dim3((N + 7) / 8), dim3(256), 0, h->stream, offsets, nbr_j, shift, N, P,
+                       rev, h->d_err);
+    return hipGetLastError() == hipSuccess ? POD_OK : POD_EHIP;
 }
 
 }  // extern "C"

@@ -69,16 +69,18 @@ def lib():
     L.pod_num_descriptors.argtypes = [_vp, P(i), P(i)]
     L.pod_get_basis.argtypes = [_vp, _dp, _dp]
     L.pod_descriptors.argtypes = [_vp, i, i, _vp, _dp, _vp, _vp, _vp, _vp]
-    L.pod_energy_forces.argtypes = [_vp, i, i, _vp, _dp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+    L.pod_energy_forces.argtypes = [_vp, i, i, _vp, _dp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+    L.pod_neighbor_reverse.argtypes = [_vp, i, i, _vp, _vp, _vp, _vp]
     L.pod_check.argtypes = [_vp]
     L.pod_set_kernel_timing.argtypes = [_vp, i]
-    L.pod_get_kernel_time.argtypes = [_vp, _dp, P(i)]
+    L.pod_get_kernel_time.argtypes = [_vp, i, _dp, P(i)]
     L.pod_strerror.argtypes = [i]
     L.pod_strerror.restype = ctypes.c_char_p
     L.pod_free.argtypes = [_vp]
     L.pod_free.restype = None
     for name in ("pod_init", "pod_compute_basis", "pod_num_descriptors", "pod_get_basis", "pod_descriptors",
-                 "pod_energy_forces", "pod_check", "pod_set_kernel_timing", "pod_get_kernel_time"):
+                 "pod_energy_forces", "pod_check", "pod_set_kernel_timing", "pod_get_kernel_time",
+                 "pod_neighbor_reverse"):
         getattr(L, name).restype = i
     _lib = L
     return L
@@ -197,11 +199,17 @@ def pod_descriptors(h: Handle, N, P, pos, cell, offsets, nbr_j, shift, D):
                               _ptr(D)), "pod_descriptors")
 
 
+def pod_neighbor_reverse(h: Handle, N, P, offsets, nbr_j, shift, rev):
+    _ok(lib().pod_neighbor_reverse(h.ptr, int(N), int(P), _ptr(offsets), _ptr(nbr_j), _ptr(shift), _ptr(rev)),
+        "pod_neighbor_reverse")
+
+
 def pod_energy_forces(h: Handle, N, P, pos, cell, offsets, nbr_j, shift, c, E_atom=None, E=None, F=None, W=None,
-                      G=None):
+                      G=None, rev=None):
     arr, cp = _cell_ptr(cell)
     _ok(lib().pod_energy_forces(h.ptr, int(N), int(P), _ptr(pos), cp, _ptr(offsets), _ptr(nbr_j), _ptr(shift),
-                                _ptr(c), _ptr(E_atom), _ptr(E), _ptr(F), _ptr(W), _ptr(G)), "pod_energy_forces")
+                                _ptr(rev), _ptr(c), _ptr(E_atom), _ptr(E), _ptr(F), _ptr(W), _ptr(G)),
+        "pod_energy_forces")
 
 
 def pod_check(h: Handle):
@@ -212,10 +220,11 @@ def pod_set_kernel_timing(h: Handle, n: int):
     _ok(lib().pod_set_kernel_timing(h.ptr, int(n)), "pod_set_kernel_timing")
 
 
-def pod_get_kernel_time(h: Handle):
+def pod_get_kernel_time(h: Handle, kind: int = 1):
+    """(total ms, launches) of kernel `kind` (0 pair stage, 1 per-atom kernel)."""
     ms = ctypes.c_double()
     n = ctypes.c_int()
-    _ok(lib().pod_get_kernel_time(h.ptr, ctypes.byref(ms), ctypes.byref(n)), "pod_get_kernel_time")
+    _ok(lib().pod_get_kernel_time(h.ptr, int(kind), ctypes.byref(ms), ctypes.byref(n)), "pod_get_kernel_time")
     return ms.value, n.value
 
 
@@ -238,6 +247,16 @@ class DeviceNeighbors:
         self.shift = torch.as_tensor(np.asarray(shift, dtype=np.int32), device=device)
         self.N = int(self.offsets.numel()) - 1
         self.P = int(self.nbr_j.numel())
+        self.rev = None
+
+    def build_reverse(self, model: "PodModel", check=True):
+        """Reverse-pair index on the device (once per list)."""
+        import torch
+        self.rev = torch.empty(max(self.P, 1), dtype=torch.int32, device=self.offsets.device)
+        pod_neighbor_reverse(model.h, self.N, self.P, self.offsets, self.nbr_j, self.shift, self.rev)
+        if check:
+            pod_check(model.h)
+        return self.rev
 
     @classmethod
     def from_list(cls, nl, device="cuda"):
@@ -287,7 +306,7 @@ class PodModel:
             "G": torch.empty(self.M, dtype=torch.float64, device=self.device) if global_desc else None,
         }
         pod_energy_forces(self.h, N, nbrs.P, pos, cell, nbrs.offsets, nbrs.nbr_j, nbrs.shift, c,
-                          o["E_atom"], o["E"], o["F"], o["W"], o["G"])
+                          o["E_atom"], o["E"], o["F"], o["W"], o["G"], rev=nbrs.rev)
         if check:
             pod_check(self.h)
         return o

@@ -81,7 +81,9 @@ class Case:
         return pod.PodModel(lib_setup(self.setup), dtype, Q=self.Q[:, : self.K])
 
     def run(self, dtype, pos=None):
-        """Descriptors and energy/forces from the GPU, as float64 numpy."""
+        """Descriptors and energy/forces from the GPU, as float64 numpy.  Forces
+        are taken on both force paths: atomics ("F") and the reverse-index
+        gather ("F_gather"); the gather path's E, W, G must agree too."""
         import torch
         pos = self.pos if pos is None else pos
         m = self.model(dtype)
@@ -92,7 +94,24 @@ class Case:
         res = {"D": D.double().cpu().numpy(), "E": float(o["E"].item()),
                "E_atom": o["E_atom"].double().cpu().numpy(), "F": o["F"].double().cpu().numpy(),
                "W": o["W"].cpu().numpy(), "G": o["G"].cpu().numpy()}
+        nb.build_reverse(m)
+        o2 = m.energy_forces(pos, self.cell, nb, self.c)
+        torch.cuda.synchronize()
+        res["F_gather"] = o2["F"].double().cpu().numpy()
+        res["E_gather"] = float(o2["E"].item())
+        res["W_gather"] = o2["W"].cpu().numpy()
+        res["rev"] = nb.rev[: nb.P].cpu().numpy()
         return res
+
+
+def reverse_index(nl):
+    """Host reference of the reverse-pair index (dictionary lookup)."""
+    N = len(nl.offsets) - 1
+    centre = np.repeat(np.arange(N), np.diff(nl.offsets))
+    key = {(int(i), int(j), int(a), int(b), int(c)): p
+           for p, (i, j, (a, b, c)) in enumerate(zip(centre, nl.nbr_j, nl.shift3))}
+    return np.array([key[(int(j), int(i), -int(a), -int(b), -int(c))]
+                     for i, j, (a, b, c) in zip(centre, nl.nbr_j, nl.shift3)], dtype=np.int64)
 
 
 def positions_for(dtype, pos):

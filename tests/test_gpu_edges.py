@@ -142,6 +142,34 @@ def test_invalid_arguments_rejected_on_host():
                                                         torch.zeros((2, m.M), dtype=torch.float64, device="cuda")))
 
 
+def test_gather_forces_are_bitwise_reproducible():
+    pos, cell = _small()
+    nl = wl.neighbor_list(pos, cell, S.rcut)
+    m = _model()
+    nb = pod.DeviceNeighbors.from_list(nl)
+    nb.build_reverse(m)
+    c = wl.coefficients(S.M, 3)
+    a = m.energy_forces(pos, cell, nb, c)["F"].cpu().numpy()
+    b = m.energy_forces(pos, cell, nb, c)["F"].cpu().numpy()
+    assert np.array_equal(a, b)
+
+
+def test_reverse_index_reports_missing_pair():
+    pos, cell = _small()
+    nl = wl.neighbor_list(pos, cell, S.rcut)
+    m = _model()
+    # drop the last pair of atom 0: its reverse in the partner's list is orphaned
+    off = nl.offsets.copy()
+    keep = np.ones(nl.n_pairs, dtype=bool)
+    keep[off[1] - 1] = False
+    off[1:] -= 1
+    nb = pod.DeviceNeighbors(off, nl.nbr_j[keep], nl.shift[keep])
+    say("[gpu] edge: reverse index with a missing pair")
+    with pytest.raises(pod.PodError) as ei:
+        nb.build_reverse(m)
+    assert pod.ERRORS[ei.value.code] == "POD_ENEIGH"
+
+
 def test_repeat_calls_agree():
     pos, cell = _small()
     nl = wl.neighbor_list(pos, cell, S.rcut)

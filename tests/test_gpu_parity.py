@@ -8,7 +8,7 @@ Tolerances (normwise relative, max-abs error over max-abs reference):
 import numpy as np
 import pytest
 
-from gpu_common import Case, colerr, oracle_params, positions_for, relerr, say
+from gpu_common import Case, colerr, oracle_params, positions_for, relerr, reverse_index, say
 from oracle import pod_oracle as po
 from paper_2212_14446_amd import pod, workloads as wl
 
@@ -33,9 +33,12 @@ def _compare(case, dtype, full=True):
         "E": abs(got["E"] - o["E"]) / max(abs(o["E"]), 1e-300),
         "E_atom": relerr(got["E_atom"], o["E_atom"]),
         "F": relerr(got["F"], o["F"]),
+        "F_gather": relerr(got["F_gather"], o["F"]),
         "W": relerr(got["W"], o["W"]),
+        "W_gather": relerr(got["W_gather"], o["W"]),
         "G": relerr(got["G"], o["G"]),
     }
+    assert np.array_equal(got["rev"], reverse_index(case.nl))
     say(f"[gpu]   errors {dtype}: " + " ".join(f"{k}={v:.3e}" for k, v in errs.items()))
     return errs
 
@@ -47,8 +50,8 @@ def _assert64(errs):
 
 def _assert32(errs):
     assert errs["E"] < 2e-5 and errs["E_atom"] < 2e-5, errs
-    assert errs["F"] < 1e-4, errs
-    assert errs["W"] < 1e-4 and errs["G"] < 1e-4, errs
+    assert errs["F"] < 1e-4 and errs["F_gather"] < 1e-4, errs
+    assert errs["W"] < 1e-4 and errs["W_gather"] < 1e-4 and errs["G"] < 1e-4, errs
     assert errs["D"] < 1e-3, errs
 
 

@@ -4,7 +4,7 @@ the oracle, in the launch configuration the benchmark times."""
 import numpy as np
 import pytest
 
-from gpu_common import Case, colerr, positions_for, relerr, say
+from gpu_common import Case, colerr, positions_for, relerr, reverse_index, say
 from paper_2212_14446_amd import workloads as wl
 
 pytestmark = pytest.mark.gpu
@@ -26,10 +26,12 @@ def test_cfg2_f64_full(cfg2, cfg2_ref):
     got = cfg2.run("f64")
     errs = {"D": colerr(got["D"], D_ref), "E": abs(got["E"] - o["E"]) / abs(o["E"]),
             "E_atom": relerr(got["E_atom"], o["E_atom"]), "F": relerr(got["F"], o["F"]),
-            "W": relerr(got["W"], o["W"]), "G": relerr(got["G"], o["G"])}
+            "F_gather": relerr(got["F_gather"], o["F"]), "W": relerr(got["W"], o["W"]),
+            "W_gather": relerr(got["W_gather"], o["W"]), "G": relerr(got["G"], o["G"])}
     say("[gpu]   " + " ".join(f"{k}={v:.3e}" for k, v in errs.items()))
     for k, v in errs.items():
         assert v < 1e-10, (k, v)
+    assert np.array_equal(got["rev"], reverse_index(cfg2.nl))
 
 
 def test_cfg2_f32_full(cfg2):
@@ -42,7 +44,8 @@ def test_cfg2_f32_full(cfg2):
     o = case.oracle_ef()
     errs = {"D": colerr(got["D"], D_ref), "E": abs(got["E"] - o["E"]) / abs(o["E"]),
             "E_atom": relerr(got["E_atom"], o["E_atom"]), "F": relerr(got["F"], o["F"]),
-            "W": relerr(got["W"], o["W"]), "G": relerr(got["G"], o["G"])}
+            "F_gather": relerr(got["F_gather"], o["F"]), "W": relerr(got["W"], o["W"]),
+            "G": relerr(got["G"], o["G"])}
     say("[gpu]   " + " ".join(f"{k}={v:.3e}" for k, v in errs.items()))
     assert errs["E"] < 2e-5 and errs["E_atom"] < 2e-5
-    assert errs["F"] < 1e-4
+    assert errs["F"] < 1e-4 and errs["F_gather"] < 1e-4
