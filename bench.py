@@ -41,17 +41,21 @@ def kernel_hash():
 
 
 def committed_traffic(dtype):
-    """HBM traffic per launch from the committed counter summary, if it was
-    taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", "traffic_atom_kernel_bcc20_15840.json")
+    """HBM bytes per launch of the per-atom kernel from the committed counter
+    summary, if it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic_atom_kernel_bcc20_15840.md")
     if not os.path.exists(path):
         return None
+    vals = {}
     with open(path) as f:
-        t = json.load(f)
-    if t.get("kernel_hash") != kernel_hash():
+        for line in f:
+            if ":" in line and not line.startswith(("|", "#", " ")):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("kernel_hash") != kernel_hash():
         return None
-    rec = t.get(dtype)
-    return None if rec is None else rec.get("bytes_per_launch")
+    v = vals.get(f"{dtype}_bytes_per_launch")
+    return None if v is None else int(v)
 
 
 def run_gpu(w, dtype, steps, warmup):
