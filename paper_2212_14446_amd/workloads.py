@@ -276,3 +276,33 @@ def small_bcc(n: int = 2, sigma: float = 0.1, seed: int = 11, setup: PodSetup = 
     pos = displace(pos, sigma, seed)
     nl = neighbor_list(pos, cell, setup.rcut)
     return Workload(f"bcc{n}_s{sigma}", pos, cell, nl, setup, coefficients(setup.M, seed + 1))
+
+
+def config4() -> Workload:
+    """54,000-atom BCC box (30^3 cells), sigma 0.2, 2/3/4-body (FP32 path),
+    coefficients set per body order from descriptor statistics by
+    ``standardised_coefficients``."""
+    pos, cell = config4_positions()
+    s = PodSetup(rin=0.5, rcut=5.0, L=8, K2=6, K3=6, K4=6, P3=4, P4=4)
+    nl = neighbor_list(pos, cell, s.rcut)
+    return Workload("bcc30_54000_s0.2", pos, cell, nl, s, np.zeros(s.M))
+
+
+def standardised_coefficients(D, setup: PodSetup, seed: int, targets=(1.0, 0.3, 0.1)):
+    """Coefficients c_m = z_m s_b / (sigma_m sqrt(n_b)) with z ~ N(0, 1),
+    sigma_m the standard deviation of descriptor m over the rows of D and
+    n_b the size of its body-order block, so that the per-atom energy of the
+    2-, 3- and 4-body blocks has a spread of about s_b = targets (eV)."""
+    rng = np.random.default_rng(seed)
+    M = D.shape[1]
+    c = np.zeros(M)
+    sig = D.std(axis=0)
+    sig[sig == 0] = 1.0
+    m2 = setup.K2
+    m3 = setup.K3 * (setup.P3 + 1) if setup.K3 else 0
+    blocks = [(1, 1 + m2), (1 + m2, 1 + m2 + m3), (1 + m2 + m3, M)]
+    for (lo, hi), s in zip(blocks, targets):
+        if hi > lo:
+            z = rng.normal(size=hi - lo)
+            c[lo:hi] = z * s / (sig[lo:hi] * np.sqrt(hi - lo))
+    return c
