@@ -136,6 +136,42 @@ int pod_energy_forces(pod_handle* h, int N, int P, const void* pos, const double
                       const int* offsets, const int* nbr_j, const int* shift, const int* rev,
                       const void* c, void* E_atom, double* E, void* F, double* W, double* G);
 
+/* Batched descriptor-matrix assembly for fitting (Sec. IV.A, eqs. (58a),
+ * (63a)): many independent periodic cells in one persistent launch, FP64
+ * handles only (POD_ENOTSUP otherwise).
+ *   n_cfg        : number of cells; N, P: total atoms and pairs over all cells
+ *   cfg_atom_off : n_cfg + 1 ints (device); cell c owns atoms
+ *                  [cfg_atom_off[c], cfg_atom_off[c+1]), cfg_atom_off[0] = 0,
+ *                  cfg_atom_off[n_cfg] = N
+ *   pos          : N x 3 doubles (device), all cells stacked
+ *   cells        : n_cfg x 9 doubles (DEVICE), lattice vectors as rows
+ *   offsets, nbr_j, shift : one CSR list over the N stacked atoms as for the
+ *                  single-system calls; nbr_j holds stacked indices, and every
+ *                  neighbour of an atom of cell c must lie in cell c (else
+ *                  POD_ENEIGH is latched and the pair skipped)
+ *   D            : N x M per-atom descriptors (device) or NULL
+ *   G            : n_cfg x M global descriptors G_c = sum_{i in c} D_i
+ *                  (device) or NULL
+ *   dGdR         : 3N x M (device) or NULL; row 3n + d, column k holds
+ *                  dG_{c,k}/dr_{n,d} for the cell c that owns atom n, i.e. each
+ *                  cell's (3 N_c) x M block of derivatives, stacked.
+ *   tune         : launch shape (see pod_tune) or NULL for the defaults.
+ * The library plans on the host from offsets and cfg_atom_off (a blocking
+ * device-to-host copy of both), so the call returns after the plan, with the
+ * kernel queued on the handle's stream.  A cell with more atoms than the
+ * LDS accumulator holds (the limit depends on M and the tune) gives
+ * POD_ENOTSUP.  Scratch grows in the handle (POD_ENOMEM on failure). */
+typedef struct pod_tune {
+    int cw;       /* descriptor columns per dG/dR chunk (0 = default 6) */
+    int ag;       /* atoms per Jacobian group (0 = default 8) */
+    int nblocks;  /* persistent workgroups (0 = default 512, capped at n_cfg) */
+} pod_tune;
+
+int pod_batch_assemble(pod_handle* h, int n_cfg, int N, int P, const int* cfg_atom_off,
+                       const void* pos, const double* cells, const int* offsets,
+                       const int* nbr_j, const int* shift, double* D, double* G,
+                       double* dGdR, const pod_tune* tune);
+
 /* Diagnostics.  pod_set_kernel_timing(h, n) with n > 0 makes the next n
  * compute calls record pairs of HIP events on the handle's stream around each
  * of their kernels (n = 0 switches recording off).  pod_get_kernel_time waits

@@ -26,240 +26,14 @@
 #include <cstdint>
 
 #include "pod.h"
+#include "pod_device.h"
 #include "pod_internal.h"
 #include "pod_tables.h"
 
 namespace pod {
 namespace {
 
-template <typename T> __device__ __forceinline__ T d_exp(T x);
-template <> __device__ __forceinline__ double d_exp(double x) { return exp(x); }
-template <> __device__ __forceinline__ float d_exp(float x) { return expf(x); }
-template <typename T> __device__ __forceinline__ T d_expm1(T x);
-template <> __device__ __forceinline__ double d_expm1(double x) { return expm1(x); }
-template <> __device__ __forceinline__ float d_expm1(float x) { return expm1f(x); }
-template <typename T> __device__ __forceinline__ T d_log(T x);
-template <> __device__ __forceinline__ double d_log(double x) { return log(x); }
-template <> __device__ __forceinline__ float d_log(float x) { return logf(x); }
-template <typename T> __device__ __forceinline__ T d_sqrt(T x);
-template <> __device__ __forceinline__ double d_sqrt(double x) { return sqrt(x); }
-template <> __device__ __forceinline__ float d_sqrt(float x) { return sqrtf(x); }
-template <typename T> __device__ __forceinline__ T d_rsqrt(T x);
-template <> __device__ __forceinline__ double d_rsqrt(double x) { return rsqrt(x); }
-template <> __device__ __forceinline__ float d_rsqrt(float x) { return rsqrtf(x); }
-template <typename T> __device__ __forceinline__ void d_sincos(T x, T* s, T* c);
-template <> __device__ __forceinline__ void d_sincos(double x, double* s, double* c) { sincos(x, s, c); }
-template <> __device__ __forceinline__ void d_sincos(float x, float* s, float* c) { sincosf(x, s, c); }
-template <typename T> __device__ __forceinline__ bool d_finite(T x) { return isfinite(x); }
-
-__device__ __forceinline__ int wave_max(int v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o));
-    return v;
-}
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
-    return v;
-}
-
-__device__ __forceinline__ int unpack_shift(int sh, int d) {
-    return static_cast<int>(static_cast<int8_t>((sh >> (8 * d)) & 0xFF));
-}
-
-// Radial functions R_k(r) = sum_l Q_lk Phi_l(r) and (DERIV) R'_k(r) for k <
-// POD_MAX_K (Sec. II.B, eqs. (3)-(8), (11), (12)).  Q is zero beyond K.
-template <typename T, bool DERIV>
-__device__ __forceinline__ void radial(const ParamsT<T>* __restrict__ P, T r, T rinv,
-                                       T (&R)[POD_MAX_K], T (&dR)[POD_MAX_K]) {
-    const T inv_h = P->inv_h;
-    const T dist = r - P->rin;
-    const T t = dist * inv_h;
-    const T t2 = t * t;
-    const T y = T(1) - t2 * t;
-    const T s = y * y + T(1e-6);
-    const T rs = d_rsqrt(s);
-    const T fc = d_exp(T(1) - rs);
-    const T dfc = DERIV ? fc * y * (rs * rs * rs) * (T(-3) * t2 * inv_h) : T(0);
-    const T idist = T(1) / dist;
-    constexpr T kPi = T(3.14159265358979323846);
-    T x = 0, dx = 0, s1 = 0, c1 = 1, sk = 0, ck = 1;
-#pragma unroll
-    for (int k = 0; k < POD_MAX_K; ++k) { R[k] = 0; dR[k] = 0; }
-    const int L = P->L;
-    for (int l = 0; l < L; ++l) {
-        const SnapT<T>& sn = P->s[l];
-        T psi = 0, dpsi = 0;
-        if (sn.bessel) {
-            if (sn.newbeta) {
-                if (sn.bh == T(0)) {
-                    x = t; dx = inv_h;
-                } else {
-                    const T em = d_expm1(-sn.bh * dist);
-                    x = em * sn.inv_em1;
-                    dx = -sn.bh * (em + T(1)) * sn.inv_em1;
-                }
-                d_sincos(kPi * x, &s1, &c1);
-                sk = 0; ck = 1;
-            }
-            T sa, ca;
-            if (sn.steps >= 0) {
-                for (int q = 0; q < sn.steps; ++q) {
-                    const T ns = sk * c1 + ck * s1;
-                    const T nc = ck * c1 - sk * s1;
-                    sk = ns; ck = nc;
-                }
-                sa = sk; ca = ck;
-            } else {
-                d_sincos(sn.apix * x, &sa, &ca);
-            }
-            const T phi = sa * idist;
-            psi = sn.kappa * phi;
-            if (DERIV) dpsi = sn.kappa * (sn.apix * ca * dx - phi) * idist;
-        }
-        if (sn.power) {
-            T v;
-            if (sn.power == 1) {
-                v = rinv;
-                for (int q = 1; q < sn.igamma; ++q) v *= rinv;
-            } else {
-                v = d_exp(-sn.gamma * d_log(r));
-            }
-            const T w = T(1) - sn.kappa;
-            psi += w * v;
-            if (DERIV) dpsi -= w * sn.gamma * v * rinv;
-        }
-        const T ph = fc * psi;
-        const T dph = DERIV ? dfc * psi + fc * dpsi : T(0);
-#pragma unroll
-        for (int k = 0; k < POD_MAX_K; ++k) {
-            const T qlk = P->Q[l][k];
-            R[k] += qlk * ph;
-            if (DERIV) dR[k] += qlk * dph;
-        }
-    }
-}
-
-
-// sin(pi x) and cos(pi x) for -0.25 <= x <= 1.25 (here x is the scaled
-// distance, in [0, 1]).  Quadrant reduction t = x - k/2 with k = rint(2x) is
-// exact (Sterbenz); sin and cos of theta = pi t, |theta| <= pi/4, come from
-// their Taylor series (terms to theta^17 / theta^18 in double, theta^9 /
-// theta^10 in float: truncation below half an ulp).
-template <typename T>
-__device__ __forceinline__ void sincospi_unit(T x, T* sp, T* cp) {
-    const T k = rint(T(2) * x);
-    const T t = x - T(0.5) * k;
-    const T th = T(3.14159265358979323846) * t;
-    const T z = th * th;
-    T sn, cs;
-    if constexpr (sizeof(T) == 8) {
-        T ps = T(1.0 / 355687428096000.0);                      //  1/17!
-        ps = ps * z - T(1.0 / 1307674368000.0);                 // -1/15!
-        ps = ps * z + T(1.0 / 6227020800.0);                    //  1/13!
-        ps = ps * z - T(1.0 / 39916800.0);                      // -1/11!
-        ps = ps * z + T(1.0 / 362880.0);                        //  1/9!
-        ps = ps * z - T(1.0 / 5040.0);                          // -1/7!
-        ps = ps * z + T(1.0 / 120.0);                           //  1/5!
-        ps = ps * z - T(1.0 / 6.0);                             // -1/3!
-        T pc = -T(1.0 / 6402373705728000.0);                    // -1/18!
-        pc = pc * z + T(1.0 / 20922789888000.0);                //  1/16!
-        pc = pc * z - T(1.0 / 87178291200.0);                   // -1/14!
-        pc = pc * z + T(1.0 / 479001600.0);                     //  1/12!
-        pc = pc * z - T(1.0 / 3628800.0);                       // -1/10!
-        pc = pc * z + T(1.0 / 40320.0);                         //  1/8!
-        pc = pc * z - T(1.0 / 720.0);                           // -1/6!
-        pc = pc * z + T(1.0 / 24.0);                            //  1/4!
-        pc = pc * z - T(0.5);                                   // -1/2!
-        sn = th + th * z * ps;
-        cs = T(1) + z * pc;
-    } else {
-        T ps = T(1.0 / 362880.0);                               //  1/9!
-        ps = ps * z - T(1.0 / 5040.0);                          // -1/7!
-        ps = ps * z + T(1.0 / 120.0);                           //  1/5!
-        ps = ps * z - T(1.0 / 6.0);                             // -1/3!
-        T pc = -T(1.0 / 3628800.0);                             // -1/10!
-        pc = pc * z + T(1.0 / 40320.0);                         //  1/8!
-        pc = pc * z - T(1.0 / 720.0);                           // -1/6!
-        pc = pc * z + T(1.0 / 24.0);                            //  1/4!
-        pc = pc * z - T(0.5);                                   // -1/2!
-        sn = th + th * z * ps;
-        cs = T(1) + z * pc;
-    }
-    // rotate by k quarter turns
-    const int q = static_cast<int>(k) & 3;
-    T so = sn, co = cs;
-    if (q == 1) { so = cs; co = -sn; }
-    else if (q == 2) { so = -sn; co = -cs; }
-    else if (q == 3) { so = -cs; co = sn; }
-    *sp = so;
-    *cp = co;
-}
-
-// Radial functions for the standard snapshot family (Bessel alpha = 1..nb at
-// one beta, inverse powers gamma = 1..ni): one expm1, one sincos and one exp
-// per pair; sin/cos(alpha pi x) by angle addition; Q read from LDS.
-template <typename T, bool DERIV>
-__device__ __forceinline__ void radial_std(const ParamsT<T>* __restrict__ P, const T* __restrict__ sQ, T r,
-                                           T rinv, T (&R)[POD_MAX_K], T (&dR)[POD_MAX_K]) {
-    const T inv_h = P->inv_h;
-    const T dist = r - P->rin;
-    const T t = dist * inv_h;
-    const T t2 = t * t;
-    const T y = T(1) - t2 * t;
-    const T s = y * y + T(1e-6);
-    const T rs = d_rsqrt(s);
-    const T fc = d_exp(T(1) - rs);
-    const T dfc = DERIV ? fc * y * (rs * rs * rs) * (T(-3) * t2 * inv_h) : T(0);
-    const T idist = T(1) / dist;
-    constexpr T kPi = T(3.14159265358979323846);
-#pragma unroll
-    for (int k = 0; k < POD_MAX_K; ++k) { R[k] = 0; dR[k] = 0; }
-    const int nb = P->std_nb, ni = P->std_ni;
-    if (nb > 0) {
-        T x, dx;
-        const T bh = P->std_bh;
-        if (bh == T(0)) {
-            x = t; dx = inv_h;
-        } else {
-            const T em = d_expm1(-bh * dist);
-            x = em * P->std_inv_em1;
-            dx = -bh * (em + T(1)) * P->std_inv_em1;
-        }
-        T s1, c1;
-        sincospi_unit(x, &s1, &c1);
-        const T fci = fc * idist;
-        const T dfci = DERIV ? dfc * idist : T(0);
-        const T pdx = kPi * dx;
-        T sk = 0, ck = 1;
-        for (int l = 0; l < nb; ++l) {
-            const T ns = sk * c1 + ck * s1;
-            const T nc = ck * c1 - sk * s1;
-            sk = ns; ck = nc;
-            // Phi = f_c sin/(r - rin); Phi' = f_c' sin/(r-rin) + f_c (alpha pi cos dx - sin/(r-rin))/(r-rin)
-            const T ph = fci * sk;
-            const T dph = DERIV ? dfci * sk + fci * (T(l + 1) * pdx * ck - sk * idist) : T(0);
-            const T* q = sQ + l * POD_MAX_K;
-#pragma unroll
-            for (int k = 0; k < POD_MAX_K; ++k) {
-                R[k] += q[k] * ph;
-                if (DERIV) dR[k] += q[k] * dph;
-            }
-        }
-    }
-    T pw = T(1);
-    for (int g = 1; g <= ni; ++g) {
-        pw *= rinv;                                  // r^-g
-        const T ph = fc * pw;
-        const T dph = DERIV ? (dfc - T(g) * fc * rinv) * pw : T(0);
-        const T* q = sQ + (nb + g - 1) * POD_MAX_K;
-#pragma unroll
-        for (int k = 0; k < POD_MAX_K; ++k) {
-            R[k] += q[k] * ph;
-            if (DERIV) dR[k] += q[k] * dph;
-        }
-    }
-}
+using namespace dev;
 
 template <typename T>
 struct KArgs {
@@ -280,21 +54,6 @@ struct KArgs {
     int want_back;     // run the backward sweep (forces or virial requested)
     int* err;
 };
-
-template <typename T, int PA>
-__device__ __forceinline__ void accumulate_basis(T (&acc)[n_mono(PA)], T Rm, T ux, T uy, T uz) {
-    constexpr MonoTable<PA> mt{};
-    constexpr int NA = n_mono(PA);
-    T A[NA];
-    A[0] = Rm;
-    acc[0] += Rm;
-#pragma unroll
-    for (int mu = 1; mu < NA; ++mu) {
-        const T u = mt.axis[mu] == 0 ? ux : (mt.axis[mu] == 1 ? uy : uz);
-        A[mu] = A[mt.par[mu]] * u;
-        acc[mu] += A[mu];
-    }
-}
 
 // Neighbour slots are fetched two rounds ahead: the index and image shift of
 // round r + 2 and the neighbour position of round r + 1 are requested before

@@ -78,9 +78,10 @@ template <int PA>
 struct D4Build {
     int KA;
     int pa[64], pb[64], pc[64];   // (a, b, c) of each p, Table 1 order
+    int tbeg[64], tend[64];       // merged terms of p: [tbeg[p], tend[p])
     int nt;
     int tp[D4_CAP], tx[D4_CAP], ty[D4_CAP], tz[D4_CAP], tc[D4_CAP];
-    constexpr D4Build() : KA(0), pa{}, pb{}, pc{}, nt(0), tp{}, tx{}, ty{}, tz{}, tc{} {
+    constexpr D4Build() : KA(0), pa{}, pb{}, pc{}, tbeg{}, tend{}, nt(0), tp{}, tx{}, ty{}, tz{}, tc{} {
         for (int n = 0; n <= PA; ++n)
             for (int a = n; a >= 0; --a)
                 for (int b = (a < n - a ? a : n - a); b >= 0; --b) {
@@ -88,6 +89,7 @@ struct D4Build {
                     if (c < 0 || c > b) continue;
                     const int p = KA++;
                     pa[p] = a; pb[p] = b; pc[p] = c;
+                    tbeg[p] = nt; tend[p] = nt;
                     if (b == 0 && c == 0) continue;      // eq. (27a)
                     const int first = nt;
                     // monomials of degree a, b, c: (x1, y1, z1) etc.
@@ -123,6 +125,7 @@ struct D4Build {
                                         }
                                 }
                         }
+                    tend[p] = nt;
                 }
     }
 };

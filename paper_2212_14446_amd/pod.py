@@ -40,6 +40,10 @@ class PodParamsC(ctypes.Structure):
     ]
 
 
+class PodTuneC(ctypes.Structure):
+    _fields_ = [("cw", ctypes.c_int), ("ag", ctypes.c_int), ("nblocks", ctypes.c_int)]
+
+
 class PodError(RuntimeError):
     def __init__(self, code: int, where: str = ""):
         self.code = code
@@ -71,6 +75,7 @@ def lib():
     L.pod_descriptors.argtypes = [_vp, i, i, _vp, _dp, _vp, _vp, _vp, _vp]
     L.pod_energy_forces.argtypes = [_vp, i, i, _vp, _dp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
     L.pod_neighbor_reverse.argtypes = [_vp, i, i, _vp, _vp, _vp, _vp]
+    L.pod_batch_assemble.argtypes = [_vp, i, i, i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, P(PodTuneC)]
     L.pod_check.argtypes = [_vp]
     L.pod_set_kernel_timing.argtypes = [_vp, i]
     L.pod_get_kernel_time.argtypes = [_vp, i, _dp, P(i)]
@@ -80,7 +85,7 @@ def lib():
     L.pod_free.restype = None
     for name in ("pod_init", "pod_compute_basis", "pod_num_descriptors", "pod_get_basis", "pod_descriptors",
                  "pod_energy_forces", "pod_check", "pod_set_kernel_timing", "pod_get_kernel_time",
-                 "pod_neighbor_reverse"):
+                 "pod_neighbor_reverse", "pod_batch_assemble"):
         getattr(L, name).restype = i
     _lib = L
     return L
@@ -212,6 +217,17 @@ def pod_energy_forces(h: Handle, N, P, pos, cell, offsets, nbr_j, shift, c, E_at
         "pod_energy_forces")
 
 
+def pod_batch_assemble(h: Handle, n_cfg, N, P, cfg_atom_off, pos, cells, offsets, nbr_j, shift, D=None, G=None,
+                       dGdR=None, tune=None):
+    """tune: None (library defaults) or a (cw, ag, nblocks) triple."""
+    t = None
+    if tune is not None:
+        t = ctypes.byref(PodTuneC(int(tune[0]), int(tune[1]), int(tune[2])))
+    _ok(lib().pod_batch_assemble(h.ptr, int(n_cfg), int(N), int(P), _ptr(cfg_atom_off), _ptr(pos), _ptr(cells),
+                                 _ptr(offsets), _ptr(nbr_j), _ptr(shift), _ptr(D), _ptr(G), _ptr(dGdR), t),
+        "pod_batch_assemble")
+
+
 def pod_check(h: Handle):
     _ok(lib().pod_check(h.ptr), "pod_check")
 
@@ -313,6 +329,44 @@ class PodModel:
 
     def check(self):
         pod_check(self.h)
+
+
+class DeviceBatch:
+    """Many cells stacked for pod_batch_assemble: atom offsets per cell, the
+    stacked positions, the cells (n_cfg x 3 x 3) and one stacked CSR list."""
+
+    def __init__(self, cfg_atom_off, pos, cells, offsets, nbr_j, shift, device="cuda"):
+        import torch
+        self.cfg_atom_off = torch.as_tensor(np.asarray(cfg_atom_off, dtype=np.int32), device=device)
+        self.pos = torch.as_tensor(np.asarray(pos, dtype=np.float64), device=device).contiguous()
+        self.cells = torch.as_tensor(np.asarray(cells, dtype=np.float64).reshape(-1, 9), device=device).contiguous()
+        self.nbrs = DeviceNeighbors(offsets, nbr_j, shift, device)
+        self.n_cfg = int(self.cfg_atom_off.numel()) - 1
+        self.N = self.nbrs.N
+        self.P = self.nbrs.P
+
+    @classmethod
+    def from_batch(cls, b, device="cuda"):
+        """From a workloads.Batch."""
+        return cls(b.cfg_atom_off, b.pos, b.cells, b.nl.offsets, b.nl.nbr_j, b.nl.shift, device)
+
+
+def batch_assemble(model: PodModel, batch: DeviceBatch, D=True, G=True, dGdR=True, tune=None, check=True,
+                   out=None):
+    """D (N x M), G (n_cfg x M) and dG/dR (3N x M) of every cell, FP64."""
+    import torch
+    dev, M = model.device, model.M
+    o = out if out is not None else {
+        "D": torch.empty((batch.N, M), dtype=torch.float64, device=dev) if D else None,
+        "G": torch.empty((batch.n_cfg, M), dtype=torch.float64, device=dev) if G else None,
+        "dGdR": torch.empty((3 * batch.N, M), dtype=torch.float64, device=dev) if dGdR else None,
+    }
+    nb = batch.nbrs
+    pod_batch_assemble(model.h, batch.n_cfg, batch.N, batch.P, batch.cfg_atom_off, batch.pos, batch.cells,
+                       nb.offsets, nb.nbr_j, nb.shift, o["D"], o["G"], o["dGdR"], tune)
+    if check:
+        pod_check(model.h)
+    return o
 
 
 def setup_from_workload(s) -> Setup:

@@ -306,3 +306,101 @@ def standardised_coefficients(D, setup: PodSetup, seed: int, targets=(1.0, 0.3, 
             z = rng.normal(size=hi - lo)
             c[lo:hi] = z * s / (sig[lo:hi] * np.sqrt(hi - lo))
     return c
+
+
+# --------------------------------------------------------------------------
+# Batches of small cells (descriptor-matrix assembly)
+# --------------------------------------------------------------------------
+V_ATOM = A_TA ** 3 / 2.0          # volume per atom of the BCC reference (A^3)
+_SITES_PER_CELL = {"bcc": 2, "fcc": 4, "a15": 8}
+
+
+@dataclass
+class Batch:
+    """Many periodic cells, concatenated: atoms of cell c are
+    cfg_atom_off[c]:cfg_atom_off[c+1]; neighbour indices are global."""
+    kinds: list
+    cfg_atom_off: np.ndarray   # int32 [n_cfg + 1]
+    pos: np.ndarray            # [N_tot, 3]
+    cells: np.ndarray          # [n_cfg, 3, 3]
+    nl: NeighborList           # global CSR
+    setup: PodSetup
+
+    @property
+    def n_cfg(self) -> int:
+        return len(self.cfg_atom_off) - 1
+
+    @property
+    def N(self) -> int:
+        return self.pos.shape[0]
+
+    def config(self, c):
+        """(pos, cell, local neighbour list) of cell c."""
+        a0, a1 = int(self.cfg_atom_off[c]), int(self.cfg_atom_off[c + 1])
+        o = self.nl.offsets[a0:a1 + 1].astype(np.int64)
+        p0, p1 = int(o[0]), int(o[-1])
+        nl = NeighborList((o - p0).astype(np.int32), (self.nl.nbr_j[p0:p1] - a0).astype(np.int32),
+                          self.nl.shift3[p0:p1], self.nl.shift[p0:p1])
+        return self.pos[a0:a1], self.cells[c], nl
+
+
+def small_cell(kind: str, n_atoms: int, vol_scale: float, sigma: float, rng):
+    """One cell of n_atoms: a lattice supercell (the smallest n1 x n2 x n3 with
+    at least n_atoms sites, random sites deleted down to n_atoms) or a random
+    liquid (sequential insertion, minimum distance 2 A), at volume per atom
+    V_ATOM * vol_scale."""
+    if kind == "liquid":
+        box = (n_atoms * V_ATOM * vol_scale) ** (1.0 / 3.0)
+        seed = int(rng.integers(1 << 31))
+        pos, cell = random_liquid(n_atoms, box, 2.0, seed)
+        return pos, cell
+    spc = _SITES_PER_CELL[kind]
+    best = None
+    for n1 in range(1, 8):
+        for n2 in range(1, n1 + 1):
+            for n3 in range(1, n2 + 1):
+                if n1 * n2 * n3 * spc >= n_atoms:
+                    key = (n1 * n2 * n3, n1 - n3)
+                    if best is None or key < best[0]:
+                        best = (key, (n1, n2, n3))
+    n1, n2, n3 = best[1]
+    a = (spc * V_ATOM * vol_scale) ** (1.0 / 3.0)
+    pos, cell = lattice(kind, n1, n2, n3, a)
+    if pos.shape[0] > n_atoms:
+        keep = np.sort(rng.choice(pos.shape[0], size=n_atoms, replace=False))
+        pos = pos[keep]
+    pos = pos + rng.normal(0.0, sigma, size=pos.shape)
+    return pos, cell
+
+
+def make_batch(n_cfg: int, seed: int, setup: PodSetup, n_min: int = 2, n_max: int = 250, sigma: float = 0.1):
+    """n_cfg cells, atom counts uniform in [n_min, n_max], kinds uniform over
+    BCC / FCC / A15 / liquid, volume per atom scaled by U[0.9, 1.1]."""
+    rng = np.random.default_rng(seed)
+    kinds, poss, cells, lists = [], [], [], []
+    for _ in range(n_cfg):
+        kind = ["bcc", "fcc", "a15", "liquid"][int(rng.integers(4))]
+        n = int(rng.integers(n_min, n_max + 1))
+        scale = float(rng.uniform(0.9, 1.1))
+        pos, cell = small_cell(kind, n, scale, sigma, rng)
+        kinds.append(kind)
+        poss.append(pos)
+        cells.append(cell)
+        lists.append(neighbor_list(pos, cell, setup.rcut))
+    counts = np.array([p.shape[0] for p in poss])
+    cfg_off = np.zeros(n_cfg + 1, dtype=np.int64)
+    cfg_off[1:] = np.cumsum(counts)
+    pair_counts = np.array([nl.n_pairs for nl in lists])
+    pair_off = np.zeros(n_cfg + 1, dtype=np.int64)
+    pair_off[1:] = np.cumsum(pair_counts)
+    offsets = np.concatenate([[0]] + [nl.offsets[1:].astype(np.int64) + pair_off[c] for c, nl in enumerate(lists)])
+    nbr_j = np.concatenate([nl.nbr_j.astype(np.int64) + cfg_off[c] for c, nl in enumerate(lists)])
+    shift3 = np.concatenate([nl.shift3 for nl in lists]).astype(np.int32)
+    nl = NeighborList(offsets.astype(np.int32), nbr_j.astype(np.int32), shift3, pack_shift(shift3))
+    return Batch(kinds, cfg_off.astype(np.int32), np.concatenate(poss), np.stack(cells), nl, setup)
+
+
+def config3(n_cfg: int = 2000) -> Batch:
+    """2,000 cells of 2-250 atoms (seed 6), 2/3/4-body parameters of the
+    15,840-atom box."""
+    return make_batch(n_cfg, seed=6, setup=SETUP_CFG2)
