@@ -8,8 +8,10 @@ and global descriptors, with inputs already resident in HBM.
 
 Prints one JSON line (rank 0).  Extra objects: ``roofline`` for the main
 per-atom kernel (timed with HIP events inside the library, on its stream),
-``cpu_baseline`` (the FP64 oracle on the host, single thread) and ``f32``
-(the same workload on the FP32 path).
+``cpu_baseline`` (the FP64 oracle on the host, single thread), ``f32``
+(the same workload on the FP32 path) and ``batch`` (the batched
+descriptor-matrix assembly of 2,000 uneven cells with dG/dR, FP64, at the
+autotuner's launch shape).
 """
 from __future__ import annotations
 
@@ -29,6 +31,7 @@ METRIC = "atoms/s for POD energy+forces (FP64/FP32) and MLP-surrogate speedup at
 PEAK_F64 = 78.6e12    # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz, FP64 vector
 PEAK_F32 = 157.3e12   # published FP32 vector peak (packed); unpacked issue gives 78.6e12
 KERNEL_SOURCES = ["paper_2212_14446_amd/csrc/pod_kernels.hip", "paper_2212_14446_amd/csrc/pod_tables.h",
+                  "paper_2212_14446_amd/csrc/pod_device.h",
                   "paper_2212_14446_amd/csrc/pod_internal.h"]
 
 
@@ -127,6 +130,46 @@ def roofline(w, r, dtype):
             "finalize_kernel_ms": r["finalize_kernel_ms"]}
 
 
+def run_batch(steps, warmup):
+    """Batched assembly of 2,000 cells (2..250 atoms; BCC/FCC/A15/liquid):
+    D, G and dG/dR per cell in one launch, FP64, autotuned launch shape."""
+    import torch
+
+    from paper_2212_14446_amd import autotune as at, flops as fl, pod, workloads as wl
+    b = wl.config3()
+    print(f"[bench] batch: {b.n_cfg} cells, N={b.N}, P={b.nl.n_pairs}", file=sys.stderr, flush=True)
+    s = b.setup
+    m = pod.PodModel(pod.setup_from_workload(s), "f64")
+    db = pod.DeviceBatch.from_batch(b)
+    tune = at.tune_batch(m, db, reps=2)
+    out = None
+    for _ in range(warmup):
+        out = pod.batch_assemble(m, db, tune=tune, out=out)
+    torch.cuda.synchronize()
+    pod.pod_set_kernel_timing(m.h, steps)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        pod.batch_assemble(m, db, tune=tune, out=out, check=False)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    kms, kn = pod.pod_get_kernel_time(m.h, 1)
+    pod.pod_set_kernel_timing(m.h, 0)
+    m.check()
+    kms /= max(kn, 1)
+    K = max(s.K2, s.K3, s.K4)
+    PA = max(s.P3 if s.K3 else 0, s.P4 if s.K4 else 0)
+    f = fl.batch_counts(K, s.L, PA, s.P4, s.M, b.nl.n_pairs, b.N)
+    ach = f["total"] / (kms * 1e-3)
+    return {"workload": f"{b.n_cfg} cells, 2..250 atoms, bcc/fcc/a15/liquid, rcut {s.rcut}",
+            "cells": b.n_cfg, "atoms": b.N, "pairs": b.nl.n_pairs, "outputs": "D, G, dG/dR (FP64)",
+            "ms_per_assembly": ms, "cells_per_s": b.n_cfg / (ms * 1e-3), "atoms_per_s": b.N / (ms * 1e-3),
+            "tune": list(tune), "kernel_ms": kms,
+            "roofline": {"bound": "alu", "achieved": ach / 1e12, "peak": PEAK_F64 / 1e12, "unit": "TFLOP/s",
+                         "frac": ach / PEAK_F64, "flops_per_launch": f["total"]}}
+
+
 def cpu_baseline(w):
     """The FP64 oracle (as written) on the host, one thread, full workload."""
     from threadpoolctl import threadpool_limits
@@ -152,6 +195,7 @@ def main():
     ap.add_argument("--rcut", type=float, default=5.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-f32", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (a known-size "
                          "kernel for scaling hardware traffic counters)")
@@ -199,6 +243,9 @@ def main():
         print(f"[bench] f32 {r32}", file=sys.stderr, flush=True)
         rec["f32"] = {"value": w.N / (r32["ms_per_step"] * 1e-3), "ms_per_step": r32["ms_per_step"],
                       "roofline": roofline(w, r32, "f32")}
+    if not args.no_batch:
+        rec["batch"] = run_batch(10, 2)
+        print(f"[bench] batch {rec['batch']}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         rec["cpu_baseline"] = cpu_baseline(w)

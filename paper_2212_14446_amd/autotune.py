@@ -1,7 +1,8 @@
 """Autotuner of the batched assembly's launch shape.
 
-pod_batch_assemble takes a pod_tune triple (cw, ag, nblocks): descriptor
-columns per dG/dR chunk, atoms per Jacobian group and persistent workgroups.
+pod_batch_assemble takes a pod_tune triple (cw, nblocks, threads):
+descriptor columns per dG/dR chunk, persistent workgroups and threads per
+workgroup.
 The best triple depends on the batch (cell sizes, pair counts) and on the
 descriptor set (M, K, angular degree).  This module times a fixed candidate
 list through the library (HIP events on the handle's stream), picks the
@@ -24,14 +25,14 @@ import numpy as np
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "pod_batch_tune.json")
 
-CW = (3, 6, 9, 17)
-AG = (4, 8, 16)
-NBLOCKS = (256, 512, 1024)
+CW = (4, 6, 8, 9)
+NBLOCKS = (512, 1024, 2048)
+THREADS = (128, 256, 512)
 
 
-def candidates(cw: Iterable[int] = CW, ag: Iterable[int] = AG, nblocks: Iterable[int] = NBLOCKS):
+def candidates(cw: Iterable[int] = CW, nblocks: Iterable[int] = NBLOCKS, threads: Iterable[int] = THREADS):
     """Fixed, ordered candidate list."""
-    return [(c, a, b) for c in cw for a in ag for b in nblocks]
+    return [(c, b, t) for c in cw for b in nblocks for t in threads]
 
 
 def signature(n_cfg: int, cell_atoms: Sequence[int], cell_pairs: Sequence[int], M: int, K: int, PA: int,

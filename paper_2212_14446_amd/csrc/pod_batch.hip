@@ -4,18 +4,19 @@
 // dG/dr_n (Sec. II.G, eqs. (26c), (24c), product rule for the 2- and 4-body
 // terms), in FP64, in one persistent launch.
 //
-// One 256-thread workgroup processes one cell at a time; cells are dealt to
-// workgroups in order of decreasing pair count.  Per cell:
+// One workgroup processes one cell at a time; cells are dealt to workgroups
+// in order of decreasing pair count.  Per cell:
 //   1. pair records (rhat, 1/r, R_k, R'_k) for every pair of the cell, in the
-//      workgroup's scratch region (L2-resident);
+//      workgroup's scratch region (cache-resident);
 //   2. forward: lanes (atom, m) accumulate the atomic-basis rows (eq. (24b)),
 //      contract them (eqs. (25)-(30a)), write D, sum G in LDS, keep B;
 //   3. dG/dR: for each radial index m and each chunk of at most `cw` of its
 //      descriptor columns, the cell's dG/dR block [N_c][3][cw] is held in LDS.
-//      For groups of `ag` atoms the Jacobian rows dD_d/dB_{i m .} go to LDS;
-//      then one lane per pair contracts them with the derivatives of the pair's
-//      basis functions and adds +v to the row of the neighbour, -v to the row
-//      of the centre (LDS atomics).  The chunk is then written out.
+//      Work items are (atom i, column): the lane forms the Jacobian row
+//      dD_col/dB_{i m .} in registers, walks the pairs of atom i, contracts
+//      the row with each pair's basis derivative (eq. (24c)) into v = dD_i/dr_ij,
+//      adds +v to the LDS row of the neighbour (atomic) and keeps -v for atom
+//      i in registers, added once at the end.  The chunk is then written out.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -33,7 +34,7 @@ namespace {
 
 using namespace dev;
 
-constexpr int BT = 256;   // threads per workgroup
+constexpr int MAX_THREADS = 512;
 constexpr size_t LDS_LIMIT = 64 * 1024;
 
 struct BArgs {
@@ -50,32 +51,29 @@ struct BArgs {
     double* D;
     double* G;
     double* dGdR;
-    double* scratch;      // per workgroup: rec_cap * SR + b_cap * K * NAP doubles
+    double* scratch;      // per workgroup: rec_cap * (4 + 2K) + b_cap * K * NA doubles
     long rec_cap, b_cap;
-    int cw, ag, nc_max;
+    int cw, nc_max;
     int* err;
 };
 
-__host__ __device__ constexpr int odd(int n) { return n | 1; }
-
 struct BatchLds {
-    size_t q, gsum, b, j, acc, off, total;
+    size_t q, gsum, acc, off, total;
 };
 
-__host__ __device__ inline BatchLds batch_lds(int M, int NA, int cw, int ag, int nc_max) {
+__host__ __device__ inline BatchLds batch_lds(int M, int cw, int nc_max) {
     BatchLds L;
     const size_t d = sizeof(double);
     L.q = 0;
     L.gsum = L.q + static_cast<size_t>(POD_MAX_L) * POD_MAX_K * d;
-    L.b = L.gsum + static_cast<size_t>(M + 1) * d;
-    L.j = L.b + static_cast<size_t>(ag) * odd(NA) * d;
-    L.acc = L.j + static_cast<size_t>(ag) * cw * odd(NA) * d;
+    L.acc = L.gsum + static_cast<size_t>(M + 1) * d;
     L.off = L.acc + static_cast<size_t>(nc_max) * 3 * cw * d;
     L.total = L.off + static_cast<size_t>(nc_max + 1) * sizeof(int);
     return L;
 }
 
-// Global column of local column lc of radial index m: [D2_m] [D3_m,0..P3] [D4_m,0..Ka4-1].
+// Global column of local column lc of radial index m, laid out per m as
+// [D2_m] [D3_m,0..P3] [D4_m,0..Ka4-1] (each present when m is below K2, K3, K4).
 __device__ __forceinline__ int column_of(const ParamsT<double>* P, int m, int lc, int* kind, int* idx) {
     if (m < P->K2) {
         if (lc == 0) { *kind = 2; *idx = 0; return 1 + m; }
@@ -89,11 +87,50 @@ __device__ __forceinline__ int column_of(const ParamsT<double>* P, int m, int lc
     return P->off4 + m * P->Ka4 + lc;
 }
 
-template <int PA, bool FAST>
-__global__ __launch_bounds__(BT) void batch_kernel(BArgs g) {
+// Row J_mu = dD/dB_{i m mu} of one descriptor of radial index m, from the
+// atomic-basis row b = B_{i m .}.  All indices are compile-time, so b and J
+// stay in registers.
+template <int PA>
+__device__ __forceinline__ void jacobian_row(int kind, int idx, const double (&b)[n_mono(PA)],
+                                             double (&J)[n_mono(PA)]) {
     constexpr MonoTable<PA> mt{};
     constexpr int NA = n_mono(PA);
-    constexpr int NAP = odd(NA);
+    using Tab = D4Table<PA>;
+#pragma unroll
+    for (int mu = 0; mu < NA; ++mu) J[mu] = 0.0;
+    if (kind == 2) {                       // eq. (25): D2 = B_m0
+        J[0] = 1.0;
+    } else if (kind == 3) {                // eq. (26c): D3_n = sum_{|mu|=n} c_mu B_mu^2
+#pragma unroll
+        for (int mu = 0; mu < NA; ++mu)
+            if (mt.deg[mu] == idx) J[mu] = 2.0 * mt.mult[mu] * b[mu];
+    } else if (Tab::build.pb[idx] == 0) {  // eq. (27a): D4_(a,0,0) = B_0 D3_a
+        const int aa = Tab::build.pa[idx];
+        double d3a = 0.0;
+#pragma unroll
+        for (int mu = 0; mu < NA; ++mu)
+            if (mt.deg[mu] == aa) {
+                d3a += mt.mult[mu] * b[mu] * b[mu];
+                J[mu] = 2.0 * mt.mult[mu] * b[0] * b[mu];
+            }
+        J[0] += d3a;
+    } else {                               // eq. (30a): sum_t c_t B_x B_y B_z
+#pragma unroll
+        for (int t = 0; t < Tab::NT; ++t)
+            if (Tab::build.tp[t] == idx) {
+                const int x = Tab::build.tx[t], y = Tab::build.ty[t], z = Tab::build.tz[t];
+                const double cf = Tab::build.tc[t];
+                J[x] += cf * b[y] * b[z];
+                J[y] += cf * b[x] * b[z];
+                J[z] += cf * b[x] * b[y];
+            }
+    }
+}
+
+template <int PA, bool FAST>
+__global__ __launch_bounds__(MAX_THREADS) void batch_kernel(BArgs g) {
+    constexpr MonoTable<PA> mt{};
+    constexpr int NA = n_mono(PA);
     using Tab = D4Table<PA>;
     constexpr int KA = Tab::KA;
     constexpr int NT = Tab::NT;
@@ -101,24 +138,23 @@ __global__ __launch_bounds__(BT) void batch_kernel(BArgs g) {
     const ParamsT<double>* __restrict__ P = g.prm;
     const int K = P->K, M = P->M;
     const int SR = 4 + 2 * K;
+    const int nth = blockDim.x;
     const int tid = threadIdx.x;
-    const int lane = tid & 63, wv = tid >> 6;
+    const int lane = tid & 63, wv = tid >> 6, nwv = nth >> 6;
     const int apw = WAVE / K;
     const int al = lane / K, q = lane - al * K;
-    const int cw = g.cw, ag = g.ag;
+    const int cw = g.cw;
 
     extern __shared__ __align__(16) unsigned char smem[];
-    const BatchLds LY = batch_lds(M, NA, cw, ag, g.nc_max);
+    const BatchLds LY = batch_lds(M, cw, g.nc_max);
     double* sQ = reinterpret_cast<double*>(smem + LY.q);
     double* sG = reinterpret_cast<double*>(smem + LY.gsum);
-    double* sB = reinterpret_cast<double*>(smem + LY.b);
-    double* sJ = reinterpret_cast<double*>(smem + LY.j);
     double* sAcc = reinterpret_cast<double*>(smem + LY.acc);
     int* sOff = reinterpret_cast<int*>(smem + LY.off);
 
     if (FAST)
-        for (int i = tid; i < POD_MAX_L * POD_MAX_K; i += BT) sQ[i] = (&P->Q[0][0])[i];
-    double* rec = g.scratch + static_cast<size_t>(blockIdx.x) * (g.rec_cap * SR + g.b_cap * K * NAP);
+        for (int i = tid; i < POD_MAX_L * POD_MAX_K; i += nth) sQ[i] = (&P->Q[0][0])[i];
+    double* rec = g.scratch + static_cast<size_t>(blockIdx.x) * (g.rec_cap * SR + g.b_cap * K * NA);
     double* Bs = rec + g.rec_cap * SR;
     const double rin = P->rin, rcut = P->rcut;
 
@@ -126,7 +162,7 @@ __global__ __launch_bounds__(BT) void batch_kernel(BArgs g) {
         const int c = g.order[w];
         const int a0 = g.cfg_off[c], a1 = g.cfg_off[c + 1];
         const int Nc = a1 - a0;
-        for (int i = tid; i <= Nc; i += BT) sOff[i] = g.offsets[a0 + i];
+        for (int i = tid; i <= Nc; i += nth) sOff[i] = g.offsets[a0 + i];
         double cell[9];
 #pragma unroll
         for (int k = 0; k < 9; ++k) cell[k] = g.cells[9 * static_cast<size_t>(c) + k];
@@ -135,7 +171,7 @@ __global__ __launch_bounds__(BT) void batch_kernel(BArgs g) {
         const int Pc = sOff[Nc] - p0;
 
         // ---- 1. pair records ----
-        for (int pp = tid; pp < Pc; pp += BT) {
+        for (int pp = tid; pp < Pc; pp += nth) {
             int lo = 0, hi = Nc;   // sOff[lo] - p0 <= pp < sOff[hi] - p0
             while (hi - lo > 1) {
                 const int mid = (lo + hi) >> 1;
@@ -174,11 +210,11 @@ __global__ __launch_bounds__(BT) void batch_kernel(BArgs g) {
             for (int k = 0; k < POD_MAX_K; ++k)
                 if (k < K) { row[4 + k] = R[k] * z; row[4 + K + k] = dR[k] * z; }
         }
-        for (int k = tid; k < M; k += BT) sG[k] = 0.0;
+        for (int k = tid; k < M; k += nth) sG[k] = 0.0;
         __syncthreads();
 
         // ---- 2. forward: atomic basis, descriptors, G ----
-        for (int base = 0; base < Nc; base += 4 * apw) {
+        for (int base = 0; base < Nc; base += nwv * apw) {
             const int a = base + wv * apw + al;
             const bool act = al < apw && a < Nc;
             const int m = q;
@@ -206,7 +242,7 @@ __global__ __launch_bounds__(BT) void batch_kernel(BArgs g) {
                                         acc[Tab::build.tz[t]];
             if (act) {
 #pragma unroll
-                for (int mu = 0; mu < NA; ++mu) Bs[(static_cast<size_t>(a) * K + m) * NAP + mu] = acc[mu];
+                for (int mu = 0; mu < NA; ++mu) Bs[(static_cast<size_t>(a) * K + m) * NA + mu] = acc[mu];
                 double* Drow = g.D ? g.D + static_cast<size_t>(a0 + a) * M : nullptr;
                 if (q == 0) { if (Drow) Drow[0] = 1.0; atomicAdd(&sG[0], 1.0); }
                 if (m < P->K2) { if (Drow) Drow[1 + m] = acc[0]; atomicAdd(&sG[1 + m], acc[0]); }
@@ -232,7 +268,7 @@ __global__ __launch_bounds__(BT) void batch_kernel(BArgs g) {
         }
         __syncthreads();
         if (g.G)
-            for (int k = tid; k < M; k += BT) g.G[static_cast<size_t>(c) * M + k] = sG[k];
+            for (int k = tid; k < M; k += nth) g.G[static_cast<size_t>(c) * M + k] = sG[k];
 
         // ---- 3. dG/dR ----
         if (g.dGdR) {
@@ -240,62 +276,24 @@ __global__ __launch_bounds__(BT) void batch_kernel(BArgs g) {
                 const int ncol_m = (m < P->K2 ? 1 : 0) + (m < P->K3 ? P->P3 + 1 : 0) + (m < P->K4 ? P->Ka4 : 0);
                 for (int cs = 0; cs < ncol_m; cs += cw) {
                     const int nc = min(cw, ncol_m - cs);
-                    for (int t = tid; t < Nc * 3 * cw; t += BT) sAcc[t] = 0.0;
+                    for (int t = tid; t < Nc * 3 * cw; t += nth) sAcc[t] = 0.0;
                     __syncthreads();
-                    for (int g0 = 0; g0 < Nc; g0 += ag) {
-                        const int ng = min(ag, Nc - g0);
-                        for (int t = tid; t < ng * NA; t += BT) {
-                            const int ga = t / NA, mu = t - ga * NA;
-                            sB[ga * NAP + mu] = Bs[(static_cast<size_t>(g0 + ga) * K + m) * NAP + mu];
+                    for (int it = tid; it < Nc * nc; it += nth) {
+                        const int a = it / nc, cl = it - a * nc;
+                        int kind, idx;
+                        column_of(P, m, cs + cl, &kind, &idx);
+                        double J[NA];
+                        {
+                            double b[NA];
+                            const double* brow = Bs + (static_cast<size_t>(a) * K + m) * NA;
+#pragma unroll
+                            for (int mu = 0; mu < NA; ++mu) b[mu] = brow[mu];
+                            jacobian_row<PA>(kind, idx, b, J);
                         }
-                        __syncthreads();
-                        // Jacobian rows dD_col/dB_{i m .} of the chunk's columns
-                        for (int t = tid; t < ng * nc; t += BT) {
-                            const int ga = t / nc, cl = t - ga * nc;
-                            int kind, idx;
-                            column_of(P, m, cs + cl, &kind, &idx);
-                            const double* b = sB + ga * NAP;
-                            double* J = sJ + (ga * cw + cl) * NAP;
-#pragma unroll
-                            for (int mu = 0; mu < NA; ++mu) J[mu] = 0.0;
-                            if (kind == 2) {
-                                J[0] = 1.0;                                            // eq. (25)
-                            } else if (kind == 3) {
-#pragma unroll
-                                for (int mu = 0; mu < NA; ++mu)                          // eq. (26c)
-                                    if (mt.deg[mu] == idx) J[mu] = 2.0 * mt.mult[mu] * b[mu];
-                            } else if (Tab::build.pb[idx] == 0) {
-                                const int aa = Tab::build.pa[idx];                        // eq. (27a)
-                                double d3a = 0.0;
-#pragma unroll
-                                for (int mu = 0; mu < NA; ++mu)
-                                    if (mt.deg[mu] == aa) d3a += mt.mult[mu] * b[mu] * b[mu];
-                                J[0] += d3a;
-#pragma unroll
-                                for (int mu = 0; mu < NA; ++mu)
-                                    if (mt.deg[mu] == aa) J[mu] += b[0] * 2.0 * mt.mult[mu] * b[mu];
-                            } else {
-                                for (int tt = Tab::build.tbeg[idx]; tt < Tab::build.tend[idx]; ++tt) {   // eq. (30a)
-                                    const int x = Tab::build.tx[tt], y = Tab::build.ty[tt], z = Tab::build.tz[tt];
-                                    const double cf = Tab::build.tc[tt];
-                                    J[x] += cf * b[y] * b[z];
-                                    J[y] += cf * b[x] * b[z];
-                                    J[z] += cf * b[x] * b[y];
-                                }
-                            }
-                        }
-                        __syncthreads();
-                        // one lane per pair of the group
-                        const int pbeg = sOff[g0] - p0, pend = sOff[g0 + ng] - p0;
-                        for (int pp = pbeg + tid; pp < pend; pp += BT) {
-                            int lo = g0, hi = g0 + ng;
-                            while (hi - lo > 1) {
-                                const int mid = (lo + hi) >> 1;
-                                if (sOff[mid] - p0 <= pp) lo = mid; else hi = mid;
-                            }
-                            const int il = lo, ga = lo - g0;
+                        double s0 = 0.0, s1 = 0.0, s2 = 0.0;   // -sum_j v_ij, the centre's own row
+                        const int pe = sOff[a + 1] - p0;
+                        for (int pp = sOff[a] - p0; pp < pe; ++pp) {
                             const int jl = g.nbr_j[p0 + pp] - a0;
-                            if (jl < 0 || jl >= Nc) continue;
                             const double* row = rec + static_cast<size_t>(pp) * SR;
                             const double ux = row[0], uy = row[1], uz = row[2], ri = row[3];
                             const double Rm = row[4 + m], dRm = row[4 + K + m];
@@ -306,36 +304,40 @@ __global__ __launch_bounds__(BT) void batch_kernel(BArgs g) {
                                 const double u = mt.axis[mu] == 0 ? ux : (mt.axis[mu] == 1 ? uy : uz);
                                 A[mu] = A[mt.par[mu]] * u;
                             }
-                            for (int cl = 0; cl < nc; ++cl) {
-                                const double* J = sJ + (ga * cw + cl) * NAP;
-                                // h = sum_mu J_mu A_mu(u), its u-gradient q and the Euler sum
-                                // u . grad h = sum_mu deg(mu) J_mu A_mu (A_mu homogeneous)
-                                double hsum = 0, eul = 0, q0 = 0, q1 = 0, q2 = 0;
+                            // h = sum_mu J_mu A_mu(u), its u-gradient q and the Euler sum
+                            // u . grad h = sum_mu deg(mu) J_mu A_mu (A_mu homogeneous)
+                            double hn[PA + 1];
 #pragma unroll
-                                for (int mu = 0; mu < NA; ++mu) {
-                                    const double t = J[mu] * A[mu];
-                                    hsum += t;
-                                    eul += double(mt.deg[mu]) * t;
-                                    if (mt.down[mu][0] >= 0) q0 += double(mt.ex[mu][0]) * J[mu] * A[mt.down[mu][0]];
-                                    if (mt.down[mu][1] >= 0) q1 += double(mt.ex[mu][1]) * J[mu] * A[mt.down[mu][1]];
-                                    if (mt.down[mu][2] >= 0) q2 += double(mt.ex[mu][2]) * J[mu] * A[mt.down[mu][2]];
-                                }
-                                // eq. (24c): R'_m h rhat + R_m (grad_u h - (rhat . grad_u h) rhat) / r
-                                const double c1 = dRm * hsum - Rm * eul * ri;
-                                const double c2 = Rm * ri;
-                                const double v0 = c1 * ux + c2 * q0, v1 = c1 * uy + c2 * q1, v2 = c1 * uz + c2 * q2;
+                            for (int n = 0; n <= PA; ++n) hn[n] = 0.0;
+                            double q0 = 0, q1 = 0, q2 = 0;
+#pragma unroll
+                            for (int mu = 0; mu < NA; ++mu) {
+                                hn[mt.deg[mu]] += J[mu] * A[mu];
+                                if (mt.down[mu][0] >= 0) q0 += double(mt.ex[mu][0]) * J[mu] * A[mt.down[mu][0]];
+                                if (mt.down[mu][1] >= 0) q1 += double(mt.ex[mu][1]) * J[mu] * A[mt.down[mu][1]];
+                                if (mt.down[mu][2] >= 0) q2 += double(mt.ex[mu][2]) * J[mu] * A[mt.down[mu][2]];
+                            }
+                            double hsum = 0.0, eul = 0.0;
+#pragma unroll
+                            for (int n = 0; n <= PA; ++n) { hsum += hn[n]; eul += double(n) * hn[n]; }
+                            // eq. (24c): R'_m h rhat + R_m (grad_u h - (rhat . grad_u h) rhat) / r
+                            const double c1 = dRm * hsum - Rm * eul * ri;
+                            const double c2 = Rm * ri;
+                            const double v0 = c1 * ux + c2 * q0, v1 = c1 * uy + c2 * q1, v2 = c1 * uz + c2 * q2;
+                            if (jl >= 0 && jl < Nc) {
                                 atomicAdd(&sAcc[(jl * 3 + 0) * cw + cl], v0);
                                 atomicAdd(&sAcc[(jl * 3 + 1) * cw + cl], v1);
                                 atomicAdd(&sAcc[(jl * 3 + 2) * cw + cl], v2);
-                                atomicAdd(&sAcc[(il * 3 + 0) * cw + cl], -v0);
-                                atomicAdd(&sAcc[(il * 3 + 1) * cw + cl], -v1);
-                                atomicAdd(&sAcc[(il * 3 + 2) * cw + cl], -v2);
                             }
+                            s0 -= v0; s1 -= v1; s2 -= v2;
                         }
-                        __syncthreads();
+                        atomicAdd(&sAcc[(a * 3 + 0) * cw + cl], s0);
+                        atomicAdd(&sAcc[(a * 3 + 1) * cw + cl], s1);
+                        atomicAdd(&sAcc[(a * 3 + 2) * cw + cl], s2);
                     }
+                    __syncthreads();
                     // write the chunk out
-                    for (int t = tid; t < Nc * 3 * nc; t += BT) {
+                    for (int t = tid; t < Nc * 3 * nc; t += nth) {
                         const int n = t / (3 * nc), r3 = t - n * 3 * nc;
                         const int d = r3 / nc, cl = r3 - d * nc;
                         int kind, idx;
@@ -345,28 +347,28 @@ __global__ __launch_bounds__(BT) void batch_kernel(BArgs g) {
                     __syncthreads();
                 }
             }
-            for (int t = tid; t < Nc * 3; t += BT) g.dGdR[(static_cast<size_t>(a0) * 3 + t) * M] = 0.0;
+            for (int t = tid; t < Nc * 3; t += nth) g.dGdR[(static_cast<size_t>(a0) * 3 + t) * M] = 0.0;
         }
         __syncthreads();
     }
 }
 
 template <int PA>
-hipError_t launch_batch(const BArgs& a, bool fast, int nblk, size_t lds, hipStream_t st) {
-    if (fast) hipLaunchKernelGGL((batch_kernel<PA, true>), dim3(nblk), dim3(BT), lds, st, a);
-    else hipLaunchKernelGGL((batch_kernel<PA, false>), dim3(nblk), dim3(BT), lds, st, a);
+hipError_t launch_batch(const BArgs& a, bool fast, int nblk, int nth, size_t lds, hipStream_t st) {
+    if (fast) hipLaunchKernelGGL((batch_kernel<PA, true>), dim3(nblk), dim3(nth), lds, st, a);
+    else hipLaunchKernelGGL((batch_kernel<PA, false>), dim3(nblk), dim3(nth), lds, st, a);
     return hipGetLastError();
 }
 
-hipError_t dispatch_batch(int PA, const BArgs& a, bool fast, int nblk, size_t lds, hipStream_t st) {
+hipError_t dispatch_batch(int PA, const BArgs& a, bool fast, int nblk, int nth, size_t lds, hipStream_t st) {
     switch (PA) {
-        case 0: return launch_batch<0>(a, fast, nblk, lds, st);
-        case 1: return launch_batch<1>(a, fast, nblk, lds, st);
-        case 2: return launch_batch<2>(a, fast, nblk, lds, st);
-        case 3: return launch_batch<3>(a, fast, nblk, lds, st);
-        case 4: return launch_batch<4>(a, fast, nblk, lds, st);
-        case 5: return launch_batch<5>(a, fast, nblk, lds, st);
-        case 6: return launch_batch<6>(a, fast, nblk, lds, st);
+        case 0: return launch_batch<0>(a, fast, nblk, nth, lds, st);
+        case 1: return launch_batch<1>(a, fast, nblk, nth, lds, st);
+        case 2: return launch_batch<2>(a, fast, nblk, nth, lds, st);
+        case 3: return launch_batch<3>(a, fast, nblk, nth, lds, st);
+        case 4: return launch_batch<4>(a, fast, nblk, nth, lds, st);
+        case 5: return launch_batch<5>(a, fast, nblk, nth, lds, st);
+        case 6: return launch_batch<6>(a, fast, nblk, nth, lds, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -403,15 +405,15 @@ int pod_batch_assemble(pod_handle* h, int n_cfg, int N, int P, const int* cfg_at
         max_nc = std::max(max_nc, nc);
         max_pc = std::max(max_pc, npair[c]);
     }
-    const int NA = n_mono(h->PA), NAP = NA | 1;
-    int cw = tune && tune->cw > 0 ? tune->cw : 6;
-    int ag = tune && tune->ag > 0 ? tune->ag : 8;
-    int nblk = tune && tune->nblocks > 0 ? tune->nblocks : 512;
+    const int NA = n_mono(h->PA);
+    int cw = tune && tune->cw > 0 ? tune->cw : 9;
+    int nblk = tune && tune->nblocks > 0 ? tune->nblocks : 2048;
+    const int nth = tune && tune->threads > 0 ? tune->threads : 512;
+    if (nth % 64 != 0 || nth > MAX_THREADS) return POD_EINVAL;
     nblk = std::min(nblk, n_cfg);
     const int nc_max = ((max_nc + 15) / 16) * 16;
-    while (cw > 1 && batch_lds(h->M, NA, cw, ag, nc_max).total > LDS_LIMIT) --cw;
-    while (ag > 1 && batch_lds(h->M, NA, cw, ag, nc_max).total > LDS_LIMIT) --ag;
-    const size_t lds = batch_lds(h->M, NA, cw, ag, nc_max).total;
+    while (cw > 1 && batch_lds(h->M, cw, nc_max).total > LDS_LIMIT) --cw;
+    const size_t lds = batch_lds(h->M, cw, nc_max).total;
     if (lds > LDS_LIMIT) return POD_ENOTSUP;   // a cell too large for the LDS accumulator
     // cells by decreasing pair count, dealt round-robin to the workgroups
     std::vector<int> order(n_cfg);
@@ -419,7 +421,7 @@ int pod_batch_assemble(pod_handle* h, int n_cfg, int N, int P, const int* cfg_at
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return npair[x] > npair[y]; });
     const int SR = 4 + 2 * h->K;
     const long rec_cap = std::max(max_pc, 1), b_cap = std::max(max_nc, 1);
-    const size_t per_blk = static_cast<size_t>(rec_cap) * SR + static_cast<size_t>(b_cap) * h->K * NAP;
+    const size_t per_blk = static_cast<size_t>(rec_cap) * SR + static_cast<size_t>(b_cap) * h->K * NA;
     const size_t order_bytes = ((sizeof(int) * n_cfg + 255) / 256) * 256;
     int rc = ensure_scratch(h, order_bytes + per_blk * nblk * sizeof(double));
     if (rc != POD_OK) return rc;
@@ -435,10 +437,10 @@ int pod_batch_assemble(pod_handle* h, int n_cfg, int N, int P, const int* cfg_at
     a.D = D; a.G = G; a.dGdR = dGdR;
     a.scratch = reinterpret_cast<double*>(static_cast<char*>(h->d_scratch) + order_bytes);
     a.rec_cap = rec_cap; a.b_cap = b_cap;
-    a.cw = cw; a.ag = ag; a.nc_max = nc_max;
+    a.cw = cw; a.nc_max = nc_max;
     a.err = h->d_err;
     timing_begin(h, 1);
-    const hipError_t e = dispatch_batch(h->PA, a, h->std_ok != 0, nblk, lds, h->stream);
+    const hipError_t e = dispatch_batch(h->PA, a, h->std_ok != 0, nblk, nth, lds, h->stream);
     timing_end(h, 1);
     return e == hipSuccess ? POD_OK : POD_EHIP;
 }

@@ -16,6 +16,14 @@ snapshots, G_a nonzero partial derivatives of the monomials):
 Per atom (NT merged eq. (30a) terms, K_a four-body functions):
   K (3 N_a + 4 NT + 3 N_a + 9 NT + 2 (2 + P_a + K_a))
              D3 (eq. (26a)), D4 (eq. (30a)), their adjoints, energy
+
+Batched assembly with descriptor derivatives (batch_counts): radial with
+derivatives and forward as above, the per-atom forward contraction
+K (3 N_a + 4 NT), and for dG/dR, per pair and radial index m the monomials
+(N_a - 1), and per pair and descriptor column
+  2 N_a + 6 N_a(P_a - 1) + 2 (P_a + 1) + 12
+  (h = J . A, its u-gradient from the monomials of degree < P_a, the degree
+  sums, and v of eq. (24c) with its two scatters).
 """
 from __future__ import annotations
 
@@ -69,3 +77,14 @@ def counts(K, L, PA, P4=None):
     atom = K * (3 * Na + 4 * NT + 3 * Na + 9 * NT + 2 * (2 + PA + Ka))
     return {"radial_per_pair": radial, "forward_per_pair": fwd, "backward_per_pair": bwd,
             "per_atom": atom, "Na": Na, "Ga": Ga, "NT": NT}
+
+
+def batch_counts(K, L, PA, P4, M, n_pairs, n_atoms):
+    """Algorithmic flops of one batched assembly (D, G and dG/dR)."""
+    c = counts(K, L, PA, P4)
+    Na, NT = c["Na"], c["NT"]
+    Na_low = len(monomials(PA - 1)) if PA > 0 else 0
+    per_col = 2 * Na + 6 * Na_low + 2 * (PA + 1) + 12
+    fwd = (c["radial_per_pair"] + c["forward_per_pair"]) * n_pairs + K * (3 * Na + 4 * NT) * n_atoms
+    deriv = n_pairs * ((M - 1) * per_col + K * (Na - 1))
+    return {"forward": fwd, "derivatives": deriv, "total": fwd + deriv, "per_pair_column": per_col}

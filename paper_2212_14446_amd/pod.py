@@ -41,7 +41,7 @@ class PodParamsC(ctypes.Structure):
 
 
 class PodTuneC(ctypes.Structure):
-    _fields_ = [("cw", ctypes.c_int), ("ag", ctypes.c_int), ("nblocks", ctypes.c_int)]
+    _fields_ = [("cw", ctypes.c_int), ("nblocks", ctypes.c_int), ("threads", ctypes.c_int)]
 
 
 class PodError(RuntimeError):
@@ -219,7 +219,7 @@ def pod_energy_forces(h: Handle, N, P, pos, cell, offsets, nbr_j, shift, c, E_at
 
 def pod_batch_assemble(h: Handle, n_cfg, N, P, cfg_atom_off, pos, cells, offsets, nbr_j, shift, D=None, G=None,
                        dGdR=None, tune=None):
-    """tune: None (library defaults) or a (cw, ag, nblocks) triple."""
+    """tune: None (library defaults) or a (cw, nblocks, threads) triple."""
     t = None
     if tune is not None:
         t = ctypes.byref(PodTuneC(int(tune[0]), int(tune[1]), int(tune[2])))

@@ -11,9 +11,9 @@ from paper_2212_14446_amd import autotune as at
 
 def test_candidates_fixed_order():
     c = at.candidates()
-    assert len(c) == len(at.CW) * len(at.AG) * len(at.NBLOCKS)
+    assert len(c) == len(at.CW) * len(at.NBLOCKS) * len(at.THREADS)
     assert c == at.candidates()
-    assert c[0] == (at.CW[0], at.AG[0], at.NBLOCKS[0])
+    assert c[0] == (at.CW[0], at.NBLOCKS[0], at.THREADS[0])
 
 
 def test_pick_fastest_and_ties():
@@ -38,7 +38,7 @@ def test_signature_depends_on_workload():
 
 def test_tune_caches_and_is_deterministic(tmp_path):
     path = str(tmp_path / "tune.json")
-    cands = at.candidates(cw=(3, 6), ag=(4,), nblocks=(256, 512))
+    cands = at.candidates(cw=(3, 6), nblocks=(4,), threads=(256, 512))
     calls = []
 
     def measure(c):

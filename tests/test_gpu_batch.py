@@ -91,7 +91,7 @@ def test_batch_matches_single_system_call(ref2, small_batch, small_got):
         assert relerr(got["G"][c], D1.sum(axis=0)) < 1e-12
 
 
-@pytest.mark.parametrize("tune", [(1, 1, 7), (3, 4, 64), (6, 8, 512), (12, 16, 4096), (17, 2, 1)])
+@pytest.mark.parametrize("tune", [(1, 7, 64), (3, 64, 128), (6, 512, 256), (12, 4096, 512), (17, 1, 192)])
 def test_batch_tunes_agree(ref2, small_batch, small_got, tune):
     got, m, db = small_got
     say(f"[gpu] batch tune {tune}")
@@ -153,6 +153,11 @@ def test_batch_errors(ref2, small_batch):
     with pytest.raises(pod.PodError) as e:
         pod.batch_assemble(m, db2)
     assert e.value.code == -1
+    # launch shapes the kernel is not built for
+    for bad_tune in ((6, 64, 100), (6, 64, 1024)):
+        with pytest.raises(pod.PodError) as e:
+            pod.batch_assemble(m, pod.DeviceBatch.from_batch(b), tune=bad_tune)
+        assert e.value.code == -1
     # a non-finite coordinate
     pos = np.asarray(b.pos).copy()
     pos[0, 1] = np.nan
@@ -208,7 +213,7 @@ def test_batch_autotuner_deterministic(ref2, small_batch, small_got, tmp_path):
     from paper_2212_14446_amd import autotune as at
     got, m, db = small_got
     path = str(tmp_path / "tune.json")
-    cands = at.candidates(cw=(3, 6), ag=(4, 8), nblocks=(64, 256))
+    cands = at.candidates(cw=(3, 6), nblocks=(64, 256), threads=(128, 256))
     best = at.tune_batch(m, db, path, cands, reps=2)
     say(f"[gpu] autotune pick {best}")
     assert best in cands
