@@ -174,14 +174,70 @@ int pod_batch_assemble(pod_handle* h, int n_cfg, int N, int P, const int* cfg_at
                        const int* nbr_j, const int* shift, double* D, double* G,
                        double* dGdR, const pod_tune* tune);
 
+/* ---- Network surrogate of the 4-body energy (Sec. IV.D, eqs. (671a)-(673a)) ----
+ * A network y(x) with two SiLU hidden layers of width POD_MLP_HIDDEN and a
+ * linear output reads the standardised descriptors x = (X - mu) * inv_sigma
+ * of one atom.  Parameters theta (FP32, device, caller-owned) are laid out as
+ * W1 [64][n_in], b1 [64], W2 [64][64], b2 [64], w3 [64], b3, row-major and
+ * concatenated (pod_mlp_num_params(n_in) floats).  Matrix products take
+ * bfloat16 operands (round to nearest even: standardised inputs, W1, W2, the
+ * first hidden activation and the back-propagated pre-activation gradients)
+ * and accumulate in FP32; biases, the output layer and the activations stay
+ * in FP32. */
+#define POD_MLP_HIDDEN 64
+#define POD_MLP_MAX_IN 64
+
+/* Parameter count for n_in inputs (1 <= n_in <= POD_MLP_MAX_IN), or POD_EINVAL. */
+int pod_mlp_num_params(int n_in);
+
+/* Network output and its input gradient (eq. (673a)) for n rows.
+ *   X        : n rows (device, handle dtype), row i holds its n_in inputs at
+ *              X[i * ldx + k] (ldx >= n_in); e.g. a descriptor matrix from
+ *              pod_descriptors offset by one column, ldx = M
+ *   theta    : parameters (device FP32); mu, inv_sigma: n_in floats (device)
+ *   y        : n floats (device) or NULL
+ *   dydx     : n x n_in floats (device) dy/dX (inv_sigma applied) or NULL
+ * Asynchronous on the handle's stream. */
+int pod_mlp_forward(pod_handle* h, int n, int n_in, const void* X, long ldx, const float* theta,
+                    const float* mu, const float* inv_sigma, float* y, float* dydx);
+
+/* One training step on a batch of n rows: the mean squared error
+ * L = (1/n) sum_i (y(x_i) - target_i)^2 (the energy part of eq. (63b), per
+ * atom), its gradient by reverse differentiation, and one Adam update
+ * (Kingma and Ba, 2015) of theta with moments adam_m, adam_v (device FP32,
+ * same layout as theta, zero before step 1; step counts from 1).
+ *   X      : n x n_in FP32 rows at X[i * ldx + k]; target: n floats (device)
+ *   loss   : device float receiving L before the update, or NULL
+ * The gradient is reduced in a fixed order: results are reproducible.
+ * Asynchronous on the handle's stream; uses the handle's network scratch. */
+int pod_mlp_train_step(pod_handle* h, int n, int n_in, const float* X, long ldx, const float* target,
+                       const float* mu, const float* inv_sigma, float* theta, float* adam_m,
+                       float* adam_v, int step, float lr, float beta1, float beta2, float eps,
+                       float* loss);
+
+/* Energies, forces and virial with the network in place of the 4-body term:
+ *   E_i = c . D_i + y((D_i[1..M-1] - mu) * inv_sigma)
+ * for a handle without 4-body descriptors (K4 = 0; n_in = M - 1 inputs,
+ * else POD_EINVAL / POD_ENOTSUP).  Forces follow eq. (673a): the adjoint of
+ * atom i takes the weights c + (0, dy/dX_i) on its descriptors, then the
+ * pair sweep of eq. (24c) as in pod_energy_forces.  Three kernels on the
+ * handle's stream: descriptors, network forward + input gradient, energy and
+ * adjoint.  Arguments as for pod_energy_forces (no G); theta, mu, inv_sigma
+ * as for pod_mlp_forward. */
+int pod_energy_forces_surrogate(pod_handle* h, int N, int P, const void* pos, const double* cell,
+                                const int* offsets, const int* nbr_j, const int* shift,
+                                const int* rev, const void* c, const float* theta, const float* mu,
+                                const float* inv_sigma, void* E_atom, double* E, void* F, double* W);
+
 /* Diagnostics.  pod_set_kernel_timing(h, n) with n > 0 makes the next n
  * compute calls record pairs of HIP events on the handle's stream around each
  * of their kernels (n = 0 switches recording off).  pod_get_kernel_time waits
  * for the stream and returns the summed elapsed time (ms) and the number of
  * recorded launches of one kernel -- kind 1: the per-atom kernel (radial
- * basis, atomic basis, contractions, energy, adjoint, per-pair gradients);
- * kind 0: the finalize kernel (totals E, W, G and the force copy-out) --
- * then resets that count. */
+ * basis, atomic basis, contractions, energy, adjoint, per-pair gradients)
+ * and the batched-assembly kernel; kind 0: the finalize kernel (totals E, W,
+ * G and the force copy-out); kind 2: the network kernels -- then resets that
+ * count. */
 int pod_set_kernel_timing(pod_handle* h, int n);
 int pod_get_kernel_time(pod_handle* h, int kind, double* total_ms, int* launches);
 

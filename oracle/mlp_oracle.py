@@ -143,24 +143,17 @@ def adam_step(theta, m, v, grad, step: int, lr: float, beta1: float = 0.9, beta2
     return np.asarray(theta, dtype=np.float64) - lr * mhat / (np.sqrt(vhat) + eps), m, v
 
 
-def surrogate_energy_forces(pos, cell, offsets, nbr_j, shift, p23, Q, c23, theta, mu, inv_sigma,
-                            bf16: bool = True):
-    """Energies, forces and virial of E_i = c23 . D23_i + y(x_i).
-
-    p23 is a 2/3-body parameter set (K4 = 0) of the POD oracle; the network
-    input is D23_i without its constant column.  Forces follow eq. (673a):
-    dE_i/dr_ij = sum_k C_ik dD_ik/dr_ij with C_i = c23 + (0, dy/dX_i), and the
-    descriptor derivatives dD_i/dr_ij from the POD oracle (eqs. (26c),
-    (24c)).  F_n = -dE/dr_n; W_ab = -sum_pairs r_ij,a dE_i/dr_ij,b."""
+def forces_from_atom_weights(pos, cell, offsets, nbr_j, shift, p, Q, C):
+    """Forces and virial of an energy whose derivative with respect to the
+    descriptors of atom i is the row C_i (eq. (673a) with the descriptor
+    derivatives of eqs. (26c), (24c) from the POD oracle):
+    dE_i/dr_ij = sum_k C_ik dD_ik/dr_ij, F_n = -dE/dr_n,
+    W_ab = -sum_pairs r_ij,a dE_i/dr_ij,b."""
     from oracle import pod_oracle as po
     pos = np.asarray(pos, dtype=np.float64)
     N = pos.shape[0]
-    D = po.descriptors_fast(pos, cell, offsets, nbr_j, shift, p23, Q)
-    y, dydx = input_gradient(theta, D[:, 1:], mu, inv_sigma, bf16)
-    c23 = np.asarray(c23, dtype=np.float64)
-    E_atom = D @ c23 + y
-    C = c23[None, :] + np.concatenate([np.zeros((N, 1)), dydx], axis=1)
-    dD, centre, pidx = po.descriptor_derivatives(pos, cell, offsets, nbr_j, shift, p23, Q)
+    C = np.asarray(C, dtype=np.float64)
+    dD, centre, pidx = po.descriptor_derivatives(pos, cell, offsets, nbr_j, shift, p, Q)
     F = np.zeros((N, 3))
     W = np.zeros((3, 3))
     if len(pidx):
@@ -171,4 +164,23 @@ def surrogate_energy_forces(pos, cell, offsets, nbr_j, shift, p23, Q, c23, theta
         dmap = np.zeros((len(nbr_j), 3))
         dmap[pidx2] = d
         W -= dmap[pidx].T @ g
+    return F, W
+
+
+def surrogate_energy_forces(pos, cell, offsets, nbr_j, shift, p23, Q, c23, theta, mu, inv_sigma,
+                            bf16: bool = True):
+    """Energies, forces and virial of E_i = c23 . D23_i + y(x_i).
+
+    p23 is a 2/3-body parameter set (K4 = 0) of the POD oracle; the network
+    input is D23_i without its constant column.  Forces follow eq. (673a)
+    with the per-atom weights C_i = c23 + (0, dy/dX_i)."""
+    from oracle import pod_oracle as po
+    pos = np.asarray(pos, dtype=np.float64)
+    N = pos.shape[0]
+    D = po.descriptors_fast(pos, cell, offsets, nbr_j, shift, p23, Q)
+    y, dydx = input_gradient(theta, D[:, 1:], mu, inv_sigma, bf16)
+    c23 = np.asarray(c23, dtype=np.float64)
+    E_atom = D @ c23 + y
+    C = c23[None, :] + np.concatenate([np.zeros((N, 1)), dydx], axis=1)
+    F, W = forces_from_atom_weights(pos, cell, offsets, nbr_j, shift, p23, Q, C)
     return {"E_atom": E_atom, "E": float(E_atom.sum()), "F": F, "W": W, "y": y, "dydx": dydx, "D": D}

@@ -239,6 +239,23 @@ int pod::ensure_scratch(pod_handle* h, size_t bytes) {
     return POD_OK;
 }
 
+int pod::ensure_mscratch(pod_handle* h, size_t bytes) {
+    if (bytes <= h->mscratch_bytes) return POD_OK;
+    if (h->d_mscratch) {
+        if (hipStreamSynchronize(h->stream) != hipSuccess) return POD_EHIP;
+        (void)hipFree(h->d_mscratch);
+        h->d_mscratch = nullptr;
+        h->mscratch_bytes = 0;
+    }
+    size_t want = bytes + bytes / 4 + 4096;
+    if (hipMalloc(&h->d_mscratch, want) != hipSuccess) {
+        h->d_mscratch = nullptr;
+        return POD_ENOMEM;
+    }
+    h->mscratch_bytes = want;
+    return POD_OK;
+}
+
 void pod::timing_begin(pod_handle* h, int kind) {
     auto& ev = h->ev[kind];
     const int u = h->ev_used[kind];
@@ -256,8 +273,8 @@ void pod::timing_end(pod_handle* h, int kind) {
 
 namespace {
 void release_events(pod_handle* h) {
-    if (!h->ev[0].empty() || !h->ev[1].empty()) (void)hipStreamSynchronize(h->stream);
-    for (int k = 0; k < 2; ++k) {
+    if (!h->ev[0].empty() || !h->ev[1].empty() || !h->ev[2].empty()) (void)hipStreamSynchronize(h->stream);
+    for (int k = 0; k < 3; ++k) {
         for (hipEvent_t e : h->ev[k]) (void)hipEventDestroy(e);
         h->ev[k].clear();
         h->ev_used[k] = 0;
@@ -270,7 +287,7 @@ extern "C" {
 int pod_set_kernel_timing(pod_handle* h, int n) {
     if (!h || n < 0 || n > (1 << 20)) return POD_EINVAL;
     release_events(h);
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < 3; ++k) {
         h->ev[k].reserve(2 * static_cast<size_t>(n));
         for (int i = 0; i < 2 * n; ++i) {
             hipEvent_t e;
@@ -282,7 +299,7 @@ int pod_set_kernel_timing(pod_handle* h, int n) {
 }
 
 int pod_get_kernel_time(pod_handle* h, int kind, double* total_ms, int* launches) {
-    if (!h || kind < 0 || kind > 1) return POD_EINVAL;
+    if (!h || kind < 0 || kind > 2) return POD_EINVAL;
     if (hipStreamSynchronize(h->stream) != hipSuccess) return POD_EHIP;
     double tot = 0.0;
     for (int i = 0; i < h->ev_used[kind]; ++i) {
@@ -410,6 +427,7 @@ void pod_free(pod_handle* h) {
     if (h->d_params) (void)hipFree(h->d_params);
     if (h->d_err) (void)hipFree(h->d_err);
     if (h->d_scratch) (void)hipFree(h->d_scratch);
+    if (h->d_mscratch) (void)hipFree(h->d_mscratch);
     if (h->d_facc) (void)hipFree(h->d_facc);
     delete h;
 }

@@ -76,17 +76,24 @@ struct pod_handle {
     int facc_n;
     int facc_dirty;            // a call failed between accumulation and copy-out
     size_t scratch_bytes;
-    // kernel timing: per kernel kind (0 pair stage, 1 per-atom), 2 events per launch
-    std::vector<hipEvent_t> ev[2];
-    int ev_used[2];
+    void* d_mscratch;          // network outputs and gradient partials (separate from d_scratch,
+    size_t mscratch_bytes;     // which the energy kernels reuse within one call)
+    // kernel timing per kernel kind (0 finalize, 1 per-atom, 2 network), 2 events per launch
+    std::vector<hipEvent_t> ev[3];
+    int ev_used[3];
 };
 
 namespace pod {
 // Grow the handle's scratch buffer to at least `bytes` (POD_OK / POD_ENOMEM).
 int ensure_scratch(pod_handle* h, size_t bytes);
+// Same for the network scratch buffer.
+int ensure_mscratch(pod_handle* h, size_t bytes);
 // Force accumulator for N atoms, zero on return (POD_OK / POD_ENOMEM / POD_EHIP).
 int ensure_force_acc(pod_handle* h, int N);
 // Kernel timing around the main per-atom launch (no-ops unless enabled).
 void timing_begin(pod_handle* h, int kind);
 void timing_end(pod_handle* h, int kind);
+// Network forward + input gradient on the handle's stream (x_dtype: POD_F64 / POD_F32).
+int mlp_forward_launch(pod_handle* h, int n, int n_in, const void* X, long ldx, int x_dtype, const float* theta,
+                       const float* mu, const float* isg, float* y, float* dydx);
 }  // namespace pod

@@ -52,6 +52,9 @@ struct KArgs {
     double* part;      // block partials, column-major [10 + M][nblk] (mode 1)
     int want_G;        // block partials of G requested
     int want_back;     // run the backward sweep (forces or virial requested)
+    const float* y_net;  // mode 2: per-atom network energy (N)
+    const float* g_net;  // mode 2: per-atom dy/dD for descriptor columns 1.. (N x n_net)
+    int n_net;
     int* err;
 };
 
@@ -296,6 +299,19 @@ __device__ __forceinline__ void atom_body(const KArgs<T>& g) {
     T eff3[PA + 1];
 #pragma unroll
     for (int n = 0; n <= PA; ++n) eff3[n] = w3[n];
+    if constexpr (MODE == 2) {
+        // network surrogate (eq. (673a)): energy y_i, adjoint weights c + dy/dD_i
+        if (act) {
+            const float* gn = g.g_net + static_cast<size_t>(atom) * g.n_net;
+            if (has2) eff2 += static_cast<T>(gn[m]);
+            if (has3) {
+#pragma unroll
+                for (int n = 0; n <= PA; ++n)
+                    if (n <= P3) eff3[n] += static_cast<T>(gn[P->off3 - 1 + m * (P3 + 1) + n]);
+            }
+            if (q == 0) e += static_cast<double>(g.y_net[atom]);
+        }
+    }
 #pragma unroll
     for (int p = 0; p < KA; ++p)
         if (Tab::build.pb[p] == 0) {
@@ -647,6 +663,7 @@ int fill_args(pod_handle* h, KArgs<T>& a, int N, int P, const void* pos, const d
     a.offsets = offsets; a.nbr_j = nbr_j; a.shift = shift;
     a.coef = nullptr; a.D = nullptr; a.E_atom = nullptr; a.Facc = nullptr; a.gbuf = nullptr; a.part = nullptr;
     a.want_G = 0; a.want_back = 0;
+    a.y_net = nullptr; a.g_net = nullptr; a.n_net = 0;
     a.err = h->d_err;
     return POD_OK;
 }
@@ -668,10 +685,11 @@ int descriptors_impl(pod_handle* h, int N, int P, const void* pos, const double*
     return e == hipSuccess ? POD_OK : POD_EHIP;
 }
 
-template <typename T>
+template <typename T, int MODE = 1>
 int energy_forces_impl(pod_handle* h, int N, int P, const void* pos, const double* cell, const int* offsets,
                        const int* nbr_j, const int* shift, const int* rev, const void* c, void* E_atom, double* E,
-                       void* F, double* W, double* G) {
+                       void* F, double* W, double* G, const float* y_net = nullptr, const float* g_net = nullptr,
+                       int n_net = 0) {
     KArgs<T> a;
     int rc = fill_args<T>(h, a, N, P, pos, cell, offsets, nbr_j, shift);
     if (rc != POD_OK) return rc;
@@ -692,9 +710,10 @@ int energy_forces_impl(pod_handle* h, int N, int P, const void* pos, const doubl
     a.gbuf = gather ? reinterpret_cast<T*>(static_cast<char*>(h->d_scratch) + part_bytes) : nullptr;
     a.want_G = G != nullptr;
     a.want_back = (F != nullptr) || (W != nullptr);
+    a.y_net = y_net; a.g_net = g_net; a.n_net = n_net;
     if (nblk > 0) {
         timing_begin(h, 1);
-        const hipError_t e = dispatch_pa<T, 1>(h->PA, a, h->std_ok != 0, nblk,
+        const hipError_t e = dispatch_pa<T, MODE>(h->PA, a, h->std_ok != 0, nblk,
                                                lds_bytes(h->K, h->PA, sizeof(T), h->M), h->stream);
         timing_end(h, 1);
         if (e != hipSuccess) return POD_EHIP;
@@ -720,6 +739,35 @@ int energy_forces_impl(pod_handle* h, int N, int P, const void* pos, const doubl
         }
     }
     return POD_OK;
+}
+
+// Network surrogate of the 4-body term: descriptors, network forward and
+// input gradient, then energy and adjoint with per-atom weights (mode 2).
+template <typename T>
+int surrogate_impl(pod_handle* h, int N, int P, const void* pos, const double* cell, const int* offsets,
+                   const int* nbr_j, const int* shift, const int* rev, const void* c, const float* theta,
+                   const float* mu, const float* isg, void* E_atom, double* E, void* F, double* W) {
+    const int n_in = h->M - 1;
+    const size_t align = 256;
+    const size_t d_bytes = (static_cast<size_t>(N) * h->M * sizeof(T) + align - 1) / align * align;
+    const size_t y_bytes = (static_cast<size_t>(N) * sizeof(float) + align - 1) / align * align;
+    const size_t g_bytes = static_cast<size_t>(N) * n_in * sizeof(float);
+    float* y = nullptr;
+    float* gr = nullptr;
+    if (N > 0) {
+        int rc = ensure_mscratch(h, d_bytes + y_bytes + g_bytes);
+        if (rc != POD_OK) return rc;
+        char* base = static_cast<char*>(h->d_mscratch);
+        T* D = reinterpret_cast<T*>(base);
+        y = reinterpret_cast<float*>(base + d_bytes);
+        gr = reinterpret_cast<float*>(base + d_bytes + y_bytes);
+        rc = descriptors_impl<T>(h, N, P, pos, cell, offsets, nbr_j, shift, D);
+        if (rc != POD_OK) return rc;
+        rc = mlp_forward_launch(h, N, n_in, D + 1, h->M, h->dtype, theta, mu, isg, y, gr);
+        if (rc != POD_OK) return rc;
+    }
+    return energy_forces_impl<T, 2>(h, N, P, pos, cell, offsets, nbr_j, shift, rev, c, E_atom, E, F, W, nullptr,
+                                    y, gr, n_in);
 }
 
 bool bad_common(pod_handle* h, int N, int P, const void* pos, const int* offsets, const int* nbr_j,
@@ -753,6 +801,21 @@ int pod_energy_forces(pod_handle* h, int N, int P, const void* pos, const double
         return pod::energy_forces_impl<double>(h, N, P, pos, cell, offsets, nbr_j, shift, rev, c, E_atom, E, F, W,
                                                G);
     return pod::energy_forces_impl<float>(h, N, P, pos, cell, offsets, nbr_j, shift, rev, c, E_atom, E, F, W, G);
+}
+
+int pod_energy_forces_surrogate(pod_handle* h, int N, int P, const void* pos, const double* cell,
+                                const int* offsets, const int* nbr_j, const int* shift, const int* rev, const void* c,
+                                const float* theta, const float* mu, const float* inv_sigma, void* E_atom, double* E,
+                                void* F, double* W) {
+    if (pod::bad_common(h, N, P, pos, offsets, nbr_j, shift)) return POD_EINVAL;
+    if (!c || !theta || !mu || !inv_sigma) return POD_EINVAL;
+    if (h->K4 != 0) return POD_EINVAL;
+    if (h->M - 1 < 1 || h->M - 1 > POD_MLP_MAX_IN) return POD_ENOTSUP;
+    if (h->dtype == POD_F64)
+        return pod::surrogate_impl<double>(h, N, P, pos, cell, offsets, nbr_j, shift, rev, c, theta, mu, inv_sigma,
+                                           E_atom, E, F, W);
+    return pod::surrogate_impl<float>(h, N, P, pos, cell, offsets, nbr_j, shift, rev, c, theta, mu, inv_sigma,
+                                      E_atom, E, F, W);
 }
 
 int pod_neighbor_reverse(pod_handle* h, int N, int P, const int* offsets, const int* nbr_j, const int* shift,

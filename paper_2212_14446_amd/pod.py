@@ -23,6 +23,7 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "pod.h")
 
 POD_F64, POD_F32 = 0, 1
 POD_MAX_L, POD_MAX_K, POD_MAX_P = 16, 8, 6
+POD_MLP_HIDDEN, POD_MLP_MAX_IN = 64, 64
 ERRORS = {0: "POD_OK", -1: "POD_EINVAL", -2: "POD_ERANGE", -3: "POD_ENONFINITE", -4: "POD_ENOMEM",
           -5: "POD_EHIP", -6: "POD_ENOTSUP", -7: "POD_ENEIGH"}
 
@@ -76,6 +77,12 @@ def lib():
     L.pod_energy_forces.argtypes = [_vp, i, i, _vp, _dp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
     L.pod_neighbor_reverse.argtypes = [_vp, i, i, _vp, _vp, _vp, _vp]
     L.pod_batch_assemble.argtypes = [_vp, i, i, i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, P(PodTuneC)]
+    lg, f = ctypes.c_long, ctypes.c_float
+    L.pod_mlp_num_params.argtypes = [i]
+    L.pod_mlp_forward.argtypes = [_vp, i, i, _vp, lg, _vp, _vp, _vp, _vp, _vp]
+    L.pod_mlp_train_step.argtypes = [_vp, i, i, _vp, lg, _vp, _vp, _vp, _vp, _vp, _vp, i, f, f, f, f, _vp]
+    L.pod_energy_forces_surrogate.argtypes = [_vp, i, i, _vp, _dp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                              _vp, _vp, _vp]
     L.pod_check.argtypes = [_vp]
     L.pod_set_kernel_timing.argtypes = [_vp, i]
     L.pod_get_kernel_time.argtypes = [_vp, i, _dp, P(i)]
@@ -85,7 +92,8 @@ def lib():
     L.pod_free.restype = None
     for name in ("pod_init", "pod_compute_basis", "pod_num_descriptors", "pod_get_basis", "pod_descriptors",
                  "pod_energy_forces", "pod_check", "pod_set_kernel_timing", "pod_get_kernel_time",
-                 "pod_neighbor_reverse", "pod_batch_assemble"):
+                 "pod_neighbor_reverse", "pod_batch_assemble", "pod_mlp_num_params", "pod_mlp_forward",
+                 "pod_mlp_train_step", "pod_energy_forces_surrogate"):
         getattr(L, name).restype = i
     _lib = L
     return L
@@ -112,6 +120,15 @@ def _ptr(t):
     if not t.is_contiguous():
         raise ValueError("expected a contiguous tensor")
     return ctypes.c_void_p(t.data_ptr())
+
+
+def _ptr_at(t, elem_offset):
+    """Device pointer of element `elem_offset` of a contiguous tensor."""
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous device tensor")
+    if not 0 <= elem_offset < max(t.numel(), 1):
+        raise ValueError("offset outside the tensor")
+    return ctypes.c_void_p(t.data_ptr() + int(elem_offset) * t.element_size())
 
 
 def _cell_ptr(cell):
@@ -228,6 +245,37 @@ def pod_batch_assemble(h: Handle, n_cfg, N, P, cfg_atom_off, pos, cells, offsets
         "pod_batch_assemble")
 
 
+def pod_mlp_num_params(n_in):
+    rc = lib().pod_mlp_num_params(int(n_in))
+    if rc < 0:
+        raise PodError(rc, "pod_mlp_num_params")
+    return rc
+
+
+def pod_mlp_forward(h: Handle, n, n_in, X, ldx, theta, mu, inv_sigma, y=None, dydx=None, x_col=0):
+    """X: contiguous device tensor in the handle dtype; the network reads
+    X.flat[i * ldx + x_col + k]."""
+    xp = _ptr_at(X, x_col) if n > 0 else _ptr(X)
+    _ok(lib().pod_mlp_forward(h.ptr, int(n), int(n_in), xp, int(ldx), _ptr(theta), _ptr(mu), _ptr(inv_sigma),
+                              _ptr(y), _ptr(dydx)), "pod_mlp_forward")
+
+
+def pod_mlp_train_step(h: Handle, n, n_in, X, ldx, target, mu, inv_sigma, theta, m, v, step, lr, beta1=0.9,
+                       beta2=0.999, eps=1e-8, loss=None):
+    _ok(lib().pod_mlp_train_step(h.ptr, int(n), int(n_in), _ptr(X), int(ldx), _ptr(target), _ptr(mu),
+                                 _ptr(inv_sigma), _ptr(theta), _ptr(m), _ptr(v), int(step), float(lr), float(beta1),
+                                 float(beta2), float(eps), _ptr(loss)), "pod_mlp_train_step")
+
+
+def pod_energy_forces_surrogate(h: Handle, N, P, pos, cell, offsets, nbr_j, shift, c, theta, mu, inv_sigma,
+                                E_atom=None, E=None, F=None, W=None, rev=None):
+    arr, cp = _cell_ptr(cell)
+    _ok(lib().pod_energy_forces_surrogate(h.ptr, int(N), int(P), _ptr(pos), cp, _ptr(offsets), _ptr(nbr_j),
+                                          _ptr(shift), _ptr(rev), _ptr(c), _ptr(theta), _ptr(mu), _ptr(inv_sigma),
+                                          _ptr(E_atom), _ptr(E), _ptr(F), _ptr(W)),
+        "pod_energy_forces_surrogate")
+
+
 def pod_check(h: Handle):
     _ok(lib().pod_check(h.ptr), "pod_check")
 
@@ -323,6 +371,27 @@ class PodModel:
         }
         pod_energy_forces(self.h, N, nbrs.P, pos, cell, nbrs.offsets, nbrs.nbr_j, nbrs.shift, c,
                           o["E_atom"], o["E"], o["F"], o["W"], o["G"], rev=nbrs.rev)
+        if check:
+            pod_check(self.h)
+        return o
+
+    def energy_forces_surrogate(self, pos, cell, nbrs: DeviceNeighbors, c, net, forces=True, virial=True,
+                                per_atom=True, check=True, out=None):
+        """Energy and forces with the network `net` (surrogate.Network) in
+        place of the 4-body term; this model must have K4 = 0."""
+        import torch
+        pos = self._pos(pos)
+        c = torch.as_tensor(c, dtype=self.torch_dtype, device=self.device).contiguous()
+        N = nbrs.N
+        o = out if out is not None else {
+            "E": torch.empty(1, dtype=torch.float64, device=self.device),
+            "E_atom": torch.empty(N, dtype=self.torch_dtype, device=self.device) if per_atom else None,
+            "F": torch.empty((N, 3), dtype=self.torch_dtype, device=self.device) if forces else None,
+            "W": torch.empty((3, 3), dtype=torch.float64, device=self.device) if virial else None,
+        }
+        pod_energy_forces_surrogate(self.h, N, nbrs.P, pos, cell, nbrs.offsets, nbrs.nbr_j, nbrs.shift, c,
+                                    net.theta, net.mu, net.inv_sigma, o["E_atom"], o["E"], o["F"], o["W"],
+                                    rev=nbrs.rev)
         if check:
             pod_check(self.h)
         return o
