@@ -9,9 +9,12 @@ and global descriptors, with inputs already resident in HBM.
 Prints one JSON line (rank 0).  Extra objects: ``roofline`` for the main
 per-atom kernel (timed with HIP events inside the library, on its stream),
 ``cpu_baseline`` (the FP64 oracle on the host, single thread), ``f32``
-(the same workload on the FP32 path) and ``batch`` (the batched
+(the same workload on the FP32 path), ``batch`` (the batched
 descriptor-matrix assembly of 2,000 uneven cells with dG/dR, FP64, at the
-autotuner's launch shape).
+autotuner's launch shape) and ``surrogate`` (the 4-body network surrogate:
+trained on the exact 4-body energies of 19 displaced 54,000-atom boxes, then
+timed and scored against exact FP32 2/3/4-body energies and forces on a
+1,024,000-atom box, beside the 2/3-body model without it).
 """
 from __future__ import annotations
 
@@ -170,6 +173,85 @@ def run_batch(steps, warmup):
                          "frac": ach / PEAK_F64, "flops_per_launch": f["total"]}}
 
 
+PEAK_BF16 = 2.5e15     # dense bfloat16 MFMA peak
+
+
+def run_surrogate(steps, epochs=30):
+    """Config-5 experiment, all on the device through the library."""
+    import itertools
+
+    import torch
+
+    from paper_2212_14446_amd import pod, surrogate, workloads as wl
+    S, S23 = wl.SETUP_CFG5, wl.SETUP_CFG5_23
+    n_in = S23.M - 1
+    m64 = pod.PodModel(pod.setup_from_workload(S), "f64")
+    gen = wl.config5_train_boxes()
+    first = next(gen)
+    nb0 = pod.DeviceNeighbors.from_list(first[2])
+    c = wl.standardised_coefficients(m64.descriptors(first[0], first[1], nb0).cpu().numpy(), S, seed=9)
+    t0 = time.perf_counter()
+    X, T = surrogate.four_body_dataset(m64, ((p, cl, nl) for p, cl, nl, _ in itertools.chain([first], gen)), c,
+                                       n_in)
+    t_data = time.perf_counter() - t0
+    m23 = pod.PodModel(pod.setup_from_workload(S23), "f32")
+    net = surrogate.Network(n_in, seed=1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist = surrogate.fit(m23.h, net, X, T, epochs=epochs, batch=8192, lr=3e-3, seed=2)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    y, _ = net.forward(m23.h, X, grad=False)
+    e_train = float(torch.sqrt(((y - T) ** 2).mean()))
+    print(f"[bench] surrogate trained on {X.shape[0]} environments in {t_train:.2f} s "
+          f"(data {t_data:.1f} s), energy rmse {e_train:.4f} eV", file=sys.stderr, flush=True)
+    del X, T, y
+    w = wl.config5_infer()
+    nb = pod.DeviceNeighbors.from_list(w.nl)
+    m32 = pod.PodModel(pod.setup_from_workload(S), "f32")
+    nb.build_reverse(m32)
+    c23 = c[: S23.M].copy()
+    pos = torch.tensor(w.pos, dtype=torch.float32, device="cuda")
+
+    def timed(fn, model):
+        o = fn()
+        torch.cuda.synchronize()
+        pod.pod_set_kernel_timing(model.h, steps)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        kt = {k: pod.pod_get_kernel_time(model.h, k) for k in (0, 1, 2)}
+        pod.pod_set_kernel_timing(model.h, 0)
+        model.check()
+        return o, e0.elapsed_time(e1) / steps, {k: (v[0] / v[1] if v[1] else 0.0) for k, v in kt.items()}
+
+    ex, t_ex, _ = timed(lambda: m32.energy_forces(pos, w.cell, nb, c, virial=False, global_desc=False,
+                                                  check=False), m32)
+    su, t_su, k_su = timed(lambda: m23.energy_forces_surrogate(pos, w.cell, nb, c23, net, virial=False,
+                                                               check=False), m23)
+    n4, t_n4, _ = timed(lambda: m23.energy_forces(pos, w.cell, nb, c23, virial=False, global_desc=False,
+                                                  check=False), m23)
+    rm = lambda a, b: float(torch.sqrt(((a.double() - b.double()) ** 2).mean()))
+    f_net = 2 * (n_in * 64 + 64 * 64 + 64) + 2 * (64 * 64 + 64 * n_in)   # forward + input gradient per atom
+    net_ms = k_su[2]
+    ach = f_net * w.N / (net_ms * 1e-3) if net_ms > 0 else 0.0
+    return {"workload": f"{w.name}: {w.N} atoms, {w.nl.n_pairs} pairs, FP32",
+            "train": {"environments": 19 * 54000, "boxes": 19, "epochs": epochs, "batch": 8192,
+                      "seconds": t_train, "energy_rmse_eV": e_train, "final_loss_std_units": hist[-1]},
+            "ms_exact": t_ex, "ms_surrogate": t_su, "ms_without_4body": t_n4,
+            "speedup_vs_exact": t_ex / t_su, "speedup_ceiling_free_network": t_ex / t_n4,
+            "atoms_per_s_exact": w.N / (t_ex * 1e-3), "atoms_per_s_surrogate": w.N / (t_su * 1e-3),
+            "force_rmse_eV_per_A": {"surrogate": rm(su["F"], ex["F"]), "without_4body": rm(n4["F"], ex["F"])},
+            "energy_rmse_eV_per_atom": {"surrogate": rm(su["E_atom"], ex["E_atom"]),
+                                        "without_4body": rm(n4["E_atom"], ex["E_atom"])},
+            "surrogate_kernels_ms": {"per_atom_kernels": k_su[1], "network": k_su[2], "finalize": k_su[0]},
+            "network_mfma": {"bound": "mfma", "achieved": ach / 1e12, "peak": PEAK_BF16 / 1e12, "unit": "TFLOP/s",
+                             "frac": ach / PEAK_BF16, "flops_per_atom": f_net}}
+
+
 def cpu_baseline(w):
     """The FP64 oracle (as written) on the host, one thread, full workload."""
     from threadpoolctl import threadpool_limits
@@ -196,6 +278,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-f32", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (a known-size "
                          "kernel for scaling hardware traffic counters)")
@@ -246,6 +329,9 @@ def main():
     if not args.no_batch:
         rec["batch"] = run_batch(10, 2)
         print(f"[bench] batch {rec['batch']}", file=sys.stderr, flush=True)
+    if not args.no_surrogate:
+        rec["surrogate"] = run_surrogate(20)
+        print(f"[bench] surrogate {rec['surrogate']}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         rec["cpu_baseline"] = cpu_baseline(w)

@@ -22,16 +22,19 @@
  *     offsets[N] = P, non-decreasing), nbr_j[P] in [0, N), shift[P] packing the
  *     periodic image n as three signed bytes (n_x | n_y << 8 | n_z << 16).
  *     r_ij = pos[j] + n_x a1 + n_y a2 + n_z a3 - pos[i], a_k the rows of cell.
- *     The list is full (both directions); every pair must satisfy
- *     rin < |r_ij| < rcut.  Periodic self-images (i == j, n != 0) are allowed.
+ *     The list is full (both directions).  Pairs with |r_ij| >= rcut are not
+ *     neighbours (Sec. II.A) and contribute nothing, so a list built with a
+ *     skin distance can be reused while atoms move; a pair with
+ *     |r_ij| <= rin is a data error.  Periodic self-images (i == j, n != 0)
+ *     are allowed.
  *   - pos: N x 3 row-major device array in the handle's dtype.
  *   - cell: 9 doubles in HOST memory, lattice vectors as rows; NULL for an open
  *     system (all shifts must then be zero).
  *   - Device pointers are caller-owned; the library never frees them.  All
  *     compute calls are asynchronous on the handle's HIP stream.
  *   - Errors: 0 = OK, negative POD_E* codes.  Argument errors are reported by
- *     the call itself; errors found in the data on the device (a pair outside
- *     (rin, rcut), a non-finite coordinate, a malformed list) are latched in a
+ *     the call itself; errors found in the data on the device (a pair at or
+ *     inside rin, a non-finite coordinate, a malformed list) are latched in a
  *     device error word and reported by pod_check().  Offending pairs or atoms
  *     are skipped, never read out of bounds.  Nothing aborts across the ABI.
  *   - One handle per stream; calls on one handle must not overlap.
@@ -45,7 +48,7 @@ extern "C" {
 
 #define POD_OK 0
 #define POD_EINVAL (-1)      /* invalid argument or parameter */
-#define POD_ERANGE (-2)      /* a pair distance outside (rin, rcut) */
+#define POD_ERANGE (-2)      /* a pair distance at or below rin */
 #define POD_ENONFINITE (-3)  /* a non-finite coordinate */
 #define POD_ENOMEM (-4)      /* device allocation failed */
 #define POD_EHIP (-5)        /* a HIP runtime call failed */

@@ -195,8 +195,8 @@ __global__ __launch_bounds__(MAX_THREADS) void batch_kernel(BArgs g) {
                     atomicOr(g.err, ERR_NONFINITE);
                 } else {
                     const double rr = sqrt(r2);
-                    if (rr <= rin || rr >= rcut) atomicOr(g.err, ERR_RANGE);
-                    else { r = rr; ok = true; }
+                    if (rr <= rin) atomicOr(g.err, ERR_RANGE);
+                    else if (rr < rcut) { r = rr; ok = true; }   // beyond rcut: not a neighbour
                 }
             }
             const double ri = 1.0 / r;

@@ -410,7 +410,7 @@ const char* pod_strerror(int code) {
     switch (code) {
         case POD_OK: return "ok";
         case POD_EINVAL: return "invalid argument";
-        case POD_ERANGE: return "pair distance outside (rin, rcut)";
+        case POD_ERANGE: return "pair distance at or below rin";
         case POD_ENONFINITE: return "non-finite coordinate";
         case POD_ENOMEM: return "device allocation failed";
         case POD_EHIP: return "HIP runtime error";

@@ -107,10 +107,11 @@ __device__ __forceinline__ bool slot_geometry(const KArgs<T>& g, bool valid, con
         return false;
     }
     const T rr = d_sqrt(r2);
-    if (rr <= g.prm->rin || rr >= g.prm->rcut) {
+    if (rr <= g.prm->rin) {
         if (report) atomicOr(g.err, ERR_RANGE);
         return false;
     }
+    if (rr >= g.prm->rcut) return false;   // not a neighbour (Sec. II.A): no contribution
     d[0] = d0; d[1] = d1; d[2] = d2;
     r = rr;
     return true;

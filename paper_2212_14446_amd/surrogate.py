@@ -104,3 +104,23 @@ def fit(h: pod.Handle, net: Network, X, target, epochs: int = 20, batch: int = 8
             print(f"[fit] epoch {ep + 1}/{epochs} loss {history[-1]:.4e}", flush=True)
     net.fold_output_scale(t_std, t_mean)
     return history
+
+
+def four_body_dataset(model, boxes, c, n_in: int):
+    """Training rows from full 2/3/4-body systems: inputs are the 2/3-body
+    descriptors (columns 1..n_in of D) and labels the exact per-atom 4-body
+    energies sum_{k in 4-body} c_k D_ik, both computed by the library
+    (pod_descriptors, and pod_energy_forces with the 4-body coefficients
+    only).  model: FP64 PodModel with 4-body terms; boxes: iterable of
+    (pos, cell, neighbour list).  Returns (X FP32 [n, n_in], E4 FP32 [n])."""
+    import torch
+    c4 = np.array(c, dtype=np.float64)
+    c4[: n_in + 1] = 0.0
+    Xs, Ts = [], []
+    for pos, cell, nl in boxes:
+        nb = pod.DeviceNeighbors.from_list(nl)
+        D = model.descriptors(pos, cell, nb)
+        o = model.energy_forces(pos, cell, nb, c4, forces=False, virial=False, global_desc=False)
+        Xs.append(D[:, 1:n_in + 1].float())
+        Ts.append(o["E_atom"].float())
+    return torch.cat(Xs).contiguous(), torch.cat(Ts).contiguous()

@@ -288,6 +288,32 @@ def config4() -> Workload:
     return Workload("bcc30_54000_s0.2", pos, cell, nl, s, np.zeros(s.M))
 
 
+SETUP_CFG5 = PodSetup(rin=0.5, rcut=5.0, L=8, K2=6, K3=6, K4=6, P3=4, P4=4)
+SETUP_CFG5_23 = PodSetup(rin=0.5, rcut=5.0, L=8, K2=6, K3=6, K4=0, P3=4, P4=0)
+
+
+def config5_train_boxes(n_boxes: int = 19, seed: int = 9):
+    """Training environments for the 4-body surrogate: n_boxes BCC 30^3
+    boxes (54,000 atoms each), each displaced with its own sigma drawn
+    uniformly from [0.05, 0.3] A.  Yields (pos, cell, nl, sigma)."""
+    rng = np.random.default_rng(seed)
+    sigmas = rng.uniform(0.05, 0.3, size=n_boxes)
+    seeds = rng.integers(1, 1 << 31, size=n_boxes)
+    base, cell = bcc(30)
+    for k in range(n_boxes):
+        pos = displace(base, float(sigmas[k]), int(seeds[k]))
+        yield pos, cell, neighbor_list(pos, cell, SETUP_CFG5.rcut), float(sigmas[k])
+
+
+def config5_infer() -> Workload:
+    """1,024,000-atom BCC box (80^3 cells), sigma 0.15 A, for surrogate
+    inference."""
+    pos, cell = bcc(80)
+    pos = displace(pos, 0.15, 10)
+    nl = neighbor_list(pos, cell, SETUP_CFG5.rcut)
+    return Workload("bcc80_1024000_s0.15", pos, cell, nl, SETUP_CFG5, np.zeros(SETUP_CFG5.M))
+
+
 def standardised_coefficients(D, setup: PodSetup, seed: int, targets=(1.0, 0.3, 0.1)):
     """Coefficients c_m = z_m s_b / (sigma_m sqrt(n_b)) with z ~ N(0, 1),
     sigma_m the standard deviation of descriptor m over the rows of D and

@@ -94,12 +94,44 @@ def _raises(code, fn):
     assert pod.ERRORS[ei.value.code] == code, ei.value
 
 
-def test_error_pair_beyond_cutoff():
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_skin_list_equals_exact_list(dtype):
+    """Pairs at or beyond rcut are not neighbours: a list built with a skin
+    (rcut + 0.6 A) gives the results of the exact list, on every output and
+    both force paths."""
     pos, cell = _small()
-    nl = wl.neighbor_list(pos, cell, 5.6)      # list built for a larger cut-off
+    exact = wl.neighbor_list(pos, cell, S.rcut)
+    skin = wl.neighbor_list(pos, cell, S.rcut + 0.6)
+    assert skin.n_pairs > exact.n_pairs
+    m = _model(dtype)
+    c = wl.coefficients(S.M, 3)
+    say(f"[gpu] edge: skin list {skin.n_pairs} pairs vs exact {exact.n_pairs} ({dtype})")
+    out = []
+    for nl in (exact, skin):
+        nb = pod.DeviceNeighbors.from_list(nl)
+        D = m.descriptors(pos, cell, nb).double().cpu().numpy()
+        o = m.energy_forces(pos, cell, nb, c)
+        nb.build_reverse(m)
+        o2 = m.energy_forces(pos, cell, nb, c)
+        out.append((D, {k: v.double().cpu().numpy() for k, v in o.items()}, o2["F"].double().cpu().numpy()))
+    tol = 1e-12 if dtype == "f64" else 1e-5
+    assert colerr(out[1][0], out[0][0]) < tol
+    for k in ("E", "E_atom", "F", "W", "G"):
+        assert relerr(out[1][1][k], out[0][1][k]) < tol, k
+    assert relerr(out[1][2], out[0][2]) < tol
+
+
+def test_error_pair_inside_rin():
+    pos, cell = _small()
+    pos = pos.copy()
+    nl = wl.neighbor_list(pos, cell, S.rcut)
+    j = int(nl.nbr_j[0])
+    assert j != 0
+    sh = nl.shift3[0] @ cell
+    pos[0] = pos[j] + sh - np.array([0.3, 0.0, 0.0])     # |r_0j| = 0.3 A < rin
     m = _model()
     nb = pod.DeviceNeighbors.from_list(nl)
-    say("[gpu] edge: ERANGE")
+    say("[gpu] edge: ERANGE (pair inside rin)")
     _raises("POD_ERANGE", lambda: m.descriptors(pos, cell, nb))
     _raises("POD_ERANGE", lambda: m.energy_forces(pos, cell, nb, np.ones(m.M)))
     m.check()   # the error word was cleared

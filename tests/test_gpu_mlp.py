@@ -269,3 +269,31 @@ def test_surrogate_rejects_four_body_handle(sur_case):
         m.energy_forces_surrogate(w.pos, w.cell, nb, np.zeros(m.M), net)
     assert e.value.code == -1
     torch.cuda.synchronize()
+
+
+def test_surrogate_learns_four_body_forces():
+    """Trained on the exact 4-body energies of six displaced BCC boxes, the
+    surrogate's forces on a seventh box are much closer to the exact 2/3/4-body
+    forces than the 2/3-body model without it."""
+    import torch
+    S, S23 = wl.SETUP_CFG5, wl.SETUP_CFG5_23
+    m64 = pod.PodModel(pod.setup_from_workload(S), "f64")
+    boxes = []
+    for k, sig in enumerate((0.08, 0.15, 0.25, 0.12, 0.2, 0.28, 0.17)):
+        pos, cell = wl.bcc(10)
+        pos = wl.displace(pos, sig, 300 + k)
+        boxes.append((pos, cell, wl.neighbor_list(pos, cell, S.rcut)))
+    nb0 = pod.DeviceNeighbors.from_list(boxes[0][2])
+    c = wl.standardised_coefficients(m64.descriptors(boxes[0][0], boxes[0][1], nb0).cpu().numpy(), S, seed=31)
+    X, T = surrogate.four_body_dataset(m64, boxes[:-1], c, 36)
+    m23 = pod.PodModel(pod.setup_from_workload(S23), "f64")
+    net = surrogate.Network(36, seed=5)
+    surrogate.fit(m23.h, net, X, T, epochs=60, batch=512, lr=3e-3, seed=6)
+    pos, cell, nl = boxes[-1]
+    nb = pod.DeviceNeighbors.from_list(nl)
+    ex = m64.energy_forces(pos, cell, nb, c)["F"]
+    su = m23.energy_forces_surrogate(pos, cell, nb, c[:37], net)["F"]
+    n4 = m23.energy_forces(pos, cell, nb, c[:37])["F"]
+    rm = lambda a, b: float(torch.sqrt(((a - b) ** 2).mean()))
+    say(f"[gpu] learned surrogate: force rmse {rm(su, ex):.4f} eV/A, without 4-body {rm(n4, ex):.4f} eV/A")
+    assert rm(su, ex) < 0.3 * rm(n4, ex)
