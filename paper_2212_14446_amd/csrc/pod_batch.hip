@@ -38,7 +38,7 @@ constexpr int MAX_THREADS = 512;
 constexpr size_t LDS_LIMIT = 64 * 1024;
 
 struct BArgs {
-    const ParamsT<double>* prm;
+    ParamsT<double> prm;  // by value: read with scalar loads
     int n_cfg;
     const int* order;     // processing order of the cells
     const int* cfg_off;   // n_cfg + 1 atom offsets
@@ -135,7 +135,7 @@ __global__ __launch_bounds__(MAX_THREADS) void batch_kernel(BArgs g) {
     constexpr int KA = Tab::KA;
     constexpr int NT = Tab::NT;
 
-    const ParamsT<double>* __restrict__ P = g.prm;
+    const ParamsT<double>* __restrict__ P = &g.prm;
     const int K = P->K, M = P->M;
     const int SR = 4 + 2 * K;
     const int nth = blockDim.x;
@@ -429,7 +429,7 @@ int pod_batch_assemble(pod_handle* h, int n_cfg, int N, int P, const int* cfg_at
     if (hipMemcpyAsync(d_order, order.data(), sizeof(int) * n_cfg, hipMemcpyHostToDevice, h->stream) != hipSuccess)
         return POD_EHIP;
     BArgs a;
-    a.prm = static_cast<const ParamsT<double>*>(h->d_params);
+    a.prm = h->hp_d;
     a.n_cfg = n_cfg; a.order = d_order; a.cfg_off = cfg_atom_off;
     a.pos = static_cast<const double*>(pos); a.cells = cells;
     a.offsets = offsets; a.nbr_j = nbr_j; a.shift = shift;

@@ -358,23 +358,17 @@ int pod_init(const pod_params* p, void* hip_stream, pod_handle** out) {
         for (int l = 0; l < p->L; ++l)
             for (int k = 0; k < h->K; ++k) h->Q[l * h->K + k] = qfull[l * p->L + k];
     }
-    const size_t pbytes = h->dtype == POD_F64 ? sizeof(pod::ParamsT<double>) : sizeof(pod::ParamsT<float>);
-    if (hipMalloc(&h->d_params, pbytes) != hipSuccess) { delete h; return POD_ENOMEM; }
     if (hipMalloc(reinterpret_cast<void**>(&h->d_err), sizeof(int)) != hipSuccess) {
-        (void)hipFree(h->d_params); delete h; return POD_ENOMEM;
+        delete h; return POD_ENOMEM;
     }
-    hipError_t e1, e2;
     if (h->dtype == POD_F64) {
-        pod::ParamsT<double> d; fill_params(h, d);
-        h->std_ok = d.std_ok;
-        e1 = hipMemcpy(h->d_params, &d, sizeof(d), hipMemcpyHostToDevice);
+        fill_params(h, h->hp_d);
+        h->std_ok = h->hp_d.std_ok;
     } else {
-        pod::ParamsT<float> d; fill_params(h, d);
-        h->std_ok = d.std_ok;
-        e1 = hipMemcpy(h->d_params, &d, sizeof(d), hipMemcpyHostToDevice);
+        fill_params(h, h->hp_f);
+        h->std_ok = h->hp_f.std_ok;
     }
-    e2 = hipMemset(h->d_err, 0, sizeof(int));
-    if (e1 != hipSuccess || e2 != hipSuccess) { pod_free(h); return POD_EHIP; }
+    if (hipMemset(h->d_err, 0, sizeof(int)) != hipSuccess) { pod_free(h); return POD_EHIP; }
     *out = h;
     return POD_OK;
 }
@@ -424,7 +418,6 @@ void pod_free(pod_handle* h) {
     if (!h) return;
     release_events(h);
     (void)hipStreamSynchronize(h->stream);
-    if (h->d_params) (void)hipFree(h->d_params);
     if (h->d_err) (void)hipFree(h->d_err);
     if (h->d_scratch) (void)hipFree(h->d_scratch);
     if (h->d_mscratch) (void)hipFree(h->d_mscratch);

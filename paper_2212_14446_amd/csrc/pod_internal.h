@@ -69,7 +69,10 @@ struct pod_handle {
     std::vector<double> alpha, beta, gamma, kappa;
     std::vector<double> Q;     // L x K row-major
     std::vector<double> eig;   // L
-    void* d_params;            // ParamsT<T>
+    // parameter block of the kernels, passed by value in their arguments
+    // (scalar loads through the constant cache); the member for the dtype
+    pod::ParamsT<double> hp_d;
+    pod::ParamsT<float> hp_f;
     int* d_err;
     void* d_scratch;           // block partial sums
     double* d_facc;            // force accumulator, 3 x facc_n doubles, zero between calls

@@ -37,7 +37,7 @@ using namespace dev;
 
 template <typename T>
 struct KArgs {
-    const ParamsT<T>* prm;
+    ParamsT<T> prm;    // by value: read with scalar loads
     int N, P;
     const T* pos;
     CellT<T> cell;
@@ -90,7 +90,7 @@ template <typename T>
 __device__ __forceinline__ bool slot_geometry(const KArgs<T>& g, bool valid, const SlotIdx& s, const T (&pj)[3],
                                               const T (&pi)[3], bool report, T (&d)[3], T& r) {
     d[0] = d[1] = d[2] = T(0);
-    r = T(0.5) * (g.prm->rin + g.prm->rcut);
+    r = T(0.5) * (g.prm.rin + g.prm.rcut);
     if (!valid) return false;
     if (s.j < 0 || s.j >= g.N || (!g.cell.periodic && (s.sh & 0xFFFFFF) != 0)) {
         if (report) atomicOr(g.err, ERR_NEIGH);
@@ -107,11 +107,11 @@ __device__ __forceinline__ bool slot_geometry(const KArgs<T>& g, bool valid, con
         return false;
     }
     const T rr = d_sqrt(r2);
-    if (rr <= g.prm->rin) {
+    if (rr <= g.prm.rin) {
         if (report) atomicOr(g.err, ERR_RANGE);
         return false;
     }
-    if (rr >= g.prm->rcut) return false;   // not a neighbour (Sec. II.A): no contribution
+    if (rr >= g.prm.rcut) return false;   // not a neighbour (Sec. II.A): no contribution
     d[0] = d0; d[1] = d1; d[2] = d2;
     r = rr;
     return true;
@@ -160,7 +160,7 @@ __device__ __forceinline__ void atom_body(const KArgs<T>& g) {
     constexpr int KA = Tab::KA;
     constexpr int NT = Tab::NT;
 
-    const ParamsT<T>* __restrict__ P = g.prm;
+    const ParamsT<T>* __restrict__ P = &g.prm;
     const int K = P->K;
     const int M = P->M;
     const int SS = stage_stride(K);
@@ -650,9 +650,16 @@ hipError_t dispatch_pa(int PA, const KArgs<T>& a, bool fast, int nblk, size_t ld
 size_t lds_bytes(int K, int PA, size_t tsize, int M) { return atom_lds_layout(K, n_mono(PA), M, tsize).total; }
 
 template <typename T>
+const ParamsT<T>& host_params(const pod_handle* h);
+template <>
+const ParamsT<double>& host_params<double>(const pod_handle* h) { return h->hp_d; }
+template <>
+const ParamsT<float>& host_params<float>(const pod_handle* h) { return h->hp_f; }
+
+template <typename T>
 int fill_args(pod_handle* h, KArgs<T>& a, int N, int P, const void* pos, const double* cell, const int* offsets,
               const int* nbr_j, const int* shift) {
-    a.prm = static_cast<const ParamsT<T>*>(h->d_params);
+    a.prm = host_params<T>(h);
     a.N = N; a.P = P;
     a.pos = static_cast<const T*>(pos);
     a.cell.periodic = cell != nullptr;
