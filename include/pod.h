@@ -125,8 +125,11 @@ int pod_neighbor_reverse(pod_handle* h, int N, int P, const int* offsets, const 
 /* Linear POD energy and its derivatives (eqs. (57a), (58a), (26c), (24c)).
  *   rev    : reverse-pair index from pod_neighbor_reverse, or NULL.  With it,
  *            forces are gathered per atom, F_n = sum_{p in N(n)} (g_p - g_rev(p))
- *            with g_p = dE_i/dr_ij, in a fixed order (bitwise reproducible);
- *            without it they are accumulated with FP64 atomics.
+ *            with g_p = dE_i/dr_ij, in a fixed order (bitwise reproducible):
+ *            each g_p is stored at slot rev(p), so atom n's gather reads its
+ *            own list range.  rev must be the list's reverse index (a pair
+ *            without a reverse latches POD_ENEIGH).  Without rev, forces are
+ *            accumulated with FP64 atomics.
  *   c      : M coefficients (device, handle dtype)
  *   E_atom : N per-atom energies (device, handle dtype) or NULL
  *   E      : total energy (device, 1 double) or NULL

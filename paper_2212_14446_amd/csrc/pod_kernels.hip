@@ -48,7 +48,9 @@ struct KArgs {
     T* D;              // descriptors (mode 0)
     T* E_atom;         // per-atom energy or null (mode 1)
     double* Facc;      // force accumulator (3N, zero on entry) (mode 1, backward, no gbuf)
-    T* gbuf;           // per-pair gradients dE_i/dr_ij (3P) when a reverse index is given
+    T* gbuf;           // gather path: g_ij stored at the reverse slot rev[p] (3P)
+    double* fown;      // gather path: own-atom force sum_j g_ij (3N)
+    const int* rev;    // reverse-pair index (gather path)
     double* part;      // block partials, column-major [10 + M][nblk] (mode 1)
     int want_G;        // block partials of G requested
     int want_back;     // run the backward sweep (forces or virial requested)
@@ -64,13 +66,17 @@ struct KArgs {
 struct SlotIdx {
     int j;    // neighbour index, -1 for an empty slot
     int sh;   // packed image shift
+    int rv;   // reverse pair (gather path), -1 otherwise
 };
 
 template <typename T>
 __device__ __forceinline__ SlotIdx slot_index(const KArgs<T>& g, bool valid, int p) {
     SlotIdx s;
-    s.j = -1; s.sh = 0;
-    if (valid) { s.j = g.nbr_j[p]; s.sh = g.shift[p]; }
+    s.j = -1; s.sh = 0; s.rv = -1;
+    if (valid) {
+        s.j = g.nbr_j[p]; s.sh = g.shift[p];
+        if (g.rev) s.rv = g.rev[p];
+    }
     return s;
 }
 
@@ -443,23 +449,28 @@ __device__ __forceinline__ void atom_body(const KArgs<T>& g) {
                     }
                 }
                 if (g.gbuf) {
-                    T* gp3 = g.gbuf + 3 * static_cast<size_t>(beg + slot);
-                    gp3[0] = gx; gp3[1] = gy; gp3[2] = gz;
+                    // stored at the reverse slot: the neighbour's gather reads its own list range
+                    if (ic.rv >= 0 && ic.rv < g.P) {
+                        T* gp3 = g.gbuf + 3 * static_cast<size_t>(ic.rv);
+                        gp3[0] = gx; gp3[1] = gy; gp3[2] = gz;
+                    } else {
+                        atomicOr(g.err, ERR_NEIGH);
+                    }
                 } else {
                     const int j = ic.j;
                     atomicAdd(&g.Facc[3 * j + 0], -static_cast<double>(gx));
                     atomicAdd(&g.Facc[3 * j + 1], -static_cast<double>(gy));
                     atomicAdd(&g.Facc[3 * j + 2], -static_cast<double>(gz));
-                    fo0 += gx; fo1 += gy; fo2 += gz;
                 }
+                fo0 += gx; fo1 += gy; fo2 += gz;
                 const double dd3[3] = {double(d[0]), double(d[1]), double(d[2])};
                 const double gg[3] = {double(gx), double(gy), double(gz)};
 #pragma unroll
                 for (int x = 0; x < 3; ++x)
 #pragma unroll
                     for (int y = 0; y < 3; ++y) vir[3 * x + y] -= dd3[x] * gg[y];
-            } else if (g.gbuf) {
-                T* gp3 = g.gbuf + 3 * static_cast<size_t>(beg + slot);
+            } else if (g.gbuf && ic.rv >= 0 && ic.rv < g.P) {
+                T* gp3 = g.gbuf + 3 * static_cast<size_t>(ic.rv);
                 gp3[0] = T(0); gp3[1] = T(0); gp3[2] = T(0);
             }
         }
@@ -467,15 +478,21 @@ __device__ __forceinline__ void atom_body(const KArgs<T>& g) {
     // own-atom force F_i += sum_j g_ij: sum the K lanes of the atom
     sF[3 * lane + 0] = fo0; sF[3 * lane + 1] = fo1; sF[3 * lane + 2] = fo2;
     __syncthreads();
-    if (act && q == 0 && !g.gbuf) {
+    if (act && q == 0) {
         double f0 = 0.0, f1 = 0.0, f2 = 0.0;
         for (int k = 0; k < K; ++k) {
             const int l2 = al * K + k;
             f0 += sF[3 * l2]; f1 += sF[3 * l2 + 1]; f2 += sF[3 * l2 + 2];
         }
-        atomicAdd(&g.Facc[3 * atom + 0], f0);
-        atomicAdd(&g.Facc[3 * atom + 1], f1);
-        atomicAdd(&g.Facc[3 * atom + 2], f2);
+        if (g.gbuf) {
+            g.fown[3 * atom + 0] = f0;
+            g.fown[3 * atom + 1] = f1;
+            g.fown[3 * atom + 2] = f2;
+        } else {
+            atomicAdd(&g.Facc[3 * atom + 0], f0);
+            atomicAdd(&g.Facc[3 * atom + 1], f1);
+            atomicAdd(&g.Facc[3 * atom + 2], f2);
+        }
     }
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
@@ -512,7 +529,8 @@ struct FinArgs {
     double* Facc;
     T* F;
     long n3;
-    const T* gbuf;
+    const T* gbuf;     // gather path: g stored at reverse slots
+    const double* fown;  // gather path: own-atom sums
     const int* rev;
     const int* offsets;
     int N, P;
@@ -531,18 +549,11 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinArgs<T> f) {
             if (a < f.N) {
                 const int b = f.offsets[a], e = f.offsets[a + 1];
                 if (b >= 0 && e >= b && e <= f.P) {
+                    // slot p of atom a holds g of the pair (j -> a) whose reverse is p
                     for (int p = b + s0; p < e; p += 32) {
-                        const int q = f.rev[p];
-                        f0 += static_cast<double>(f.gbuf[3 * static_cast<size_t>(p) + 0]);
-                        f1 += static_cast<double>(f.gbuf[3 * static_cast<size_t>(p) + 1]);
-                        f2 += static_cast<double>(f.gbuf[3 * static_cast<size_t>(p) + 2]);
-                        if (q >= 0 && q < f.P) {
-                            f0 -= static_cast<double>(f.gbuf[3 * static_cast<size_t>(q) + 0]);
-                            f1 -= static_cast<double>(f.gbuf[3 * static_cast<size_t>(q) + 1]);
-                            f2 -= static_cast<double>(f.gbuf[3 * static_cast<size_t>(q) + 2]);
-                        } else if (s0 == 0) {
-                            atomicOr(f.err, ERR_NEIGH);
-                        }
+                        f0 -= static_cast<double>(f.gbuf[3 * static_cast<size_t>(p) + 0]);
+                        f1 -= static_cast<double>(f.gbuf[3 * static_cast<size_t>(p) + 1]);
+                        f2 -= static_cast<double>(f.gbuf[3 * static_cast<size_t>(p) + 2]);
                     }
                 }
             }
@@ -553,9 +564,9 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinArgs<T> f) {
                 f2 += __shfl_xor(f2, o, 32);
             }
             if (a < f.N && s0 == 0 && f.F) {
-                f.F[3 * a + 0] = static_cast<T>(f0);
-                f.F[3 * a + 1] = static_cast<T>(f1);
-                f.F[3 * a + 2] = static_cast<T>(f2);
+                f.F[3 * a + 0] = static_cast<T>(f.fown[3 * a + 0] + f0);
+                f.F[3 * a + 1] = static_cast<T>(f.fown[3 * a + 1] + f1);
+                f.F[3 * a + 2] = static_cast<T>(f.fown[3 * a + 2] + f2);
             }
         } else {
             const long i = static_cast<long>(fb) * 256 + threadIdx.x;
@@ -670,6 +681,7 @@ int fill_args(pod_handle* h, KArgs<T>& a, int N, int P, const void* pos, const d
     }
     a.offsets = offsets; a.nbr_j = nbr_j; a.shift = shift;
     a.coef = nullptr; a.D = nullptr; a.E_atom = nullptr; a.Facc = nullptr; a.gbuf = nullptr; a.part = nullptr;
+    a.fown = nullptr; a.rev = nullptr;
     a.want_G = 0; a.want_back = 0;
     a.y_net = nullptr; a.g_net = nullptr; a.n_net = 0;
     a.err = h->d_err;
@@ -706,8 +718,9 @@ int energy_forces_impl(pod_handle* h, int N, int P, const void* pos, const doubl
     const int ncol = 10 + h->M;
     const bool gather = rev != nullptr && F != nullptr;
     const size_t part_bytes = (static_cast<size_t>(ncol) * (nblk > 0 ? nblk : 1) * sizeof(double) + 255) & ~size_t(255);
-    const size_t g_bytes = gather ? static_cast<size_t>(P > 0 ? P : 1) * 3 * sizeof(T) : 0;
-    rc = ensure_scratch(h, part_bytes + g_bytes);
+    const size_t g_bytes = gather ? (static_cast<size_t>(P > 0 ? P : 1) * 3 * sizeof(T) + 255) & ~size_t(255) : 0;
+    const size_t o_bytes = gather ? static_cast<size_t>(N > 0 ? N : 1) * 3 * sizeof(double) : 0;
+    rc = ensure_scratch(h, part_bytes + g_bytes + o_bytes);
     if (rc != POD_OK) return rc;
     rc = ensure_force_acc(h, N);
     if (rc != POD_OK) return rc;
@@ -716,6 +729,8 @@ int energy_forces_impl(pod_handle* h, int N, int P, const void* pos, const doubl
     a.Facc = h->d_facc;
     a.part = static_cast<double*>(h->d_scratch);
     a.gbuf = gather ? reinterpret_cast<T*>(static_cast<char*>(h->d_scratch) + part_bytes) : nullptr;
+    a.fown = gather ? reinterpret_cast<double*>(static_cast<char*>(h->d_scratch) + part_bytes + g_bytes) : nullptr;
+    a.rev = gather ? rev : nullptr;
     a.want_G = G != nullptr;
     a.want_back = (F != nullptr) || (W != nullptr);
     a.y_net = y_net; a.g_net = g_net; a.n_net = n_net;
@@ -734,7 +749,7 @@ int energy_forces_impl(pod_handle* h, int N, int P, const void* pos, const doubl
     fa.E = E; fa.W = a.want_back ? W : nullptr; fa.G = G;
     fa.Facc = h->d_facc; fa.F = static_cast<T*>(F);
     fa.n3 = (a.want_back && !gather) ? 3L * N : 0L;
-    fa.gbuf = a.gbuf; fa.rev = gather ? rev : nullptr; fa.offsets = offsets;
+    fa.gbuf = a.gbuf; fa.fown = a.fown; fa.rev = gather ? rev : nullptr; fa.offsets = offsets;
     fa.N = N; fa.P = P; fa.err = h->d_err;
     const int nfb = gather ? (N + 7) / 8 : static_cast<int>((fa.n3 + 255) / 256);
     if (E || W || G || nfb > 0) {
