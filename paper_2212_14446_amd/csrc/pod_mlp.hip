@@ -389,13 +389,24 @@ struct AdamArgs {
 };
 
 // Sum of the partial rows in a fixed order, then one Adam update
-// (Kingma and Ba, 2015, Algorithm 1) per parameter; the thread past the last
-// parameter writes the batch loss.
-__global__ __launch_bounds__(256) void adam_kernel(AdamArgs a) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p > a.np) return;
+// (Kingma and Ba, 2015, Algorithm 1) per parameter; the parameter past the
+// last one carries the batch loss.  A workgroup takes 16 parameters; its 16
+// row groups each sum every 16th row, and the group sums are added in a
+// fixed order.
+constexpr int ADAM_P = 16, ADAM_G = 16;
+
+__global__ __launch_bounds__(ADAM_P * ADAM_G) void adam_kernel(AdamArgs a) {
+    __shared__ float red[ADAM_G][ADAM_P];
+    const int lp = threadIdx.x % ADAM_P, grp = threadIdx.x / ADAM_P;
+    const int p = blockIdx.x * ADAM_P + lp;
     float s = 0.0f;
-    for (int q = 0; q < a.rows; ++q) s += a.part[static_cast<long>(q) * a.pstride + p];
+    if (p <= a.np)
+        for (int q = grp; q < a.rows; q += ADAM_G) s += a.part[static_cast<long>(q) * a.pstride + p];
+    red[grp][lp] = s;
+    __syncthreads();
+    if (grp != 0 || p > a.np) return;
+    s = 0.0f;
+    for (int k = 0; k < ADAM_G; ++k) s += red[k][lp];
     if (p == a.np) {
         if (a.loss) *a.loss = s * a.inv_n;
         return;
@@ -456,7 +467,7 @@ int pod_mlp_train_step(pod_handle* h, int n, int n_in, const float* X, long ldx,
         return POD_EINVAL;
     const Layout o = layout(n_in);
     const int pstride = ((o.n + 1 + 63) / 64) * 64;
-    const int nblk = grid_for((n + 15) / 16, TRAIN_WAVES, 512);
+    const int nblk = grid_for((n + 15) / 16, TRAIN_WAVES, 128);
     const int rows = nblk * TRAIN_WAVES;
     const int rc = ensure_mscratch(h, static_cast<size_t>(rows) * pstride * sizeof(float));
     if (rc != POD_OK) return rc;
@@ -470,7 +481,7 @@ int pod_mlp_train_step(pod_handle* h, int n, int n_in, const float* X, long ldx,
                 eps, static_cast<float>(1.0 - std::pow(static_cast<double>(beta1), step)),
                 static_cast<float>(1.0 - std::pow(static_cast<double>(beta2), step)), 1.0f / static_cast<float>(n),
                 loss};
-    hipLaunchKernelGGL(adam_kernel, dim3((o.n + 1 + 255) / 256), dim3(256), 0, h->stream, aa);
+    hipLaunchKernelGGL(adam_kernel, dim3((o.n + 1 + ADAM_P - 1) / ADAM_P), dim3(ADAM_P * ADAM_G), 0, h->stream, aa);
     return hipGetLastError() == hipSuccess ? POD_OK : POD_EHIP;
 }
 
