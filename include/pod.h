@@ -168,9 +168,10 @@ int pod_energy_forces(pod_handle* h, int N, int P, const void* pos, const double
  * LDS accumulator holds (the limit depends on M and the tune) gives
  * POD_ENOTSUP.  Scratch grows in the handle (POD_ENOMEM on failure). */
 typedef struct pod_tune {
-    int cw;       /* descriptor columns per dG/dR chunk (0 = default 9; lowered
-                     until the cell's LDS accumulator fits) */
-    int nblocks;  /* persistent workgroups (0 = default 2048, capped at n_cfg) */
+    int cw;       /* descriptor columns per dG/dR chunk (0 = default 17; lowered
+                     until the cell's LDS accumulator fits the device's LDS
+                     per workgroup) */
+    int nblocks;  /* persistent workgroups (0 = default 512, capped at n_cfg) */
     int threads;  /* threads per workgroup, a multiple of 64 up to 512
                      (0 = default 512; otherwise POD_EINVAL) */
 } pod_tune;

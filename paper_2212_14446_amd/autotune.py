@@ -25,9 +25,9 @@ import numpy as np
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "pod_batch_tune.json")
 
-CW = (4, 6, 8, 9)
-NBLOCKS = (512, 1024, 2048)
-THREADS = (128, 256, 512)
+CW = (6, 9, 12, 17)
+NBLOCKS = (256, 512, 1024)
+THREADS = (256, 512)
 
 
 def candidates(cw: Iterable[int] = CW, nblocks: Iterable[int] = NBLOCKS, threads: Iterable[int] = THREADS):

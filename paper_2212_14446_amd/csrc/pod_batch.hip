@@ -35,7 +35,6 @@ namespace {
 using namespace dev;
 
 constexpr int MAX_THREADS = 512;
-constexpr size_t LDS_LIMIT = 64 * 1024;
 
 struct BArgs {
     ParamsT<double> prm;  // by value: read with scalar loads
@@ -355,6 +354,10 @@ __global__ __launch_bounds__(MAX_THREADS) void batch_kernel(BArgs g) {
 
 template <int PA>
 hipError_t launch_batch(const BArgs& a, bool fast, int nblk, int nth, size_t lds, hipStream_t st) {
+    const void* fn = fast ? reinterpret_cast<const void*>(&batch_kernel<PA, true>)
+                          : reinterpret_cast<const void*>(&batch_kernel<PA, false>);
+    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)) != hipSuccess)
+        return hipErrorInvalidValue;
     if (fast) hipLaunchKernelGGL((batch_kernel<PA, true>), dim3(nblk), dim3(nth), lds, st, a);
     else hipLaunchKernelGGL((batch_kernel<PA, false>), dim3(nblk), dim3(nth), lds, st, a);
     return hipGetLastError();
@@ -406,15 +409,15 @@ int pod_batch_assemble(pod_handle* h, int n_cfg, int N, int P, const int* cfg_at
         max_pc = std::max(max_pc, npair[c]);
     }
     const int NA = n_mono(h->PA);
-    int cw = tune && tune->cw > 0 ? tune->cw : 9;
-    int nblk = tune && tune->nblocks > 0 ? tune->nblocks : 2048;
+    int cw = tune && tune->cw > 0 ? tune->cw : 17;
+    int nblk = tune && tune->nblocks > 0 ? tune->nblocks : 512;
     const int nth = tune && tune->threads > 0 ? tune->threads : 512;
     if (nth % 64 != 0 || nth > MAX_THREADS) return POD_EINVAL;
     nblk = std::min(nblk, n_cfg);
     const int nc_max = ((max_nc + 15) / 16) * 16;
-    while (cw > 1 && batch_lds(h->M, cw, nc_max).total > LDS_LIMIT) --cw;
+    while (cw > 1 && batch_lds(h->M, cw, nc_max).total > h->lds_max) --cw;
     const size_t lds = batch_lds(h->M, cw, nc_max).total;
-    if (lds > LDS_LIMIT) return POD_ENOTSUP;   // a cell too large for the LDS accumulator
+    if (lds > h->lds_max) return POD_ENOTSUP;   // a cell too large for the LDS accumulator
     // cells by decreasing pair count, dealt round-robin to the workgroups
     std::vector<int> order(n_cfg);
     std::iota(order.begin(), order.end(), 0);

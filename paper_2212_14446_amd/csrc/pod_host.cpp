@@ -333,6 +333,14 @@ int pod_init(const pod_params* p, void* hip_stream, pod_handle** out) {
     if (!h) return POD_ENOMEM;
     h->dtype = p->dtype;
     h->stream = static_cast<hipStream_t>(hip_stream);
+    h->lds_max = 64 * 1024;
+    {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess &&
+            prop.sharedMemPerBlock > 0)
+            h->lds_max = prop.sharedMemPerBlock;
+    }
     h->rin = p->rin; h->rcut = p->rcut; h->L = p->L;
     h->K2 = p->K2; h->K3 = p->K3; h->K4 = p->K4; h->P3 = p->P3; h->P4 = p->P4;
     h->K = std::max(p->K2, std::max(p->K3, p->K4));

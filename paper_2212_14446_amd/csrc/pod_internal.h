@@ -79,6 +79,7 @@ struct pod_handle {
     int facc_n;
     int facc_dirty;            // a call failed between accumulation and copy-out
     size_t scratch_bytes;
+    size_t lds_max;            // LDS bytes a workgroup may use on this device
     void* d_mscratch;          // network outputs and gradient partials (separate from d_scratch,
     size_t mscratch_bytes;     // which the energy kernels reuse within one call)
     // kernel timing per kernel kind (0 finalize, 1 per-atom, 2 network), 2 events per launch
