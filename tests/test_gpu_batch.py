@@ -222,3 +222,21 @@ def test_batch_autotuner_deterministic(ref2, small_batch, small_got, tmp_path):
     t = host(pod.batch_assemble(m, db, tune=best))
     for k in ("D", "G", "dGdR"):
         assert relerr(t[k], got[k]) < 1e-12, k
+
+
+@pytest.mark.parametrize("setup", [
+    wl.SETUP_CFG1,                                                   # L 6 -> K 4, 2/3-body, P3 = 3
+    wl.PodSetup(rin=0.5, rcut=4.5, L=8, K2=3, K3=5, K4=2, P3=2, P4=6),  # P_a = 6 (largest instance)
+    wl.PodSetup(rin=0.5, rcut=5.0, L=9, K2=7, K3=0, K4=7, P3=0, P4=3),  # no 3-body block
+], ids=["cfg1", "p6", "no3body"])
+def test_batch_other_descriptor_sets(setup):
+    """Every cell of a small batch against the oracle for descriptor sets
+    other than the benchmark's (other K, angular degrees and blocks)."""
+    ref = Ref(setup)
+    b = wl.make_batch(8, 13, setup, n_min=2, n_max=120)
+    say(f"[gpu] batch other set M={setup.M} n_cfg={b.n_cfg} N={b.N}")
+    got = host(pod.batch_assemble(ref.model(), pod.DeviceBatch.from_batch(b)))
+    for c in range(b.n_cfg):
+        e = check_cell(b, got, ref, c)
+        for k, v in e.items():
+            assert v < TOL, (c, k, v)
