@@ -135,7 +135,7 @@ def run_gpu(w, dtype, steps, warmup):
             "E": float(out["E"].item())}
 
 
-def roofline(w, r, dtype):
+def roofline(w, r, dtype, traffic=True):
     """Roofline of the per-atom kernel (the dominant one) from the algorithmic
     flop model in paper_2212_14446_amd.flops; the finalize kernel's time is
     reported beside it."""
@@ -150,8 +150,11 @@ def roofline(w, r, dtype):
               + cnt["per_atom"] * w.N)
     peak = PEAK_F64 if dtype == "f64" else PEAK_F32
     achieved = f_atom / (r["kernel_ms"] * 1e-3)
+    tr = committed_traffic(dtype) if traffic else None
     return {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-            "frac": achieved / peak, "traffic": committed_traffic(dtype), "kernel": "atom_kernel (E+F)",
+            "frac": achieved / peak, "traffic": tr,
+            "hbm_GBps": (tr / (r["kernel_ms"] * 1e-3) / 1e9) if tr else None, "hbm_peak_GBps": 8000.0,
+            "kernel": "atom_kernel (E+F)",
             "kernel_ms": r["kernel_ms"], "flops_per_launch": f_atom,
             "finalize_kernel_ms": r["finalize_kernel_ms"],
             "kernel_timing": f"HIP events around each launch on the library stream, second pass of the same "
@@ -306,6 +309,7 @@ def main():
     ap.add_argument("--no-f32", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--no-rc6", action="store_true")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (a known-size "
                          "kernel for scaling hardware traffic counters)")
@@ -353,6 +357,17 @@ def main():
         print(f"[bench] f32 {r32}", file=sys.stderr, flush=True)
         rec["f32"] = {"value": w.N / (r32["ms_per_step"] * 1e-3), "ms_per_step": r32["ms_per_step"],
                       "roofline": roofline(w, r32, "f32")}
+    if not args.no_rc6 and args.rcut != 6.0:
+        # the same box at rcut 6 A (the first five BCC shells, ~56 pairs per atom)
+        w6 = wl.config2(6.0)
+        print(f"[bench] workload {w6.name}: N={w6.N} P={w6.nl.n_pairs}", file=sys.stderr, flush=True)
+        rc6 = {"workload": w6.name, "pairs": w6.nl.n_pairs, "pairs_per_atom": w6.nl.n_pairs / w6.N}
+        for dt in ("f64", "f32"):
+            r6 = run_gpu(w6, dt, args.steps, args.warmup)
+            rc6[dt] = {"value": w6.N / (r6["ms_per_step"] * 1e-3), "unit": "atoms/s",
+                       "ms_per_step": r6["ms_per_step"], "roofline": roofline(w6, r6, dt, traffic=False)}
+        rec["rcut6"] = rc6
+        print(f"[bench] rcut6 {rc6}", file=sys.stderr, flush=True)
     if not args.no_batch:
         rec["batch"] = run_batch(10, 2)
         print(f"[bench] batch {rec['batch']}", file=sys.stderr, flush=True)

@@ -49,3 +49,27 @@ def test_cfg2_f32_full(cfg2):
     say("[gpu]   " + " ".join(f"{k}={v:.3e}" for k, v in errs.items()))
     assert errs["E"] < 2e-5 and errs["E_atom"] < 2e-5
     assert errs["F"] < 1e-4 and errs["F_gather"] < 1e-4
+
+
+def test_cfg2_rcut6_sampled():
+    """The benchmark box at rcut 6 A (~56 pairs per atom): descriptors and
+    forces of 150 sampled atoms and the total energy against the oracle,
+    FP64 at 1e-10, FP32 at the benchmark spec's tolerances."""
+    w = wl.config2(6.0)
+    case = Case.from_workload(w)
+    rng = np.random.default_rng(61)
+    atoms = np.sort(rng.choice(w.N, 150, replace=False))
+    say(f"[gpu] cfg2 rcut 6: N={w.N} P={w.nl.n_pairs} ({w.nl.n_pairs / w.N:.1f} per atom)")
+    D_ref = case.oracle_descriptors(atoms=atoms)
+    D_all = case.oracle_descriptors()
+    E_ref = float((D_all @ case.c).sum())
+    from oracle import pod_oracle as po
+    o = po.energy_forces(w.pos, w.cell, w.nl.offsets.astype(np.int64), w.nl.nbr_j, w.nl.shift3, case.op, case.Q,
+                         case.c, force_atoms=atoms)
+    got = case.run("f64")
+    eD = colerr(got["D"][atoms], D_ref)
+    eE = abs(got["E"] - E_ref) / abs(E_ref)
+    eF = relerr(got["F"][atoms], o["F"][atoms])
+    eFg = relerr(got["F_gather"][atoms], o["F"][atoms])
+    say(f"[gpu]   f64 D={eD:.2e} E={eE:.2e} F={eF:.2e} F_gather={eFg:.2e}")
+    assert max(eD, eE, eF, eFg) < 1e-10
