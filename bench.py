@@ -11,7 +11,10 @@ per-atom kernel (timed with HIP events inside the library, on its stream),
 ``cpu_baseline`` (the FP64 oracle on the host, single thread), ``f32``
 (the same workload on the FP32 path), ``batch`` (the batched
 descriptor-matrix assembly of 2,000 uneven cells with dG/dR, FP64, at the
-autotuner's launch shape) and ``surrogate`` (the 4-body network surrogate:
+autotuner's launch shape), ``rcut6`` (the same box at rcut 6 A, ~56 pairs
+per atom), ``autograd`` (the differentiable energy on the 54,000-atom box,
+FP32, forward + backward), ``neighbors`` (the device neighbour-list build,
+outside the step) and ``surrogate`` (the 4-body network surrogate:
 trained on the exact 4-body energies of 19 displaced 54,000-atom boxes, then
 timed and scored against exact FP32 2/3/4-body energies and forces on a
 1,024,000-atom box, beside the 2/3-body model without it).
@@ -206,6 +209,72 @@ PEAK_BF16 = 2.5e15     # dense bfloat16 MFMA peak
 
 
 @on_stream
+def run_autograd(steps, warmup):
+    """Differentiable energy on the 54,000-atom box (FP32): one step = forward
+    (pod_energy_forces through PodEnergy) + backward (dE/dpos and dE/dc)."""
+    import torch
+
+    from paper_2212_14446_amd import autograd, pod, workloads as wl
+    w = wl.config4()
+    s = w.setup
+    m64 = pod.PodModel(pod.setup_from_workload(s), "f64")
+    nb = pod.DeviceNeighbors.from_list(w.nl)
+    c = wl.standardised_coefficients(m64.descriptors(w.pos, w.cell, nb).cpu().numpy(), s, seed=8)
+    m = pod.PodModel(pod.setup_from_workload(s), "f32")
+    nb.build_reverse(m)
+    x = torch.tensor(w.pos, dtype=torch.float32, device="cuda", requires_grad=True)
+    cc = torch.tensor(c, dtype=torch.float32, device="cuda", requires_grad=True)
+
+    def step():
+        x.grad = None
+        cc.grad = None
+        E, W = autograd.pod_energy(x, cc, m, nb, w.cell)
+        E.backward()
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    m.check()
+    ms = e0.elapsed_time(e1) / steps
+    return {"workload": f"{w.name}: {w.N} atoms, {w.nl.n_pairs} pairs, FP32",
+            "step": "E forward + backward to dE/dpos and dE/dc (torch.autograd.Function)",
+            "ms_per_step": ms, "atoms_per_s": w.N / (ms * 1e-3)}
+
+
+@on_stream
+def run_neighbors(reps, warmup=2):
+    """Device neighbour-list build (pod_build_neighbors, a blocking call),
+    reported beside the step and not part of it: the 15,840-atom box (FP64)
+    and the 1,024,000-atom box (FP32)."""
+    from paper_2212_14446_amd import pod, workloads as wl
+    out = {}
+    w = wl.config2(5.0)
+    p, cell = wl.bcc(80)
+    big = ("bcc80_1024000_s0.15", wl.displace(p, 0.15, 10), cell, wl.SETUP_CFG5)
+    for name, pos, cell, s, dt in ((w.name, w.pos, w.cell, w.setup, "f64"), (*big, "f32")):
+        m = pod.PodModel(pod.setup_from_workload(s), dt)
+        x = m._pos(pos)
+        nb = pod.DeviceNeighbors.build(m, x, cell)
+        cap = nb.P
+        for _ in range(warmup):
+            pod.DeviceNeighbors.build(m, x, cell, capacity=cap)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            pod.DeviceNeighbors.build(m, x, cell, capacity=cap, check=False)
+        ms = (time.perf_counter() - t0) * 1e3 / reps
+        m.check()
+        out[dt] = {"workload": name, "atoms": int(x.shape[0]), "pairs": nb.P, "ms_per_build": ms,
+                   "atoms_per_s": x.shape[0] / (ms * 1e-3)}
+    return out
+
+
+@on_stream
 def run_surrogate(steps, epochs=30):
     """Config-5 experiment, all on the device through the library."""
     import itertools
@@ -310,6 +379,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--no-rc6", action="store_true")
+    ap.add_argument("--no-autograd", action="store_true")
+    ap.add_argument("--no-neighbors", action="store_true")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (a known-size "
                          "kernel for scaling hardware traffic counters)")
@@ -368,6 +439,12 @@ def main():
                        "ms_per_step": r6["ms_per_step"], "roofline": roofline(w6, r6, dt, traffic=False)}
         rec["rcut6"] = rc6
         print(f"[bench] rcut6 {rc6}", file=sys.stderr, flush=True)
+    if not args.no_autograd:
+        rec["autograd"] = run_autograd(50, 5)
+        print(f"[bench] autograd {rec['autograd']}", file=sys.stderr, flush=True)
+    if not args.no_neighbors:
+        rec["neighbors"] = run_neighbors(10)
+        print(f"[bench] neighbors {rec['neighbors']}", file=sys.stderr, flush=True)
     if not args.no_batch:
         rec["batch"] = run_batch(10, 2)
         print(f"[bench] batch {rec['batch']}", file=sys.stderr, flush=True)

@@ -122,6 +122,31 @@ int pod_descriptors(pod_handle* h, int N, int P, const void* pos, const double* 
 int pod_neighbor_reverse(pod_handle* h, int N, int P, const int* offsets, const int* nbr_j,
                          const int* shift, int* rev);
 
+/* Full neighbour list in the format above (Sec. II.A: the neighbours of atom
+ * i are the atoms and periodic images closer than the cut-off), built on the
+ * device with a cell list over fractional coordinates, so triclinic and
+ * small cells (several images of one atom, self-images) are handled.
+ *   pos      : N x 3 (device, handle dtype); atoms may lie outside the cell
+ *   cell     : 9 doubles (HOST), lattice vectors as rows, or NULL for an
+ *              open system (then pos is copied to the host once to bound it)
+ *   rlist    : list radius (> 0), or 0 for the handle's rcut; a radius above
+ *              rcut gives a skin list (see the cut-off contract above)
+ *   offsets  : N + 1 ints (device), always written
+ *   nbr_j, shift : capacity ints each (device), written when capacity >= the
+ *              number of pairs; capacity 0 (with NULL arrays) only counts
+ *   n_pairs  : host out, the number of directed pairs P
+ * Pairs are kept when |r_ij| < rlist, in double (FP32 positions widened);
+ * the only pair excluded is an atom with itself in the same image.  The
+ * order of each atom's neighbours is fixed (bin scan order), so equal
+ * inputs give equal lists.  Blocking: returns after the list is written.
+ * POD_ENOTSUP if rlist spans more than 64 bins of a thin cell or P needs
+ * more than 32-bit offsets.  Latched on the device (pod_check): a
+ * non-finite coordinate (POD_ENONFINITE; the atom gets no neighbours), an
+ * image shift beyond a signed byte (POD_ENEIGH).  Scratch grows in the
+ * handle. */
+int pod_build_neighbors(pod_handle* h, int N, const void* pos, const double* cell, double rlist,
+                        int* offsets, int* nbr_j, int* shift, long capacity, long* n_pairs);
+
 /* Linear POD energy and its derivatives (eqs. (57a), (58a), (26c), (24c)).
  *   rev    : reverse-pair index from pod_neighbor_reverse, or NULL.  With it,
  *            forces are gathered per atom, F_n = sum_{p in N(n)} (g_p - g_rev(p))

@@ -78,6 +78,7 @@ def lib():
     L.pod_neighbor_reverse.argtypes = [_vp, i, i, _vp, _vp, _vp, _vp]
     L.pod_batch_assemble.argtypes = [_vp, i, i, i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, P(PodTuneC)]
     lg, f = ctypes.c_long, ctypes.c_float
+    L.pod_build_neighbors.argtypes = [_vp, i, _vp, _dp, ctypes.c_double, _vp, _vp, _vp, lg, P(lg)]
     L.pod_mlp_num_params.argtypes = [i]
     L.pod_mlp_forward.argtypes = [_vp, i, i, _vp, lg, _vp, _vp, _vp, _vp, _vp]
     L.pod_mlp_train_step.argtypes = [_vp, i, i, _vp, lg, _vp, _vp, _vp, _vp, _vp, _vp, i, f, f, f, f, _vp]
@@ -93,7 +94,7 @@ def lib():
     for name in ("pod_init", "pod_compute_basis", "pod_num_descriptors", "pod_get_basis", "pod_descriptors",
                  "pod_energy_forces", "pod_check", "pod_set_kernel_timing", "pod_get_kernel_time",
                  "pod_neighbor_reverse", "pod_batch_assemble", "pod_mlp_num_params", "pod_mlp_forward",
-                 "pod_mlp_train_step", "pod_energy_forces_surrogate"):
+                 "pod_mlp_train_step", "pod_energy_forces_surrogate", "pod_build_neighbors"):
         getattr(L, name).restype = i
     _lib = L
     return L
@@ -226,6 +227,15 @@ def pod_neighbor_reverse(h: Handle, N, P, offsets, nbr_j, shift, rev):
         "pod_neighbor_reverse")
 
 
+def pod_build_neighbors(h: Handle, N, pos, cell, rlist, offsets, nbr_j=None, shift=None, capacity=0):
+    """Returns the number of directed pairs; the list is written when capacity >= it."""
+    arr, cp = _cell_ptr(cell)
+    n = ctypes.c_long()
+    _ok(lib().pod_build_neighbors(h.ptr, int(N), _ptr(pos), cp, float(rlist), _ptr(offsets), _ptr(nbr_j),
+                                  _ptr(shift), int(capacity), ctypes.byref(n)), "pod_build_neighbors")
+    return n.value
+
+
 def pod_energy_forces(h: Handle, N, P, pos, cell, offsets, nbr_j, shift, c, E_atom=None, E=None, F=None, W=None,
                       G=None, rev=None):
     arr, cp = _cell_ptr(cell)
@@ -325,6 +335,30 @@ class DeviceNeighbors:
     @classmethod
     def from_list(cls, nl, device="cuda"):
         return cls(nl.offsets, nl.nbr_j, nl.shift, device)
+
+    @classmethod
+    def build(cls, model: "PodModel", pos, cell, rlist=0.0, capacity=None, check=True):
+        """Build the list on the device (pod_build_neighbors): one call when
+        `capacity` pairs suffice, else a second call sized from the count."""
+        import torch
+        pos = model._pos(pos)
+        N = int(pos.shape[0])
+        dev = model.device
+        offsets = torch.empty(N + 1, dtype=torch.int32, device=dev)
+        cap = int(capacity) if capacity is not None else 64 * N
+        for _ in range(2):
+            nbr_j = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+            shift = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+            P = pod_build_neighbors(model.h, N, pos, cell, rlist, offsets, nbr_j, shift, cap)
+            if P <= cap:
+                break
+            cap = P
+        if check:
+            pod_check(model.h)
+        self = cls.__new__(cls)
+        self.offsets, self.nbr_j, self.shift = offsets, nbr_j[:P], shift[:P]
+        self.N, self.P, self.rev = N, P, None
+        return self
 
 
 class PodModel:

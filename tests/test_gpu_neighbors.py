@@ -1,0 +1,236 @@
+"""Device neighbour-list builder (pod_build_neighbors) through the C ABI.
+
+The list is compared as a set of (i, j, n) triples with the oracle's brute
+force over periodic images (Sec. II.A) on small systems, and with the host
+builder on the large boxes; every atom's row must be sorted by i (CSR) and
+the energy through the device list must equal the energy through the host
+list.  Pairs within 1e-9 A of the list radius are left out of the set
+comparison (the two sides round the distance differently)."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import say
+from oracle import pod_oracle as po
+from paper_2212_14446_amd import pod, workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+S = wl.PodSetup(0.5, 5.0, 8, 4, 4, 4, 3, 3)
+
+
+def _model(dtype="f64", setup=S):
+    return pod.PodModel(pod.setup_from_workload(setup), dtype)
+
+
+def _unpack(shift):
+    s = np.asarray(shift, dtype=np.int64)
+    out = np.stack([(s >> 0) & 0xFF, (s >> 8) & 0xFF, (s >> 16) & 0xFF], axis=1)
+    return np.where(out > 127, out - 256, out)
+
+
+def _triples(offsets, nbr_j, shift3):
+    offsets = np.asarray(offsets, dtype=np.int64)
+    i = np.repeat(np.arange(offsets.size - 1), np.diff(offsets))
+    return {(int(a), int(b), int(x), int(y), int(z)) for a, b, (x, y, z) in zip(i, nbr_j, shift3)}
+
+
+def _distance(pos, cell, t):
+    cm = np.zeros((3, 3)) if cell is None else np.asarray(cell)
+    i, j, n = t[0], t[1], np.array(t[2:])
+    d = pos[j] + n @ cm - pos[i]
+    return float(np.sqrt(d @ d))
+
+
+def _device_list(m, pos, cell, rlist=0.0, capacity=None):
+    nb = pod.DeviceNeighbors.build(m, pos, cell, rlist, capacity=capacity)
+    off = nb.offsets.cpu().numpy()
+    j = nb.nbr_j.cpu().numpy()
+    sh = _unpack(nb.shift.cpu().numpy())
+    assert off[0] == 0 and off[-1] == nb.P and np.all(np.diff(off) >= 0)
+    assert j.size == nb.P and (j.size == 0 or (j.min() >= 0 and j.max() < pos.shape[0]))
+    return nb, off, j, sh
+
+
+def _compare(pos, cell, rlist, got, ref):
+    diff = got ^ ref
+    borderline = [t for t in diff if abs(_distance(pos, cell, t) - rlist) < 1e-9]
+    bad = diff - set(borderline)
+    assert not bad, f"{len(bad)} pairs differ, e.g. {sorted(bad)[:5]}"
+
+
+def _check_vs_bruteforce(m, pos, cell, rlist, name):
+    say(f"[gpu] neighbors vs brute force: {name} N={pos.shape[0]} rlist={rlist}")
+    nb, off, j, sh = _device_list(m, pos, cell, rlist)
+    ro, rj, rs = po.neighbors_bruteforce(pos, cell, rlist)
+    _compare(pos, cell, rlist, _triples(off, j, sh), _triples(ro, rj, rs))
+    return nb
+
+
+def _sheared(pos, cell, shear):
+    """The same crystal under a homogeneous shear: a triclinic cell."""
+    T = np.array(shear, dtype=np.float64)
+    return pos @ T, cell @ T
+
+
+def test_cubic_box_vs_bruteforce():
+    w = wl.small_bcc(2, sigma=0.1, seed=11)   # 16 atoms, 6.6 A cell: several images per pair
+    _check_vs_bruteforce(_model(), w.pos, w.cell, S.rcut, "bcc 2x2x2")
+
+
+def test_triclinic_cells_vs_bruteforce():
+    rng = np.random.default_rng(5)
+    m = _model()
+    for k, shear in enumerate(([[1, 0, 0], [0.3, 1, 0], [0.1, -0.2, 1]],
+                               [[1, 0.25, -0.1], [0, 1, 0.4], [0, 0, 1]])):
+        pos, cell = wl.lattice("bcc", 3, 2, 2, 3.31)
+        pos = pos + rng.normal(0, 0.1, pos.shape)
+        pos, cell = _sheared(pos, cell, shear)
+        _check_vs_bruteforce(m, pos, cell, S.rcut, f"triclinic {k}")
+
+
+def test_tiny_cells_self_images():
+    rng = np.random.default_rng(6)
+    m = _model()
+    for n_atoms, vol in ((1, 1.0), (2, 1.3), (3, 0.9)):
+        pos, cell = wl.small_cell("bcc", n_atoms, vol, 0.05, rng)
+        nb = _check_vs_bruteforce(m, pos, cell, S.rcut, f"{n_atoms}-atom cell")
+        assert nb.P > 0
+
+
+def test_open_system_vs_bruteforce():
+    rng = np.random.default_rng(7)
+    pos, _ = wl.lattice("bcc", 3, 3, 2, 3.31)
+    pos = pos + rng.normal(0, 0.1, pos.shape)
+    pos = np.vstack([pos, [[40.0, 40.0, 40.0], [-30.0, 0.0, 0.0]]])   # two lone atoms
+    nb = _check_vs_bruteforce(_model(), pos, None, S.rcut, "open cluster")
+    off = nb.offsets.cpu().numpy()
+    assert off[-1] - off[-3] == 0   # the lone atoms have no neighbours
+
+
+def test_atoms_outside_the_cell():
+    """Unwrapped coordinates: the list equals the wrapped one with the image
+    shifts moved by the lattice vectors that were added to each atom."""
+    rng = np.random.default_rng(8)
+    w = wl.small_bcc(3, sigma=0.1, seed=12)
+    wraps = rng.integers(-3, 4, size=(w.N, 3))
+    pos_u = w.pos + wraps @ w.cell
+    m = _model()
+    _, o1, j1, s1 = _device_list(m, w.pos, w.cell)
+    _, o2, j2, s2 = _device_list(m, pos_u, w.cell)
+    i1 = np.repeat(np.arange(w.N), np.diff(o1))
+    moved = s1 + wraps[i1] - wraps[j1]
+    _compare(pos_u, w.cell, S.rcut, _triples(o2, j2, s2), _triples(o1, j1, moved))
+
+
+def test_fp32_positions_and_skin():
+    w = wl.small_bcc(3, sigma=0.12, seed=13)
+    m64, m32 = _model("f64"), _model("f32")
+    _, o, j, s = _device_list(m32, w.pos.astype(np.float32), w.cell)
+    pos32 = w.pos.astype(np.float32).astype(np.float64)
+    ro, rj, rs = po.neighbors_bruteforce(pos32, w.cell, S.rcut)
+    _compare(pos32, w.cell, S.rcut, _triples(o, j, s), _triples(ro, rj, rs))
+    # a skin list (rlist > rcut) gives the same energy as the exact list
+    c = wl.coefficients(S.M, 4)
+    exact = pod.DeviceNeighbors.build(m64, w.pos, w.cell)
+    skin = pod.DeviceNeighbors.build(m64, w.pos, w.cell, rlist=S.rcut + 0.8)
+    assert skin.P > exact.P
+    a = m64.energy_forces(w.pos, w.cell, exact, c)
+    b = m64.energy_forces(w.pos, w.cell, skin, c)
+    assert abs(a["E"].item() - b["E"].item()) <= 1e-12 * abs(a["E"].item())
+    Fa, Fb = a["F"].cpu().numpy(), b["F"].cpu().numpy()
+    assert np.abs(Fa - Fb).max() <= 1e-11 * np.abs(Fa).max()
+
+
+def test_deterministic_and_count_only():
+    w = wl.small_bcc(4, sigma=0.1, seed=14)
+    m = _model()
+    a = pod.DeviceNeighbors.build(m, w.pos, w.cell)
+    b = pod.DeviceNeighbors.build(m, w.pos, w.cell, capacity=1)   # too small: counted, then built
+    for x, y in ((a.offsets, b.offsets), (a.nbr_j, b.nbr_j), (a.shift, b.shift)):
+        assert torch.equal(x, y)
+    pos = torch.as_tensor(w.pos, device="cuda")
+    off = torch.empty(w.N + 1, dtype=torch.int32, device="cuda")
+    P = pod.pod_build_neighbors(m.h, w.N, pos, w.cell, 0.0, off)
+    assert P == a.P and torch.equal(off, a.offsets)
+
+
+def test_energy_through_device_list():
+    w = wl.small_bcc(4, sigma=0.15, seed=15)
+    m = _model()
+    c = wl.coefficients(S.M, 5)
+    host = pod.DeviceNeighbors.from_list(wl.neighbor_list(w.pos, w.cell, S.rcut))
+    dev = pod.DeviceNeighbors.build(m, w.pos, w.cell)
+    dev.build_reverse(m)
+    host.build_reverse(m)
+    a = m.energy_forces(w.pos, w.cell, host, c)
+    b = m.energy_forces(w.pos, w.cell, dev, c)
+    assert abs(a["E"].item() - b["E"].item()) <= 1e-12 * abs(a["E"].item())
+    assert np.abs(a["F"].cpu().numpy() - b["F"].cpu().numpy()).max() <= 1e-11 * np.abs(a["F"].cpu().numpy()).max()
+
+
+def test_empty_and_single_atom():
+    m = _model()
+    nb = pod.DeviceNeighbors.build(m, np.zeros((0, 3)), None)
+    assert nb.N == 0 and nb.P == 0 and nb.offsets.cpu().tolist() == [0]
+    nb = pod.DeviceNeighbors.build(m, np.zeros((1, 3)), None)
+    assert nb.P == 0 and nb.offsets.cpu().tolist() == [0, 0]
+
+
+def test_argument_and_data_errors():
+    m = _model()
+    pos = torch.zeros((2, 3), dtype=torch.float64, device="cuda")
+    pos[1, 0] = 2.0
+    off = torch.empty(3, dtype=torch.int32, device="cuda")
+    cell = np.eye(3) * 10.0
+    with pytest.raises(pod.PodError) as e:
+        pod.pod_build_neighbors(m.h, 2, pos, cell, -1.0, off)
+    assert pod.ERRORS[e.value.code] == "POD_EINVAL"
+    with pytest.raises(pod.PodError) as e:
+        pod.pod_build_neighbors(m.h, 2, pos, np.zeros((3, 3)), 0.0, off)   # singular cell
+    assert pod.ERRORS[e.value.code] == "POD_EINVAL"
+    with pytest.raises(pod.PodError) as e:   # a cut-off spanning more than 64 bins of a thin cell
+        pod.pod_build_neighbors(m.h, 2, pos, np.diag([10.0, 10.0, 0.05]), 0.0, off)
+    assert pod.ERRORS[e.value.code] == "POD_ENOTSUP"
+    bad = pos.clone()
+    bad[0, 1] = float("nan")
+    P = pod.pod_build_neighbors(m.h, 2, bad, cell, 0.0, off)
+    assert P == 0
+    with pytest.raises(pod.PodError) as e:
+        pod.pod_check(m.h)
+    assert pod.ERRORS[e.value.code] == "POD_ENONFINITE"
+    pod.pod_check(m.h)   # cleared
+
+
+def test_config2_box_vs_host_builder():
+    for rcut in (5.0, 6.0):
+        w = wl.config2(rcut)
+        say(f"[gpu] neighbors: {w.name} N={w.N}")
+        m = _model(setup=w.setup)
+        _, o, j, s = _device_list(m, w.pos, w.cell)
+        assert o[-1] == w.nl.n_pairs
+        _compare(w.pos, w.cell, rcut, _triples(o, j, s), _triples(w.nl.offsets, w.nl.nbr_j, w.nl.shift3))
+
+
+def test_million_atom_box_counts():
+    w = wl.config5_infer()
+    say(f"[gpu] neighbors: {w.name} N={w.N}")
+    m = _model("f32", setup=w.setup)
+    nb = pod.DeviceNeighbors.build(m, w.pos.astype(np.float32), w.cell)
+    o = nb.offsets.cpu().numpy().astype(np.int64)
+    ref = w.nl.offsets.astype(np.int64)
+    # FP32 positions move a distance by at most ~2 sqrt(3) |x| 2^-24 < 1e-4 A
+    # here: rows may differ only by pairs that close to rcut
+    differ = np.flatnonzero(np.diff(o) != np.diff(ref))
+    say(f"[gpu] rows with another count than the FP64 host list: {differ.size}")
+    assert differ.size <= 1000
+    rows = np.union1d(differ, np.random.default_rng(1).choice(w.N, 200, replace=False))
+    j = nb.nbr_j.cpu().numpy()
+    sh = _unpack(nb.shift.cpu().numpy())
+    for i in rows:
+        got = {(int(a), *map(int, b)) for a, b in zip(j[o[i]:o[i + 1]], sh[o[i]:o[i + 1]])}
+        want = {(int(a), *map(int, b)) for a, b in zip(w.nl.nbr_j[ref[i]:ref[i + 1]],
+                                                         w.nl.shift3[ref[i]:ref[i + 1]])}
+        for t in got ^ want:
+            d = _distance(w.pos, w.cell, (int(i), *t))
+            assert abs(d - w.setup.rcut) < 1e-4, (i, t, d)
