@@ -54,6 +54,7 @@ extern "C" {
 #define POD_EHIP (-5)        /* a HIP runtime call failed */
 #define POD_ENOTSUP (-6)     /* parameters beyond what the kernels are built for */
 #define POD_ENEIGH (-7)      /* malformed neighbour list (offsets, index, shift) */
+#define POD_ESINGULAR (-8)   /* fit matrix not positive definite */
 
 #define POD_F64 0
 #define POD_F32 1
@@ -261,6 +262,36 @@ int pod_energy_forces_surrogate(pod_handle* h, int N, int P, const void* pos, co
                                 const int* rev, const void* c, const float* theta, const float* mu,
                                 const float* inv_sigma, void* E_atom, double* E, void* F, double* W);
 
+/* Linear fit (Sec. IV.A, eq. (63a)): normal equations of
+ *   min_c  w_e sum_cells (G_c . c - E_ref_c)^2
+ *        + w_f sum_rows (-dGdR_r . c - F_ref_r)^2 + gamma ||c||^2,
+ * i.e. the weights multiply the squared residuals as in the loss of
+ * eq. (63b), and forces are F = -dG/dR c (eq. (58a)).  FP64 on any handle.
+ *   M        : descriptors per atom (M + 1 <= 128, else POD_ENOTSUP)
+ *   G, E_ref : n_cfg x M global descriptors and n_cfg energies (device), as
+ *              written by pod_batch_assemble; unused when n_cfg = 0
+ *   dGdR, F_ref : n_frows x M derivative rows and n_frows forces (device),
+ *              row r = 3 n + d holds dG/dr_{n,d} and F_ref[r] = F_{n,d}
+ *              (the dGdR layout of pod_batch_assemble); unused when
+ *              n_frows = 0
+ *   w_e, w_f : finite, >= 0
+ *   Z        : (M+1) x (M+1) row-major (device), symmetric on return:
+ *              Z[:M,:M] = A^T W A, Z[:M,M] = A^T W b, Z[M,M] = b^T W b for the
+ *              rows A = [G; -dGdR], b = [E_ref; F_ref]; accumulate != 0 adds
+ *              to Z (so large sets can be streamed through in pieces).
+ * Asynchronous on the handle's stream; the Gram sums run on the FP64 matrix
+ * cores and are reduced in a fixed order (bitwise reproducible). */
+int pod_fit_gram(pod_handle* h, int M, int n_cfg, const double* G, const double* E_ref, double w_e,
+                 long n_frows, const double* dGdR, const double* F_ref, double w_f, int accumulate,
+                 double* Z);
+
+/* Solve (Z[:M,:M] + gamma I) c = Z[:M,M] (gamma >= 0) by a Cholesky
+ * factorisation of the symmetrically scaled matrix, in one workgroup on the
+ * handle's stream.  c: M doubles (device); loss: 1 double (device) or NULL,
+ * the objective of eq. (63a) at c.  A matrix that is not positive definite
+ * latches POD_ESINGULAR (pod_check), with c = 0 and loss = NaN. */
+int pod_fit_solve(pod_handle* h, int M, const double* Z, double gamma, double* c, double* loss);
+
 /* Diagnostics.  pod_set_kernel_timing(h, n) with n > 0 makes the next n
  * compute calls record pairs of HIP events on the handle's stream around each
  * of their kernels (n = 0 switches recording off).  pod_get_kernel_time waits
@@ -268,13 +299,14 @@ int pod_energy_forces_surrogate(pod_handle* h, int N, int P, const void* pos, co
  * recorded launches of one kernel -- kind 1: the per-atom kernel (radial
  * basis, atomic basis, contractions, energy, adjoint, per-pair gradients)
  * and the batched-assembly kernel; kind 0: the finalize kernel (totals E, W,
- * G and the force copy-out); kind 2: the network kernels -- then resets that
- * count. */
+ * G and the force copy-out); kind 2: the network kernels; kind 3: the Gram
+ * kernels of pod_fit_gram -- then resets that count. */
 int pod_set_kernel_timing(pod_handle* h, int n);
 int pod_get_kernel_time(pod_handle* h, int kind, double* total_ms, int* launches);
 
 /* Wait for the handle's stream, return and clear the device error word
- * (POD_OK, POD_ERANGE, POD_ENONFINITE or POD_ENEIGH), or POD_EHIP. */
+ * (POD_OK, POD_ERANGE, POD_ENONFINITE, POD_ENEIGH or POD_ESINGULAR), or
+ * POD_EHIP. */
 int pod_check(pod_handle* h);
 
 /* Static description of an error code. */

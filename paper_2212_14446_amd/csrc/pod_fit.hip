@@ -1,0 +1,425 @@
+// Linear fit of the POD coefficients (Sec. IV.A, eq. (63a)): the normal
+// equations of the weighted, regularised least-squares problem, accumulated
+// on the FP64 matrix cores, and their solution by a Cholesky factorisation
+// in one workgroup.
+//
+// Rows of the problem: one energy row per configuration (G_c, E_ref_c) with
+// weight w_e and one force row per atom coordinate (-dG/dr_{n,d}, F_ref_{n,d})
+// with weight w_f; the weights multiply the squared residuals as in the loss
+// of eq. (63b).  With every row augmented by its label, x = [a | b], the
+// Gram matrix Z = sum_r w_r x_r^T x_r holds A^T W A, A^T W b and b^T W b in
+// one (M+1) x (M+1) block.  The Gram sum is a dense contraction, so it runs
+// on v_mfma_f64_16x16x4_f64: one MFMA adds the outer products of four rows
+// for one 16 x 16 tile of Z.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "pod.h"
+#include "pod_internal.h"
+
+namespace pod {
+namespace {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+constexpr int GRAM_WAVES = 4;          // waves per workgroup
+constexpr int GRAM_THREADS = GRAM_WAVES * WAVE;
+constexpr int GRAM_BLOCKS = 512;       // persistent: two workgroups per CU
+constexpr int GRAM_ROWS = 32;          // rows per LDS chunk (8 MFMA k-steps)
+constexpr int RED_SLICES = 16;         // first reduction pass: workgroup partials in 16 slices
+constexpr int FIT_MAX_TILES = 8;       // M + 1 <= 128
+constexpr int SOLVE_THREADS = 256;      // a 16 x 16 grid in the Cholesky update
+static_assert(SOLVE_THREADS == 256, "solve_kernel maps its threads to a 16 x 16 grid");
+
+// Upper-triangle tile pairs (ti <= tj) of a T x T tiling, row by row; pair
+// p belongs to wave p % GRAM_WAVES.
+template <int T>
+struct TilePairs {
+    static constexpr int n = T * (T + 1) / 2;
+    int ti[n], tj[n];
+    constexpr TilePairs() : ti{}, tj{} {
+        int p = 0;
+        for (int i = 0; i < T; ++i)
+            for (int j = i; j < T; ++j) {
+                ti[p] = i;
+                tj[p] = j;
+                ++p;
+            }
+    }
+};
+
+struct GramArgs {
+    const double* X;   // R x M, leading dimension ldx
+    const double* y;   // R labels (column M of the augmented rows), or null
+    double ysign;      // label sign: +1 energy rows, -1 force rows (a = -dG/dr)
+    long ldx;
+    long R;
+    int M;
+    double* part;      // [gridDim.x][n pairs][256] workgroup partial tiles
+};
+
+// One wave's share of a chunk: for every k-step of four rows, the T tile
+// operands of the rows (lane l: row k0 + l / 16, column 16 t + l % 16) from
+// LDS, then one MFMA per owned tile pair.
+template <int T, int W>
+__device__ __forceinline__ void gram_chunk(const double* __restrict__ buf, int lane,
+                                           f64x4 (&acc)[(TilePairs<T>::n + GRAM_WAVES - 1) / GRAM_WAVES]) {
+    constexpr TilePairs<T> tp{};
+    constexpr int NP = TilePairs<T>::n;
+    constexpr int LDW = 16 * T + 2;
+    const int rl = lane >> 4, cl = lane & 15;
+#pragma unroll 1
+    for (int k0 = 0; k0 < GRAM_ROWS; k0 += 4) {
+        double v[T];
+#pragma unroll
+        for (int t = 0; t < T; ++t) v[t] = buf[(k0 + rl) * LDW + 16 * t + cl];
+#pragma unroll
+        for (int q = 0; W + GRAM_WAVES * q < NP; ++q) {
+            const int p = W + GRAM_WAVES * q;
+            acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[tp.ti[p]], v[tp.tj[p]], acc[q], 0, 0, 0);
+        }
+    }
+}
+
+// Gram partials of the augmented rows [X | ysign y]: chunks of GRAM_ROWS
+// rows are dealt round-robin to the workgroups, loaded cooperatively and
+// contiguously into LDS (double-buffered: the next chunk's loads are in
+// flight while the current one is multiplied), and each wave accumulates
+// its own tile pairs in registers.
+template <int T>
+__global__ __launch_bounds__(GRAM_THREADS, 2) void gram_kernel(GramArgs a) {
+    constexpr int NP = TilePairs<T>::n;
+    constexpr int QP = (NP + GRAM_WAVES - 1) / GRAM_WAVES;
+    constexpr int LDW = 16 * T + 2;
+    constexpr int EPT = (GRAM_ROWS * 16 * T + GRAM_THREADS - 1) / GRAM_THREADS;   // loads per thread and chunk
+    __shared__ double buf[2][GRAM_ROWS * LDW];
+    const int tid = threadIdx.x;
+    const int lane = tid & (WAVE - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(tid / WAVE);
+    const int D = a.M + 1;
+    const long nchunks = (a.R + GRAM_ROWS - 1) / GRAM_ROWS;
+
+    // padding columns stay zero in both buffers
+    for (int e = tid; e < 2 * GRAM_ROWS * LDW; e += GRAM_THREADS) (&buf[0][0])[e] = 0.0;
+    // (row, column) of each of this thread's loads, the same in every chunk
+    int rc[EPT];
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+        const int f = tid + GRAM_THREADS * e;
+        rc[e] = f < GRAM_ROWS * D ? ((f / D) << 8) | (f % D) : -1;
+    }
+    auto load = [&](long c, double (&pv)[EPT]) {
+        const long r0 = c * GRAM_ROWS;
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            double x = 0.0;
+            if (rc[e] >= 0) {
+                const long row = r0 + (rc[e] >> 8);
+                const int col = rc[e] & 255;
+                if (row < a.R) {
+                    if (col < a.M) x = a.X[row * a.ldx + col];
+                    else if (a.y) x = a.ysign * a.y[row];
+                }
+            }
+            pv[e] = x;
+        }
+    };
+
+    f64x4 acc[QP];
+#pragma unroll
+    for (int q = 0; q < QP; ++q) acc[q] = f64x4{0.0, 0.0, 0.0, 0.0};
+    double pv[EPT];
+    long c = blockIdx.x;
+    if (c < nchunks) load(c, pv);
+    __syncthreads();
+    int cur = 0;
+    for (; c < nchunks; c += gridDim.x) {
+#pragma unroll
+        for (int e = 0; e < EPT; ++e)
+            if (rc[e] >= 0) buf[cur][(rc[e] >> 8) * LDW + (rc[e] & 255)] = pv[e];
+        __syncthreads();
+        if (c + gridDim.x < nchunks) load(c + gridDim.x, pv);
+        switch (wave) {
+            case 0: gram_chunk<T, 0>(buf[cur], lane, acc); break;
+            case 1: gram_chunk<T, 1>(buf[cur], lane, acc); break;
+            case 2: gram_chunk<T, 2>(buf[cur], lane, acc); break;
+            default: gram_chunk<T, 3>(buf[cur], lane, acc); break;
+        }
+        cur ^= 1;
+    }
+
+    // result layout of the 16 x 16 x 4 FP64 product (checked on the device
+    // with an in-bounds probe): lane l, element e holds tile entry
+    // (row l / 16 + 4 e, column l % 16)
+#pragma unroll
+    for (int q = 0; q < QP; ++q) {
+        const int p = wave + GRAM_WAVES * q;
+        if (p < NP) {
+            double* out = a.part + (static_cast<long>(blockIdx.x) * NP + p) * 256;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) out[((lane >> 4) + 4 * e) * 16 + (lane & 15)] = acc[q][e];
+        }
+    }
+}
+
+// First reduction pass: slice s of tile pair p sums the partials of
+// workgroups s, s + S, s + 2S, ... (fixed order).
+__global__ __launch_bounds__(256) void gram_slice_kernel(const double* __restrict__ part, int nb, int NP,
+                                                         double* __restrict__ sl) {
+    const int p = blockIdx.x, s = blockIdx.y, k = threadIdx.x;
+    double v = 0.0;
+    for (int b = s; b < nb; b += RED_SLICES) v += part[(static_cast<long>(b) * NP + p) * 256 + k];
+    sl[(static_cast<long>(s) * NP + p) * 256 + k] = v;
+}
+
+struct ReduceArgs {
+    const double* sl_e;     // [RED_SLICES][NP][256] energy-row slices
+    const double* sl_f;     // [RED_SLICES][NP][256] force-row slices
+    int has_e, has_f, NP, M, T;
+    double w_e, w_f;
+    int accumulate;
+    double* Z;              // (M+1) x (M+1), row-major
+};
+
+// Z = w_e sum(energy slices) + w_f sum(force slices) (+ Z), fixed order;
+// each element is written from its upper-triangle tile entry and mirrored.
+__global__ __launch_bounds__(256) void gram_reduce_kernel(ReduceArgs a) {
+    const int p = blockIdx.x;
+    const int k = threadIdx.x;
+    int ti = 0, rem = p;
+    while (rem >= a.T - ti) {
+        rem -= a.T - ti;
+        ++ti;
+    }
+    const int tj = ti + rem;
+    const int row = 16 * ti + k / 16, col = 16 * tj + k % 16;
+    const int D = a.M + 1;
+    if (row >= D || col >= D || row > col) return;
+    double se = 0.0, sf = 0.0;
+    for (int s = 0; s < RED_SLICES; ++s) {
+        if (a.has_e) se += a.sl_e[(static_cast<long>(s) * a.NP + p) * 256 + k];
+        if (a.has_f) sf += a.sl_f[(static_cast<long>(s) * a.NP + p) * 256 + k];
+    }
+    double v = a.w_e * se + a.w_f * sf;
+    if (a.accumulate) v += a.Z[static_cast<long>(row) * D + col];
+    a.Z[static_cast<long>(row) * D + col] = v;
+    if (row != col) a.Z[static_cast<long>(col) * D + row] = v;
+}
+
+// (Z_AA + gamma I) c = Z_Ab by Cholesky on the symmetrically scaled matrix
+// (unit diagonal, same solution), one workgroup with the matrix in LDS;
+// loss = c^T Z_AA c - 2 c^T Z_Ab + Z_bb + gamma c^T c, the value of eq. (63a).
+//
+// Factorisation: outer-product form without the square roots inside the
+// loop -- step k subtracts S_ik S_jk / S_kk from the trailing lower
+// triangle, so one barrier per column suffices; afterwards
+// L_ik = S_ik / sqrt(S_kk).  The two triangular solves run in wave 0 with
+// the right-hand side in registers (lane l holds rows l and l + 64) and the
+// pivot value broadcast by readlane, so they need no barriers.
+__global__ __launch_bounds__(SOLVE_THREADS) void solve_kernel(int M, const double* __restrict__ Z, double gamma,
+                                                              double* __restrict__ c, double* __restrict__ loss,
+                                                              int* err) {
+    extern __shared__ double lds[];
+    const int D = M + 1;             // Z is D x D; S keeps Z's row stride
+    double* S = lds;                 // D x D
+    double* sc = S + D * D;          // M: 1 / sqrt(diag of the unscaled matrix)
+    double* ipiv = sc + M;           // M: 1 / sqrt(pivot)
+    double* cv = ipiv + M;           // M: solution
+    __shared__ int bad;
+    const int tid = threadIdx.x;
+    const int ty = tid >> 4, tx = tid & 15;
+    if (tid == 0) bad = 0;
+#pragma unroll 4
+    for (int e = tid; e < M * D; e += SOLVE_THREADS) S[e] = Z[e];
+    __syncthreads();
+    for (int i = tid; i < M; i += SOLVE_THREADS) {
+        const double d = S[i * D + i] + gamma;
+        if (!(d > 0.0) || !isfinite(d)) {
+            bad = 1;
+            sc[i] = 0.0;
+        } else {
+            sc[i] = 1.0 / sqrt(d);
+        }
+    }
+    __syncthreads();
+    // scaled lower triangle and right-hand side (column M)
+    for (int i = ty; i < M; i += 16) {
+        const double si = sc[i];
+        for (int j = tx; j <= i; j += 16) S[i * D + j] = (S[i * D + j] + (i == j ? gamma : 0.0)) * si * sc[j];
+        if (tx == 0) S[i * D + M] *= si;
+    }
+    __syncthreads();
+    for (int k = 0; k < M; ++k) {
+        const double d = S[k * D + k];
+        if (!(d > 0.0) || !isfinite(d) || bad) {   // uniform: every thread reads the same values
+            if (tid == 0) bad = 1;
+            break;
+        }
+        const double inv = 1.0 / d;
+        // each thread's entries of the trailing triangle are independent:
+        // unrolled so that their LDS loads overlap
+        const int nj = (M - k - 1 - tx + 15) / 16;
+        double g[8];
+#pragma unroll
+        for (int b = 0; b < 8; ++b) g[b] = b < nj ? S[(k + 1 + tx + 16 * b) * D + k] : 0.0;
+        for (int i = k + 1 + ty; i < M; i += 16) {
+            const double f = S[i * D + k] * inv;
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                const int j = k + 1 + tx + 16 * b;
+                if (j <= i) S[i * D + j] -= f * g[b];
+            }
+        }
+        __syncthreads();
+    }
+    __syncthreads();
+    if (bad) {
+        if (tid == 0) atomicOr(err, ERR_SINGULAR);
+        for (int i = tid; i < M; i += SOLVE_THREADS) c[i] = 0.0;
+        if (loss && tid == 0) *loss = NAN;
+        return;
+    }
+    // 1 / L_kk and a mirrored copy of the factor's columns in the upper
+    // triangle (S[j][i] = S[i][j], i > j), so both sweeps read rows
+    for (int k = tid; k < M; k += SOLVE_THREADS) ipiv[k] = 1.0 / sqrt(S[k * D + k]);
+    for (int i = ty; i < M; i += 16)
+        for (int j = tx; j < i; j += 16) S[j * D + i] = S[i * D + j];
+    __syncthreads();
+    if (tid < WAVE) {
+        const int l = tid;
+        const bool in0 = l < M, in1 = l + WAVE < M;
+        const double ip0 = in0 ? ipiv[l] : 0.0, ip1 = in1 ? ipiv[l + WAVE] : 0.0;
+        double r0 = in0 ? S[l * D + M] : 0.0;
+        double r1 = in1 ? S[(l + WAVE) * D + M] : 0.0;
+        // L u = r with L_ij = S_ij / sqrt(S_jj): u_j = r_j / L_jj, r_i -= L_ij u_j
+        for (int j = 0; j < M; ++j) {
+            const double pj = ipiv[j];
+            const double uj = __shfl(j < WAVE ? r0 : r1, j & (WAVE - 1)) * pj;
+            if (l == (j & (WAVE - 1))) {
+                if (j < WAVE) r0 = uj;
+                else r1 = uj;
+            }
+            const double g = uj * pj;
+            if (l > j && in0) r0 -= S[j * D + l] * g;
+            if (l + WAVE > j && in1) r1 -= S[j * D + l + WAVE] * g;
+        }
+        // L^T w = u: w_j = u_j / L_jj, u_i -= L_ji w_j (L_ji = S_ji / sqrt(S_ii))
+        for (int j = M - 1; j >= 0; --j) {
+            const double wj = __shfl(j < WAVE ? r0 : r1, j & (WAVE - 1)) * ipiv[j];
+            if (l == (j & (WAVE - 1))) {
+                if (j < WAVE) r0 = wj;
+                else r1 = wj;
+            }
+            if (l < j) r0 -= S[j * D + l] * ip0 * wj;
+            if (l + WAVE < j) r1 -= S[j * D + l + WAVE] * ip1 * wj;
+        }
+        if (in0) {
+            cv[l] = r0 * sc[l];
+            c[l] = cv[l];
+        }
+        if (in1) {
+            cv[l + WAVE] = r1 * sc[l + WAVE];
+            c[l + WAVE] = cv[l + WAVE];
+        }
+    }
+    if (!loss) return;
+    __syncthreads();
+    // objective from the unmodified Gram blocks, reloaded into LDS
+#pragma unroll 4
+    for (int e = tid; e < D * D; e += SOLVE_THREADS) S[e] = Z[e];
+    __syncthreads();
+    double* part = sc;   // M values; the scales are no longer needed
+    for (int i = tid; i < M; i += SOLVE_THREADS) {
+        double q = 0.0;
+        for (int j = 0; j < M; ++j) q += S[i * D + j] * cv[j];
+        part[i] = cv[i] * (q - 2.0 * S[i * D + M] + gamma * cv[i]);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double s = S[M * D + M];
+        for (int i = 0; i < M; ++i) s += part[i];
+        *loss = s;
+    }
+}
+
+template <int T>
+void launch_gram(const GramArgs& a, int nblk, hipStream_t s) {
+    hipLaunchKernelGGL((gram_kernel<T>), dim3(nblk), dim3(GRAM_THREADS), 0, s, a);
+}
+
+void launch_gram_t(int T, const GramArgs& a, int nblk, hipStream_t s) {
+    switch (T) {
+        case 1: launch_gram<1>(a, nblk, s); break;
+        case 2: launch_gram<2>(a, nblk, s); break;
+        case 3: launch_gram<3>(a, nblk, s); break;
+        case 4: launch_gram<4>(a, nblk, s); break;
+        case 5: launch_gram<5>(a, nblk, s); break;
+        case 6: launch_gram<6>(a, nblk, s); break;
+        case 7: launch_gram<7>(a, nblk, s); break;
+        default: launch_gram<8>(a, nblk, s); break;
+    }
+}
+
+// Workgroups for R rows: one per chunk, at most GRAM_BLOCKS.
+int gram_blocks(long R) {
+    if (R <= 0) return 0;
+    return static_cast<int>(std::min<long>(GRAM_BLOCKS, (R + GRAM_ROWS - 1) / GRAM_ROWS));
+}
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+}  // namespace
+}  // namespace pod
+
+extern "C" {
+
+int pod_fit_gram(pod_handle* h, int M, int n_cfg, const double* G, const double* E_ref, double w_e, long n_frows,
+                 const double* dGdR, const double* F_ref, double w_f, int accumulate, double* Z) {
+    using namespace pod;
+    if (!h || M < 1 || n_cfg < 0 || n_frows < 0 || !Z) return POD_EINVAL;
+    if (M + 1 > 16 * FIT_MAX_TILES) return POD_ENOTSUP;
+    if ((n_cfg > 0 && (!G || !E_ref)) || (n_frows > 0 && (!dGdR || !F_ref))) return POD_EINVAL;
+    if (!std::isfinite(w_e) || !std::isfinite(w_f) || w_e < 0.0 || w_f < 0.0) return POD_EINVAL;
+    const int T = (M + 1 + 15) / 16;
+    const int NP = T * (T + 1) / 2;
+    const int nb_e = gram_blocks(n_cfg), nb_f = gram_blocks(n_frows);
+    const size_t tile_bytes = sizeof(double) * 256 * NP;
+    const size_t be = align256(tile_bytes * nb_e), bf = align256(tile_bytes * nb_f);
+    const size_t bs = align256(tile_bytes * RED_SLICES);
+    const int rc = ensure_scratch(h, be + bf + 2 * bs);
+    if (rc != POD_OK) return rc;
+    char* base = static_cast<char*>(h->d_scratch);
+    double* part_e = reinterpret_cast<double*>(base);
+    double* part_f = reinterpret_cast<double*>(base + be);
+    double* sl_e = reinterpret_cast<double*>(base + be + bf);
+    double* sl_f = reinterpret_cast<double*>(base + be + bf + bs);
+    timing_begin(h, 3);
+    if (nb_e > 0) launch_gram_t(T, GramArgs{G, E_ref, 1.0, M, n_cfg, M, part_e}, nb_e, h->stream);
+    if (nb_f > 0) launch_gram_t(T, GramArgs{dGdR, F_ref, -1.0, M, n_frows, M, part_f}, nb_f, h->stream);
+    timing_end(h, 3);
+    if (nb_e > 0)
+        hipLaunchKernelGGL(gram_slice_kernel, dim3(NP, RED_SLICES), dim3(256), 0, h->stream, part_e, nb_e, NP, sl_e);
+    if (nb_f > 0)
+        hipLaunchKernelGGL(gram_slice_kernel, dim3(NP, RED_SLICES), dim3(256), 0, h->stream, part_f, nb_f, NP, sl_f);
+    ReduceArgs r{sl_e, sl_f, nb_e > 0, nb_f > 0, NP, M, T, w_e, w_f, accumulate ? 1 : 0, Z};
+    hipLaunchKernelGGL(gram_reduce_kernel, dim3(NP), dim3(256), 0, h->stream, r);
+    return hipGetLastError() == hipSuccess ? POD_OK : POD_EHIP;
+}
+
+int pod_fit_solve(pod_handle* h, int M, const double* Z, double gamma, double* c, double* loss) {
+    using namespace pod;
+    if (!h || M < 1 || !Z || !c) return POD_EINVAL;
+    if (!std::isfinite(gamma) || gamma < 0.0) return POD_EINVAL;
+    const size_t lds = sizeof(double) * (static_cast<size_t>(M + 1) * (M + 1) + 3 * static_cast<size_t>(M));
+    if (M > 2 * WAVE) return POD_ENOTSUP;   // two right-hand-side rows per lane
+    if (lds > h->lds_max) return POD_ENOTSUP;
+    if (hipFuncSetAttribute(reinterpret_cast<const void*>(solve_kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            static_cast<int>(lds)) != hipSuccess)
+        return POD_EHIP;
+    hipLaunchKernelGGL(solve_kernel, dim3(1), dim3(SOLVE_THREADS), lds, h->stream, M, Z, gamma, c, loss, h->d_err);
+    return hipGetLastError() == hipSuccess ? POD_OK : POD_EHIP;
+}
+
+}  // extern "C"

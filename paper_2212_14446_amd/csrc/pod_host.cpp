@@ -273,8 +273,10 @@ void pod::timing_end(pod_handle* h, int kind) {
 
 namespace {
 void release_events(pod_handle* h) {
-    if (!h->ev[0].empty() || !h->ev[1].empty() || !h->ev[2].empty()) (void)hipStreamSynchronize(h->stream);
-    for (int k = 0; k < 3; ++k) {
+    bool any = false;
+    for (int k = 0; k < pod::TIMING_KINDS; ++k) any = any || !h->ev[k].empty();
+    if (any) (void)hipStreamSynchronize(h->stream);
+    for (int k = 0; k < pod::TIMING_KINDS; ++k) {
         for (hipEvent_t e : h->ev[k]) (void)hipEventDestroy(e);
         h->ev[k].clear();
         h->ev_used[k] = 0;
@@ -287,7 +289,7 @@ extern "C" {
 int pod_set_kernel_timing(pod_handle* h, int n) {
     if (!h || n < 0 || n > (1 << 20)) return POD_EINVAL;
     release_events(h);
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < pod::TIMING_KINDS; ++k) {
         h->ev[k].reserve(2 * static_cast<size_t>(n));
         for (int i = 0; i < 2 * n; ++i) {
             hipEvent_t e;
@@ -299,7 +301,7 @@ int pod_set_kernel_timing(pod_handle* h, int n) {
 }
 
 int pod_get_kernel_time(pod_handle* h, int kind, double* total_ms, int* launches) {
-    if (!h || kind < 0 || kind > 2) return POD_EINVAL;
+    if (!h || kind < 0 || kind >= pod::TIMING_KINDS) return POD_EINVAL;
     if (hipStreamSynchronize(h->stream) != hipSuccess) return POD_EHIP;
     double tot = 0.0;
     for (int i = 0; i < h->ev_used[kind]; ++i) {
@@ -403,6 +405,7 @@ int pod_check(pod_handle* h) {
     if (hipMemcpy(&word, h->d_err, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return POD_EHIP;
     if (word != 0 && hipMemset(h->d_err, 0, sizeof(int)) != hipSuccess) return POD_EHIP;
     if (word & pod::ERR_NEIGH) return POD_ENEIGH;
+    if (word & pod::ERR_SINGULAR) return POD_ESINGULAR;
     if (word & pod::ERR_NONFINITE) return POD_ENONFINITE;
     if (word & pod::ERR_RANGE) return POD_ERANGE;
     return POD_OK;
@@ -418,6 +421,7 @@ const char* pod_strerror(int code) {
         case POD_EHIP: return "HIP runtime error";
         case POD_ENOTSUP: return "parameters beyond the compiled kernel limits";
         case POD_ENEIGH: return "malformed neighbour list";
+        case POD_ESINGULAR: return "fit matrix not positive definite";
         default: return "unknown error";
     }
 }

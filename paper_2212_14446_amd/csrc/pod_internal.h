@@ -15,6 +15,10 @@ constexpr int WAVE = 64;
 constexpr int ERR_RANGE = 1;
 constexpr int ERR_NONFINITE = 2;
 constexpr int ERR_NEIGH = 4;
+constexpr int ERR_SINGULAR = 8;   // fit matrix not positive definite
+
+// Kernel kinds with their own timing events.
+constexpr int TIMING_KINDS = 4;
 
 // One snapshot tuple as the kernels evaluate it (Sec. II.B, eqs. (3)-(6)).
 //   bessel  : kappa != 0; phi = sin(alpha pi x)/(r - rin)
@@ -82,9 +86,10 @@ struct pod_handle {
     size_t lds_max;            // LDS bytes a workgroup may use on this device
     void* d_mscratch;          // network outputs and gradient partials (separate from d_scratch,
     size_t mscratch_bytes;     // which the energy kernels reuse within one call)
-    // kernel timing per kernel kind (0 finalize, 1 per-atom, 2 network), 2 events per launch
-    std::vector<hipEvent_t> ev[3];
-    int ev_used[3];
+    // kernel timing per kernel kind (0 finalize, 1 per-atom and batch, 2 network,
+    // 3 fit Gram), 2 events per launch
+    std::vector<hipEvent_t> ev[pod::TIMING_KINDS];
+    int ev_used[pod::TIMING_KINDS];
 };
 
 namespace pod {

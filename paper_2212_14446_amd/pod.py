@@ -25,7 +25,7 @@ POD_F64, POD_F32 = 0, 1
 POD_MAX_L, POD_MAX_K, POD_MAX_P = 16, 8, 6
 POD_MLP_HIDDEN, POD_MLP_MAX_IN = 64, 64
 ERRORS = {0: "POD_OK", -1: "POD_EINVAL", -2: "POD_ERANGE", -3: "POD_ENONFINITE", -4: "POD_ENOMEM",
-          -5: "POD_EHIP", -6: "POD_ENOTSUP", -7: "POD_ENEIGH"}
+          -5: "POD_EHIP", -6: "POD_ENOTSUP", -7: "POD_ENEIGH", -8: "POD_ESINGULAR"}
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _vp = ctypes.c_void_p
@@ -79,6 +79,9 @@ def lib():
     L.pod_batch_assemble.argtypes = [_vp, i, i, i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, P(PodTuneC)]
     lg, f = ctypes.c_long, ctypes.c_float
     L.pod_build_neighbors.argtypes = [_vp, i, _vp, _dp, ctypes.c_double, _vp, _vp, _vp, lg, P(lg)]
+    d = ctypes.c_double
+    L.pod_fit_gram.argtypes = [_vp, i, i, _vp, _vp, d, lg, _vp, _vp, d, i, _vp]
+    L.pod_fit_solve.argtypes = [_vp, i, _vp, d, _vp, _vp]
     L.pod_mlp_num_params.argtypes = [i]
     L.pod_mlp_forward.argtypes = [_vp, i, i, _vp, lg, _vp, _vp, _vp, _vp, _vp]
     L.pod_mlp_train_step.argtypes = [_vp, i, i, _vp, lg, _vp, _vp, _vp, _vp, _vp, _vp, i, f, f, f, f, _vp]
@@ -94,7 +97,8 @@ def lib():
     for name in ("pod_init", "pod_compute_basis", "pod_num_descriptors", "pod_get_basis", "pod_descriptors",
                  "pod_energy_forces", "pod_check", "pod_set_kernel_timing", "pod_get_kernel_time",
                  "pod_neighbor_reverse", "pod_batch_assemble", "pod_mlp_num_params", "pod_mlp_forward",
-                 "pod_mlp_train_step", "pod_energy_forces_surrogate", "pod_build_neighbors"):
+                 "pod_mlp_train_step", "pod_energy_forces_surrogate", "pod_build_neighbors", "pod_fit_gram",
+                 "pod_fit_solve"):
         getattr(L, name).restype = i
     _lib = L
     return L
@@ -234,6 +238,15 @@ def pod_build_neighbors(h: Handle, N, pos, cell, rlist, offsets, nbr_j=None, shi
     _ok(lib().pod_build_neighbors(h.ptr, int(N), _ptr(pos), cp, float(rlist), _ptr(offsets), _ptr(nbr_j),
                                   _ptr(shift), int(capacity), ctypes.byref(n)), "pod_build_neighbors")
     return n.value
+
+
+def pod_fit_gram(h: Handle, M, n_cfg, G, E_ref, w_e, n_frows, dGdR, F_ref, w_f, Z, accumulate=False):
+    _ok(lib().pod_fit_gram(h.ptr, int(M), int(n_cfg), _ptr(G), _ptr(E_ref), float(w_e), int(n_frows), _ptr(dGdR),
+                           _ptr(F_ref), float(w_f), 1 if accumulate else 0, _ptr(Z)), "pod_fit_gram")
+
+
+def pod_fit_solve(h: Handle, M, Z, gamma, c, loss=None):
+    _ok(lib().pod_fit_solve(h.ptr, int(M), _ptr(Z), float(gamma), _ptr(c), _ptr(loss)), "pod_fit_solve")
 
 
 def pod_energy_forces(h: Handle, N, P, pos, cell, offsets, nbr_j, shift, c, E_atom=None, E=None, F=None, W=None,
