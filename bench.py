@@ -14,7 +14,9 @@ descriptor-matrix assembly of 2,000 uneven cells with dG/dR, FP64, at the
 autotuner's launch shape), ``rcut6`` (the same box at rcut 6 A, ~56 pairs
 per atom), ``autograd`` (the differentiable energy on the 54,000-atom box,
 FP32, forward + backward), ``neighbors`` (the device neighbour-list build,
-outside the step) and ``surrogate`` (the 4-body network surrogate:
+outside the step), ``opod_vs_fast`` (the paper's cost comparison: exclusive-sum
+2/3-body energy + forces and exclusive 4-body descriptors against the fast
+forms at the Table 6 sizes) and ``surrogate`` (the 4-body network surrogate:
 trained on the exact 4-body energies of 19 displaced 54,000-atom boxes, then
 timed and scored against exact FP32 2/3/4-body energies and forces on a
 1,024,000-atom box, beside the 2/3-body model without it).
@@ -322,6 +324,63 @@ def run_neighbors(reps, warmup=2):
     return out
 
 
+# Table 6: (K2, K3, P3) of the OPOD/FPOD3 models and (K4, P4) of FPOD4, rows
+# with M = 6, 15, 31, 56 (the kernels' radial/angular limits exclude 92, 141)
+TABLE6 = [(2, 1, 2, 1, 1), (5, 3, 2, 3, 2), (5, 5, 4, 5, 3), (6, 7, 6, 7, 4)]
+
+
+@on_stream
+def run_opod(steps, warmup=3):
+    """The paper's cost comparison on the 15,840-atom box (FP64): the
+    exclusive-sum 2/3-body model (OPOD, eq. (15b), O(N_i^2) per atom) against
+    the fast form (FPOD3, eq. (26a)) for energy + forces, and the exclusive
+    4-body descriptors (eq. (20a), O(N_i^3)) against the fast ones (eq. (30a)),
+    at the Table 6 sizes."""
+    import torch
+
+    from paper_2212_14446_amd import pod, workloads as wl
+    w = wl.config2(5.0)
+    nb = pod.DeviceNeighbors.from_list(w.nl)
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    rows = []
+    for (K2, K3, P3, K4, P4) in TABLE6:
+        s3 = wl.PodSetup(0.5, 5.0, 8, K2, K3, 0, P3, 0)
+        m3 = pod.PodModel(pod.setup_from_workload(s3), "f64")
+        nb.build_reverse(m3)
+        c = torch.tensor(wl.coefficients(s3.M, 3), device="cuda")
+        x3 = m3._pos(w.pos)
+        out = m3.energy_forces(x3, w.cell, nb, c)
+        oout = m3.opod_energy_forces(x3, w.cell, nb, c)
+        t_fast = timed(lambda: m3.energy_forces(x3, w.cell, nb, c, check=False, out=out))
+        t_excl = timed(lambda: m3.opod_energy_forces(x3, w.cell, nb, c, check=False, out=oout))
+        m3.check()
+        s4 = wl.PodSetup(0.5, 5.0, 8, K2, K3, K4, P3, P4)
+        m4 = pod.PodModel(pod.setup_from_workload(s4), "f64")
+        D = torch.empty((w.N, s4.M), dtype=torch.float64, device="cuda")
+        x = m4._pos(w.pos)
+        t_d_fast = timed(lambda: pod.pod_descriptors(m4.h, w.N, nb.P, x, w.cell, nb.offsets, nb.nbr_j, nb.shift, D))
+        t_d_excl = timed(lambda: pod.pod_opod_descriptors(m4.h, w.N, nb.P, x, w.cell, nb.offsets, nb.nbr_j,
+                                                          nb.shift, D))
+        m4.check()
+        rows.append({"K2": K2, "K3": K3, "P3": P3, "M3": s3.M, "fpod3_ef_ms": t_fast, "opod_ef_ms": t_excl,
+                     "opod_over_fpod3": t_excl / t_fast, "K4": K4, "P4": P4, "M4": s4.M,
+                     "fast_desc4_ms": t_d_fast, "excl_desc4_ms": t_d_excl, "excl_over_fast": t_d_excl / t_d_fast})
+        print(f"[bench] opod row {rows[-1]}", file=sys.stderr, flush=True)
+    return {"workload": f"{w.name}: {w.N} atoms, {w.nl.n_pairs} pairs, FP64", "rows": rows}
+
+
 @on_stream
 def run_surrogate(steps, epochs=30):
     """Config-5 experiment, all on the device through the library."""
@@ -429,6 +488,7 @@ def main():
     ap.add_argument("--no-rc6", action="store_true")
     ap.add_argument("--no-autograd", action="store_true")
     ap.add_argument("--no-neighbors", action="store_true")
+    ap.add_argument("--no-opod", action="store_true")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (a known-size "
                          "kernel for scaling hardware traffic counters)")
@@ -493,6 +553,8 @@ def main():
     if not args.no_neighbors:
         rec["neighbors"] = run_neighbors(10)
         print(f"[bench] neighbors {rec['neighbors']}", file=sys.stderr, flush=True)
+    if not args.no_opod:
+        rec["opod_vs_fast"] = run_opod(20)
     if not args.no_batch:
         rec["batch"] = run_batch(10, 2)
         print(f"[bench] batch {rec['batch']}", file=sys.stderr, flush=True)

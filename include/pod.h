@@ -262,6 +262,29 @@ int pod_energy_forces_surrogate(pod_handle* h, int N, int P, const void* pos, co
                                 const int* rev, const void* c, const float* theta, const float* mu,
                                 const float* inv_sigma, void* E_atom, double* E, void* F, double* W);
 
+/* Exclusive-sum descriptors, the earlier POD form the paper compares its
+ * fast descriptors with, evaluated by their defining sums on an FP64 handle
+ * (POD_ENOTSUP otherwise): D2 by eq. (12b), D3 by eq. (15b) (neighbour pairs
+ * j < k, O(N_i^2) per atom), D4 by eq. (20a) (triples j < k < l, O(N_i^3))
+ * with the angular functions g_p of eq. (19a) as Table 2 prints them (each
+ * distinct term of the cyclic orbit once; P4 <= 4, else POD_ENOTSUP).  Same
+ * layout, arguments and M as pod_descriptors; the sums run in neighbour-
+ * list order (the g_p with three distinct exponents are invariant under
+ * cyclic permutations of j, k, l only).  An atom with more than 128
+ * neighbours latches POD_ENEIGH and gets the row [1, 0, ...]. */
+int pod_opod_descriptors(pod_handle* h, int N, int P, const void* pos, const double* cell,
+                         const int* offsets, const int* nbr_j, const int* shift, void* D);
+
+/* Energies, forces and virial of the 2/3-body exclusive model (OPOD of
+ * Table 6): E_i = c . [1 | D2_i | D3_i] with D3 of eq. (15b), on an FP64
+ * handle with K4 = 0 (POD_ENOTSUP otherwise).  Forces by the chain rule of
+ * the pair sums (O(N_i^2) per atom), accumulated with FP64 atomics.
+ * Arguments as for pod_energy_forces (no reverse index, no G); same
+ * neighbour limit as pod_opod_descriptors. */
+int pod_opod_energy_forces(pod_handle* h, int N, int P, const void* pos, const double* cell,
+                           const int* offsets, const int* nbr_j, const int* shift, const void* c,
+                           void* E_atom, double* E, void* F, double* W);
+
 /* Linear fit (Sec. IV.A, eq. (63a)): normal equations of
  *   min_c  w_e sum_cells (G_c . c - E_ref_c)^2
  *        + w_f sum_rows (-dGdR_r . c - F_ref_r)^2 + gamma ||c||^2,

@@ -60,6 +60,14 @@ struct GramArgs {
     double* part;      // [gridDim.x][n pairs][256] workgroup partial tiles
 };
 
+// Value of a double held by lane `src` (uniform) of the wave.
+__device__ __forceinline__ double lane_value(double x, int src) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane(static_cast<int>(b & 0xffffffffLL), src);
+    const int hi = __builtin_amdgcn_readlane(static_cast<int>(b >> 32), src);
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
 // One wave's share of a chunk: for every k-step of four rows, the T tile
 // operands of the rows (lane l: row k0 + l / 16, column 16 t + l % 16) from
 // LDS, then one MFMA per owned tile pair.
@@ -264,12 +272,21 @@ __global__ __launch_bounds__(SOLVE_THREADS) void solve_kernel(int M, const doubl
         double g[8];
 #pragma unroll
         for (int b = 0; b < 8; ++b) g[b] = b < nj ? S[(k + 1 + tx + 16 * b) * D + k] : 0.0;
+        // all loads of a row before its stores: the compiler cannot move a
+        // load above a store to the same array, so interleaving would
+        // serialise every update on the LDS latency
         for (int i = k + 1 + ty; i < M; i += 16) {
             const double f = S[i * D + k] * inv;
+            double v[8];
 #pragma unroll
             for (int b = 0; b < 8; ++b) {
                 const int j = k + 1 + tx + 16 * b;
-                if (j <= i) S[i * D + j] -= f * g[b];
+                v[b] = j <= i ? S[i * D + j] : 0.0;
+            }
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                const int j = k + 1 + tx + 16 * b;
+                if (j <= i) S[i * D + j] = v[b] - f * g[b];
             }
         }
         __syncthreads();
@@ -296,7 +313,7 @@ __global__ __launch_bounds__(SOLVE_THREADS) void solve_kernel(int M, const doubl
         // L u = r with L_ij = S_ij / sqrt(S_jj): u_j = r_j / L_jj, r_i -= L_ij u_j
         for (int j = 0; j < M; ++j) {
             const double pj = ipiv[j];
-            const double uj = __shfl(j < WAVE ? r0 : r1, j & (WAVE - 1)) * pj;
+            const double uj = lane_value(j < WAVE ? r0 : r1, j & (WAVE - 1)) * pj;
             if (l == (j & (WAVE - 1))) {
                 if (j < WAVE) r0 = uj;
                 else r1 = uj;
@@ -307,7 +324,7 @@ __global__ __launch_bounds__(SOLVE_THREADS) void solve_kernel(int M, const doubl
         }
         // L^T w = u: w_j = u_j / L_jj, u_i -= L_ji w_j (L_ji = S_ji / sqrt(S_ii))
         for (int j = M - 1; j >= 0; --j) {
-            const double wj = __shfl(j < WAVE ? r0 : r1, j & (WAVE - 1)) * ipiv[j];
+            const double wj = lane_value(j < WAVE ? r0 : r1, j & (WAVE - 1)) * ipiv[j];
             if (l == (j & (WAVE - 1))) {
                 if (j < WAVE) r0 = wj;
                 else r1 = wj;

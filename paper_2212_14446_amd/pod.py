@@ -82,6 +82,8 @@ def lib():
     d = ctypes.c_double
     L.pod_fit_gram.argtypes = [_vp, i, i, _vp, _vp, d, lg, _vp, _vp, d, i, _vp]
     L.pod_fit_solve.argtypes = [_vp, i, _vp, d, _vp, _vp]
+    L.pod_opod_descriptors.argtypes = [_vp, i, i, _vp, _dp, _vp, _vp, _vp, _vp]
+    L.pod_opod_energy_forces.argtypes = [_vp, i, i, _vp, _dp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
     L.pod_mlp_num_params.argtypes = [i]
     L.pod_mlp_forward.argtypes = [_vp, i, i, _vp, lg, _vp, _vp, _vp, _vp, _vp]
     L.pod_mlp_train_step.argtypes = [_vp, i, i, _vp, lg, _vp, _vp, _vp, _vp, _vp, _vp, i, f, f, f, f, _vp]
@@ -98,7 +100,7 @@ def lib():
                  "pod_energy_forces", "pod_check", "pod_set_kernel_timing", "pod_get_kernel_time",
                  "pod_neighbor_reverse", "pod_batch_assemble", "pod_mlp_num_params", "pod_mlp_forward",
                  "pod_mlp_train_step", "pod_energy_forces_surrogate", "pod_build_neighbors", "pod_fit_gram",
-                 "pod_fit_solve"):
+                 "pod_fit_solve", "pod_opod_descriptors", "pod_opod_energy_forces"):
         getattr(L, name).restype = i
     _lib = L
     return L
@@ -238,6 +240,20 @@ def pod_build_neighbors(h: Handle, N, pos, cell, rlist, offsets, nbr_j=None, shi
     _ok(lib().pod_build_neighbors(h.ptr, int(N), _ptr(pos), cp, float(rlist), _ptr(offsets), _ptr(nbr_j),
                                   _ptr(shift), int(capacity), ctypes.byref(n)), "pod_build_neighbors")
     return n.value
+
+
+def pod_opod_descriptors(h: Handle, N, P, pos, cell, offsets, nbr_j, shift, D):
+    arr, cp = _cell_ptr(cell)
+    _ok(lib().pod_opod_descriptors(h.ptr, int(N), int(P), _ptr(pos), cp, _ptr(offsets), _ptr(nbr_j), _ptr(shift),
+                                   _ptr(D)), "pod_opod_descriptors")
+
+
+def pod_opod_energy_forces(h: Handle, N, P, pos, cell, offsets, nbr_j, shift, c, E_atom=None, E=None, F=None,
+                           W=None):
+    arr, cp = _cell_ptr(cell)
+    _ok(lib().pod_opod_energy_forces(h.ptr, int(N), int(P), _ptr(pos), cp, _ptr(offsets), _ptr(nbr_j),
+                                     _ptr(shift), _ptr(c), _ptr(E_atom), _ptr(E), _ptr(F), _ptr(W)),
+        "pod_opod_energy_forces")
 
 
 def pod_fit_gram(h: Handle, M, n_cfg, G, E_ref, w_e, n_frows, dGdR, F_ref, w_f, Z, accumulate=False):
@@ -418,6 +434,34 @@ class PodModel:
         }
         pod_energy_forces(self.h, N, nbrs.P, pos, cell, nbrs.offsets, nbrs.nbr_j, nbrs.shift, c,
                           o["E_atom"], o["E"], o["F"], o["W"], o["G"], rev=nbrs.rev)
+        if check:
+            pod_check(self.h)
+        return o
+
+    def opod_descriptors(self, pos, cell, nbrs: DeviceNeighbors, check=True):
+        """Exclusive-sum descriptors (eqs. (15b), (20a)), FP64 handles."""
+        import torch
+        pos = self._pos(pos)
+        D = torch.empty((nbrs.N, self.M), dtype=self.torch_dtype, device=self.device)
+        pod_opod_descriptors(self.h, nbrs.N, nbrs.P, pos, cell, nbrs.offsets, nbrs.nbr_j, nbrs.shift, D)
+        if check:
+            pod_check(self.h)
+        return D
+
+    def opod_energy_forces(self, pos, cell, nbrs: DeviceNeighbors, c, check=True, out=None):
+        """Energy, forces and virial of the 2/3-body exclusive model (K4 = 0, FP64)."""
+        import torch
+        pos = self._pos(pos)
+        c = torch.as_tensor(c, dtype=self.torch_dtype, device=self.device).contiguous()
+        N = nbrs.N
+        o = out if out is not None else {
+            "E": torch.empty(1, dtype=torch.float64, device=self.device),
+            "E_atom": torch.empty(N, dtype=self.torch_dtype, device=self.device),
+            "F": torch.empty((N, 3), dtype=self.torch_dtype, device=self.device),
+            "W": torch.empty((3, 3), dtype=torch.float64, device=self.device),
+        }
+        pod_opod_energy_forces(self.h, N, nbrs.P, pos, cell, nbrs.offsets, nbrs.nbr_j, nbrs.shift, c,
+                               o["E_atom"], o["E"], o["F"], o["W"])
         if check:
             pod_check(self.h)
         return o
