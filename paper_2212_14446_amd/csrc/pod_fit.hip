@@ -15,6 +15,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 
 #include "pod.h"
 #include "pod_internal.h"
@@ -57,6 +58,7 @@ struct GramArgs {
     long ldx;
     long R;
     int M;
+    int vec;           // X is 16-byte aligned and ldx == M: 16-byte loads
     double* part;      // [gridDim.x][n pairs][256] workgroup partial tiles
 };
 
@@ -92,69 +94,102 @@ __device__ __forceinline__ void gram_chunk(const double* __restrict__ buf, int l
 }
 
 // Gram partials of the augmented rows [X | ysign y]: chunks of GRAM_ROWS
-// rows are dealt round-robin to the workgroups, loaded cooperatively and
-// contiguously into LDS (double-buffered: the next chunk's loads are in
-// flight while the current one is multiplied), and each wave accumulates
-// its own tile pairs in registers.
+// rows are dealt round-robin to the workgroups; the rows of a chunk are one
+// contiguous block of GRAM_ROWS x M doubles, loaded in 16-byte pieces (T per
+// thread) two chunks ahead of the products (register double-buffering, so
+// two chunks per workgroup are in flight), then stored into a double-
+// buffered LDS tile with padded rows; each wave accumulates its own tile
+// pairs in registers.
 template <int T>
 __global__ __launch_bounds__(GRAM_THREADS, 2) void gram_kernel(GramArgs a) {
     constexpr int NP = TilePairs<T>::n;
     constexpr int QP = (NP + GRAM_WAVES - 1) / GRAM_WAVES;
     constexpr int LDW = 16 * T + 2;
-    constexpr int EPT = (GRAM_ROWS * 16 * T + GRAM_THREADS - 1) / GRAM_THREADS;   // loads per thread and chunk
+    static_assert(GRAM_ROWS * 16 * T / 2 <= GRAM_THREADS * T, "T pieces of 16 bytes per thread cover a chunk");
     __shared__ double buf[2][GRAM_ROWS * LDW];
     const int tid = threadIdx.x;
     const int lane = tid & (WAVE - 1);
     const int wave = __builtin_amdgcn_readfirstlane(tid / WAVE);
-    const int D = a.M + 1;
+    const int M = a.M;
     const long nchunks = (a.R + GRAM_ROWS - 1) / GRAM_ROWS;
+    const long nfull = a.R / GRAM_ROWS;           // chunks without a ragged end
+    const int npc = GRAM_ROWS * M / 2;            // 16-byte pieces per chunk
+    const bool vec = a.vec != 0;                  // X 16-byte aligned with ldx == M
 
-    // padding columns stay zero in both buffers
     for (int e = tid; e < 2 * GRAM_ROWS * LDW; e += GRAM_THREADS) (&buf[0][0])[e] = 0.0;
-    // (row, column) of each of this thread's loads, the same in every chunk
-    int rc[EPT];
+    // LDS position (row << 8 | column) of the first double of each piece
+    int rc[T];
 #pragma unroll
-    for (int e = 0; e < EPT; ++e) {
-        const int f = tid + GRAM_THREADS * e;
-        rc[e] = f < GRAM_ROWS * D ? ((f / D) << 8) | (f % D) : -1;
+    for (int e = 0; e < T; ++e) {
+        const int p = tid + GRAM_THREADS * e;
+        rc[e] = p < npc ? (((2 * p) / M) << 8) | ((2 * p) % M) : -1;
     }
-    auto load = [&](long c, double (&pv)[EPT]) {
-        const long r0 = c * GRAM_ROWS;
-#pragma unroll
-        for (int e = 0; e < EPT; ++e) {
-            double x = 0.0;
-            if (rc[e] >= 0) {
-                const long row = r0 + (rc[e] >> 8);
-                const int col = rc[e] & 255;
-                if (row < a.R) {
-                    if (col < a.M) x = a.X[row * a.ldx + col];
-                    else if (a.y) x = a.ysign * a.y[row];
-                }
-            }
-            pv[e] = x;
-        }
-    };
-
     f64x4 acc[QP];
 #pragma unroll
     for (int q = 0; q < QP; ++q) acc[q] = f64x4{0.0, 0.0, 0.0, 0.0};
-    double pv[EPT];
+    struct Regs {
+        double2 x[T];
+        double yv;
+    };
+    auto load = [&](long c, Regs& g) {
+        const long r0 = c * GRAM_ROWS;
+        if (vec && c < nfull) {
+            const double2* base = reinterpret_cast<const double2*>(a.X + r0 * M);
+#pragma unroll
+            for (int e = 0; e < T; ++e) g.x[e] = rc[e] >= 0 ? base[tid + GRAM_THREADS * e] : double2{0.0, 0.0};
+        } else {
+#pragma unroll
+            for (int e = 0; e < T; ++e) {
+                double v0 = 0.0, v1 = 0.0;
+                if (rc[e] >= 0) {
+                    const int row = rc[e] >> 8, col = rc[e] & 255;
+                    const int row1 = col + 1 < M ? row : row + 1, col1 = col + 1 < M ? col + 1 : 0;
+                    if (r0 + row < a.R) v0 = a.X[(r0 + row) * a.ldx + col];
+                    if (r0 + row1 < a.R) v1 = a.X[(r0 + row1) * a.ldx + col1];
+                }
+                g.x[e] = double2{v0, v1};
+            }
+        }
+        g.yv = (tid < GRAM_ROWS && a.y && r0 + tid < a.R) ? a.ysign * a.y[r0 + tid] : 0.0;
+    };
+    auto store = [&](const Regs& g, double* b) {
+#pragma unroll
+        for (int e = 0; e < T; ++e) {
+            if (rc[e] >= 0) {
+                const int row = rc[e] >> 8, col = rc[e] & 255;
+                b[row * LDW + col] = g.x[e].x;
+                if (col + 1 < M) b[row * LDW + col + 1] = g.x[e].y;
+                else b[(row + 1) * LDW] = g.x[e].y;
+            }
+        }
+        if (tid < GRAM_ROWS) b[tid * LDW + M] = g.yv;
+    };
+    auto compute = [&](const double* b) {
+        switch (wave) {
+            case 0: gram_chunk<T, 0>(b, lane, acc); break;
+            case 1: gram_chunk<T, 1>(b, lane, acc); break;
+            case 2: gram_chunk<T, 2>(b, lane, acc); break;
+            default: gram_chunk<T, 3>(b, lane, acc); break;
+        }
+    };
+    const long G = gridDim.x;
+    Regs ga, gb;
     long c = blockIdx.x;
-    if (c < nchunks) load(c, pv);
+    if (c < nchunks) load(c, ga);
+    if (c + G < nchunks) load(c + G, gb);
     __syncthreads();
     int cur = 0;
-    for (; c < nchunks; c += gridDim.x) {
-#pragma unroll
-        for (int e = 0; e < EPT; ++e)
-            if (rc[e] >= 0) buf[cur][(rc[e] >> 8) * LDW + (rc[e] & 255)] = pv[e];
+    for (; c < nchunks; c += 2 * G) {
+        store(ga, buf[cur]);
         __syncthreads();
-        if (c + gridDim.x < nchunks) load(c + gridDim.x, pv);
-        switch (wave) {
-            case 0: gram_chunk<T, 0>(buf[cur], lane, acc); break;
-            case 1: gram_chunk<T, 1>(buf[cur], lane, acc); break;
-            case 2: gram_chunk<T, 2>(buf[cur], lane, acc); break;
-            default: gram_chunk<T, 3>(buf[cur], lane, acc); break;
-        }
+        if (c + 2 * G < nchunks) load(c + 2 * G, ga);
+        compute(buf[cur]);
+        cur ^= 1;
+        if (c + G >= nchunks) break;
+        store(gb, buf[cur]);
+        __syncthreads();
+        if (c + 3 * G < nchunks) load(c + 3 * G, gb);
+        compute(buf[cur]);
         cur ^= 1;
     }
 
@@ -413,8 +448,10 @@ int pod_fit_gram(pod_handle* h, int M, int n_cfg, const double* G, const double*
     double* sl_e = reinterpret_cast<double*>(base + be + bf);
     double* sl_f = reinterpret_cast<double*>(base + be + bf + bs);
     timing_begin(h, 3);
-    if (nb_e > 0) launch_gram_t(T, GramArgs{G, E_ref, 1.0, M, n_cfg, M, part_e}, nb_e, h->stream);
-    if (nb_f > 0) launch_gram_t(T, GramArgs{dGdR, F_ref, -1.0, M, n_frows, M, part_f}, nb_f, h->stream);
+    const int vec_e = (reinterpret_cast<uintptr_t>(G) & 15) == 0;
+    const int vec_f = (reinterpret_cast<uintptr_t>(dGdR) & 15) == 0;
+    if (nb_e > 0) launch_gram_t(T, GramArgs{G, E_ref, 1.0, M, n_cfg, M, vec_e, part_e}, nb_e, h->stream);
+    if (nb_f > 0) launch_gram_t(T, GramArgs{dGdR, F_ref, -1.0, M, n_frows, M, vec_f, part_f}, nb_f, h->stream);
     timing_end(h, 3);
     if (nb_e > 0)
         hipLaunchKernelGGL(gram_slice_kernel, dim3(NP, RED_SLICES), dim3(256), 0, h->stream, part_e, nb_e, NP, sl_e);
