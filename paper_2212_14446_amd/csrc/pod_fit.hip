@@ -255,10 +255,8 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(ReduceArgs a) {
 // (unit diagonal, same solution), one workgroup with the matrix in LDS;
 // loss = c^T Z_AA c - 2 c^T Z_Ab + Z_bb + gamma c^T c, the value of eq. (63a).
 //
-// Factorisation: outer-product form without the square roots inside the
-// loop -- step k subtracts S_ik S_jk / S_kk from the trailing lower
-// triangle, so one barrier per column suffices; afterwards
-// L_ik = S_ik / sqrt(S_kk).  The two triangular solves run in wave 0 with
+// Factorisation: blocked right-looking Cholesky with panels of 16 columns
+// (three barriers per panel).  The two triangular solves run in wave 0 with
 // the right-hand side in registers (lane l holds rows l and l + 64) and the
 // pivot value broadcast by readlane, so they need no barriers.
 __global__ __launch_bounds__(SOLVE_THREADS) void solve_kernel(int M, const double* __restrict__ Z, double gamma,
@@ -294,34 +292,71 @@ __global__ __launch_bounds__(SOLVE_THREADS) void solve_kernel(int M, const doubl
         if (tx == 0) S[i * D + M] *= si;
     }
     __syncthreads();
-    for (int k = 0; k < M; ++k) {
-        const double d = S[k * D + k];
-        if (!(d > 0.0) || !isfinite(d) || bad) {   // uniform: every thread reads the same values
-            if (tid == 0) bad = 1;
-            break;
+    // blocked right-looking Cholesky, panels of 16 columns, lower triangle:
+    // (1) wave 0 factors the diagonal block (its LDS operations execute in
+    // order, so wavefront fences suffice between the steps), (2) one thread
+    // per row below solves the panel against it, (3) the trailing triangle
+    // takes the rank-16 update -- three barriers per panel
+    for (int k0 = 0; k0 < M; k0 += 16) {
+        const int kb = M - k0 < 16 ? M - k0 : 16;
+        if (tid < WAVE) {
+            const int r = tid & 15, cg = tid >> 4;   // row r of the block, columns 4 cg .. 4 cg + 3
+            for (int k = 0; k < kb; ++k) {
+                const double d = S[(k0 + k) * D + k0 + k];
+                if (!(d > 0.0) || !isfinite(d)) {   // the same value in every lane
+                    if (tid == 0) bad = 1;
+                    break;
+                }
+                const double lkk = sqrt(d), ilkk = 1.0 / lkk;
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+                if (cg == 0 && r >= k && r < kb) {
+                    const int at = (k0 + r) * D + k0 + k;
+                    S[at] = r == k ? lkk : S[at] * ilkk;
+                }
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+                if (r > k && r < kb) {
+                    const double lrk = S[(k0 + r) * D + k0 + k];
+#pragma unroll
+                    for (int jj = 0; jj < 4; ++jj) {
+                        const int j = 4 * cg + jj;
+                        if (j > k && j <= r) S[(k0 + r) * D + k0 + j] -= lrk * S[(k0 + j) * D + k0 + k];
+                    }
+                }
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            }
         }
-        const double inv = 1.0 / d;
-        // each thread's entries of the trailing triangle are independent:
-        // unrolled so that their LDS loads overlap
-        const int nj = (M - k - 1 - tx + 15) / 16;
-        double g[8];
+        __syncthreads();
+        if (bad) break;
+        const int b0 = k0 + kb;
+        if (tid < kb) ipiv[k0 + tid] = 1.0 / S[(k0 + tid) * D + k0 + tid];
+        __syncthreads();
+        for (int i = b0 + tid; i < M; i += SOLVE_THREADS) {
+            double x[16];
 #pragma unroll
-        for (int b = 0; b < 8; ++b) g[b] = b < nj ? S[(k + 1 + tx + 16 * b) * D + k] : 0.0;
-        // all loads of a row before its stores: the compiler cannot move a
-        // load above a store to the same array, so interleaving would
-        // serialise every update on the LDS latency
-        for (int i = k + 1 + ty; i < M; i += 16) {
-            const double f = S[i * D + k] * inv;
-            double v[8];
+            for (int q = 0; q < 16; ++q) x[q] = q < kb ? S[i * D + k0 + q] : 0.0;
 #pragma unroll
-            for (int b = 0; b < 8; ++b) {
-                const int j = k + 1 + tx + 16 * b;
-                v[b] = j <= i ? S[i * D + j] : 0.0;
+            for (int q = 0; q < 16; ++q) {
+                if (q < kb) {
+                    double v = x[q];
+#pragma unroll
+                    for (int pp = 0; pp < q; ++pp) v -= x[pp] * S[(k0 + q) * D + k0 + pp];
+                    x[q] = v * ipiv[k0 + q];
+                }
             }
 #pragma unroll
-            for (int b = 0; b < 8; ++b) {
-                const int j = k + 1 + tx + 16 * b;
-                if (j <= i) S[i * D + j] = v[b] - f * g[b];
+            for (int q = 0; q < 16; ++q)
+                if (q < kb) S[i * D + k0 + q] = x[q];
+        }
+        __syncthreads();
+        for (int i = b0 + ty; i < M; i += 16) {
+            double li[16];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) li[q] = q < kb ? S[i * D + k0 + q] : 0.0;
+            for (int j = b0 + tx; j <= i; j += 16) {
+                double v = 0.0;
+#pragma unroll
+                for (int q = 0; q < 16; ++q) v += q < kb ? li[q] * S[j * D + k0 + q] : 0.0;
+                S[i * D + j] -= v;
             }
         }
         __syncthreads();
@@ -333,39 +368,50 @@ __global__ __launch_bounds__(SOLVE_THREADS) void solve_kernel(int M, const doubl
         if (loss && tid == 0) *loss = NAN;
         return;
     }
-    // 1 / L_kk and a mirrored copy of the factor's columns in the upper
-    // triangle (S[j][i] = S[i][j], i > j), so both sweeps read rows
-    for (int k = tid; k < M; k += SOLVE_THREADS) ipiv[k] = 1.0 / sqrt(S[k * D + k]);
+    // a mirrored copy of the factor's columns in the upper triangle
+    // (S[j][i] = S[i][j], i > j), so both sweeps read rows; ipiv holds 1 / L_kk
     for (int i = ty; i < M; i += 16)
         for (int j = tx; j < i; j += 16) S[j * D + i] = S[i * D + j];
     __syncthreads();
     if (tid < WAVE) {
         const int l = tid;
         const bool in0 = l < M, in1 = l + WAVE < M;
-        const double ip0 = in0 ? ipiv[l] : 0.0, ip1 = in1 ? ipiv[l + WAVE] : 0.0;
         double r0 = in0 ? S[l * D + M] : 0.0;
         double r1 = in1 ? S[(l + WAVE) * D + M] : 0.0;
-        // L u = r with L_ij = S_ij / sqrt(S_jj): u_j = r_j / L_jj, r_i -= L_ij u_j
+        // L u = r: u_j = r_j / L_jj, r_i -= L_ij u_j (L_ij mirrored at S[j][i]);
+        // row j + 1 and its pivot are read while step j runs
+        double a0 = in0 ? S[l] : 0.0, a1 = in1 ? S[l + WAVE] : 0.0, pj = ipiv[0];
         for (int j = 0; j < M; ++j) {
-            const double pj = ipiv[j];
+            const int jn = j + 1 < M ? j + 1 : j;
+            const double n0 = in0 ? S[jn * D + l] : 0.0, n1 = in1 ? S[jn * D + l + WAVE] : 0.0, pn = ipiv[jn];
             const double uj = lane_value(j < WAVE ? r0 : r1, j & (WAVE - 1)) * pj;
             if (l == (j & (WAVE - 1))) {
                 if (j < WAVE) r0 = uj;
                 else r1 = uj;
             }
-            const double g = uj * pj;
-            if (l > j && in0) r0 -= S[j * D + l] * g;
-            if (l + WAVE > j && in1) r1 -= S[j * D + l + WAVE] * g;
+            if (l > j && in0) r0 -= a0 * uj;
+            if (l + WAVE > j && in1) r1 -= a1 * uj;
+            a0 = n0;
+            a1 = n1;
+            pj = pn;
         }
-        // L^T w = u: w_j = u_j / L_jj, u_i -= L_ji w_j (L_ji = S_ji / sqrt(S_ii))
+        // L^T w = u: w_j = u_j / L_jj, u_i -= L_ji w_j for i < j
+        a0 = in0 ? S[(M - 1) * D + l] : 0.0;
+        a1 = in1 ? S[(M - 1) * D + l + WAVE] : 0.0;
+        pj = ipiv[M - 1];
         for (int j = M - 1; j >= 0; --j) {
-            const double wj = lane_value(j < WAVE ? r0 : r1, j & (WAVE - 1)) * ipiv[j];
+            const int jn = j > 0 ? j - 1 : 0;
+            const double n0 = in0 ? S[jn * D + l] : 0.0, n1 = in1 ? S[jn * D + l + WAVE] : 0.0, pn = ipiv[jn];
+            const double wj = lane_value(j < WAVE ? r0 : r1, j & (WAVE - 1)) * pj;
             if (l == (j & (WAVE - 1))) {
                 if (j < WAVE) r0 = wj;
                 else r1 = wj;
             }
-            if (l < j) r0 -= S[j * D + l] * ip0 * wj;
-            if (l + WAVE < j) r1 -= S[j * D + l + WAVE] * ip1 * wj;
+            if (l < j) r0 -= a0 * wj;
+            if (l + WAVE < j) r1 -= a1 * wj;
+            a0 = n0;
+            a1 = n1;
+            pj = pn;
         }
         if (in0) {
             cv[l] = r0 * sc[l];
