@@ -458,8 +458,9 @@ def run_surrogate(steps, epochs=30):
                              "frac": ach / PEAK_BF16, "flops_per_atom": f_net}}
 
 
-def cpu_baseline(w):
-    """The FP64 oracle (as written) on the host, one thread, full workload."""
+def cpu_baseline(w, passes=4):
+    """The FP64 oracle (as written) on the host, one thread: `passes` full
+    energy + forces + virial passes over the workload (about 10 s)."""
     from threadpoolctl import threadpool_limits
 
     from oracle import pod_oracle as po
@@ -468,11 +469,12 @@ def cpu_baseline(w):
     Q, _ = po.pod_basis(p)
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
-        po.energy_forces(w.pos, w.cell, w.nl.offsets.astype(np.int64), w.nl.nbr_j, w.nl.shift3, p, Q, w.c)
+        for _ in range(passes):
+            po.energy_forces(w.pos, w.cell, w.nl.offsets.astype(np.int64), w.nl.nbr_j, w.nl.shift3, p, Q, w.c)
         dt = time.perf_counter() - t0
-    return {"value": w.N / dt, "unit": "atoms/s", "cores": 1, "kind": "oracle",
-            "sample": f"full {w.N}-atom box, one energy+forces+virial pass, numpy FP64, 1 thread",
-            "seconds": dt}
+    return {"value": passes * w.N / dt, "unit": "atoms/s", "cores": 1, "kind": "oracle",
+            "sample": f"{passes} passes over the full {w.N}-atom box (energy + forces + virial), numpy FP64, "
+                      f"1 thread", "seconds": dt}
 
 
 def main():

@@ -340,22 +340,28 @@ __global__ __launch_bounds__(WAVE) void opod_energy_kernel(OArgs a) {
 __global__ __launch_bounds__(256) void opod_finalize_kernel(const double* __restrict__ part, int N, double* E,
                                                             double* W, double* Facc, double* F, long n3) {
     if (blockIdx.x == 0) {
-        __shared__ double red[256];
-        for (int col = 0; col < 10; ++col) {
-            double v = 0.0;
-            for (int i = threadIdx.x; i < N; i += 256) v += part[static_cast<long>(i) * 10 + col];
-            red[threadIdx.x] = v;
-            __syncthreads();
-            for (int o = 128; o > 0; o >>= 1) {
-                if (static_cast<int>(threadIdx.x) < o) red[threadIdx.x] += red[threadIdx.x + o];
-                __syncthreads();
-            }
-            if (threadIdx.x == 0) {
-                if (col == 0 && E) *E = red[0];
-                if (col > 0 && W) W[col - 1] = red[0];
+        // each thread sums all ten columns over its atoms, then one tree
+        // reduction per column (fixed order)
+        __shared__ double red[10][256];
+        double v[10];
+#pragma unroll
+        for (int col = 0; col < 10; ++col) v[col] = 0.0;
+        for (int i = threadIdx.x; i < N; i += 256) {
+#pragma unroll
+            for (int col = 0; col < 10; ++col) v[col] += part[static_cast<long>(i) * 10 + col];
+        }
+#pragma unroll
+        for (int col = 0; col < 10; ++col) red[col][threadIdx.x] = v[col];
+        __syncthreads();
+        for (int o = 128; o > 0; o >>= 1) {
+            if (static_cast<int>(threadIdx.x) < o) {
+#pragma unroll
+                for (int col = 0; col < 10; ++col) red[col][threadIdx.x] += red[col][threadIdx.x + o];
             }
             __syncthreads();
         }
+        if (threadIdx.x == 0 && E) *E = red[0][0];
+        if (threadIdx.x < 9 && W) W[threadIdx.x] = red[1 + threadIdx.x][0];
         return;
     }
     const long k = static_cast<long>(blockIdx.x - 1) * 256 + threadIdx.x;
