@@ -325,17 +325,38 @@ __device__ __forceinline__ void atom_body(const KArgs<T>& g) {
             eff2 += w4[p] * d3[Tab::build.pa[p]];
             eff3[Tab::build.pa[p]] += w4[p] * acc[0];
         }
-    T ab[NA];
+    // the adjoint row dE_i/dB_{i m .}: in registers up to P_a = 5; beyond,
+    // the row and the basis row do not both fit, so the adjoint row is
+    // accumulated in its LDS slot (the staging area is free after the rounds)
+    constexpr bool AB_LDS = NA > 60;
+    T ab[AB_LDS ? 1 : NA];
+    if constexpr (AB_LDS) {
+        if (act) {
+            T* abrow = sT + (al * K + m) * odd_len(NA);
 #pragma unroll
-    for (int mu = 0; mu < NA; ++mu) ab[mu] = T(2 * mt.mult[mu]) * eff3[mt.deg[mu]] * acc[mu];  // eq. (26c)
-    ab[0] += eff2;
+            for (int mu = 0; mu < NA; ++mu)
+                abrow[mu] = T(2 * mt.mult[mu]) * eff3[mt.deg[mu]] * acc[mu] + (mu == 0 ? eff2 : T(0));  // eq. (26c)
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-        const int x = Tab::build.tx[t], y = Tab::build.ty[t], z = Tab::build.tz[t];
-        const T wc = w4[Tab::build.tp[t]] * T(Tab::build.tc[t]);
-        ab[x] += wc * acc[y] * acc[z];
-        ab[y] += wc * acc[x] * acc[z];
-        ab[z] += wc * acc[x] * acc[y];
+            for (int t = 0; t < NT; ++t) {
+                const int x = Tab::build.tx[t], y = Tab::build.ty[t], z = Tab::build.tz[t];
+                const T wc = w4[Tab::build.tp[t]] * T(Tab::build.tc[t]);
+                abrow[x] += wc * acc[y] * acc[z];
+                abrow[y] += wc * acc[x] * acc[z];
+                abrow[z] += wc * acc[x] * acc[y];
+            }
+        }
+    } else {
+#pragma unroll
+        for (int mu = 0; mu < NA; ++mu) ab[mu] = T(2 * mt.mult[mu]) * eff3[mt.deg[mu]] * acc[mu];  // eq. (26c)
+        ab[0] += eff2;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int x = Tab::build.tx[t], y = Tab::build.ty[t], z = Tab::build.tz[t];
+            const T wc = w4[Tab::build.tp[t]] * T(Tab::build.tc[t]);
+            ab[x] += wc * acc[y] * acc[z];
+            ab[y] += wc * acc[x] * acc[z];
+            ab[z] += wc * acc[x] * acc[y];
+        }
     }
 
     // per-atom energy: sum the K lanes of the atom through LDS
@@ -380,9 +401,11 @@ __device__ __forceinline__ void atom_body(const KArgs<T>& g) {
     // every round, re-evaluates its radial functions with derivatives and
     // contracts them with the K adjoint rows of atom a
     T* sAb = sT;
-    if (act) {
+    if constexpr (!AB_LDS) {
+        if (act) {
 #pragma unroll
-        for (int mu = 0; mu < NA; ++mu) sAb[(al * K + m) * NAP + mu] = ab[mu];
+            for (int mu = 0; mu < NA; ++mu) sAb[(al * K + m) * NAP + mu] = ab[mu];
+        }
     }
     __syncthreads();
 
