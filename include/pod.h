@@ -285,6 +285,36 @@ int pod_opod_energy_forces(pod_handle* h, int N, int P, const void* pos, const d
                            const int* offsets, const int* nbr_j, const int* shift, const void* c,
                            void* E_atom, double* E, void* F, double* W);
 
+/* Molecular dynamics, the use by which the paper measures the cost of its
+ * potentials (Sec. V, Fig. 4): nsteps velocity Verlet steps
+ *   v += dt/2 F/m;  x += dt v;  F = F(x) (pod_energy_forces);  v += dt/2 F/m
+ * on the handle's stream, asynchronous.  Units: angstrom, fs, amu, eV.
+ *   pos, vel, F : N x 3 (device, handle dtype), updated in place; F must hold
+ *                 the forces of the initial positions on entry and holds those
+ *                 of the final positions on return.  Updates are computed in
+ *                 FP64 and stored in the handle's dtype.
+ *   offsets, nbr_j, shift, rev : one list for all steps (rev as for
+ *                 pod_energy_forces, or NULL).  It must be a skin list (radius
+ *                 rcut + skin) that stays valid, i.e. no atom moves more than
+ *                 skin / 2 from where the list was built during the call.
+ *   c           : coefficients; mass > 0 (amu, all atoms); dt (fs)
+ *   E_pot, E_kin: nsteps doubles each (device) or NULL: potential and kinetic
+ *                 energy (eV) after every step.
+ *   pos_ref, max_disp : the positions the list was built at (device, N x 3)
+ *                 and 1 double (device), or both NULL: max_disp receives the
+ *                 largest |x_n - x_ref_n| over all atoms and all steps of the
+ *                 call (NaN if a coordinate became non-finite), so a caller
+ *                 can verify that every step ran on a valid list.
+ * Data errors are latched as for pod_energy_forces (pod_check). */
+int pod_md_verlet(pod_handle* h, int N, int P, void* pos, void* vel, void* F, const double* cell,
+                  const int* offsets, const int* nbr_j, const int* shift, const int* rev, const void* c,
+                  double mass, double dt, int nsteps, double* E_pot, double* E_kin, const void* pos_ref,
+                  double* max_disp);
+
+/* max_n |pos_n - pos_ref_n| into *out (device double), for the rebuild
+ * criterion of a skin list; NaN if a coordinate is not finite. */
+int pod_md_max_displacement(pod_handle* h, int N, const void* pos, const void* pos_ref, double* out);
+
 /* Linear fit (Sec. IV.A, eq. (63a)): normal equations of
  *   min_c  w_e sum_cells (G_c . c - E_ref_c)^2
  *        + w_f sum_rows (-dGdR_r . c - F_ref_r)^2 + gamma ||c||^2,

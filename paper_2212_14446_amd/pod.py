@@ -83,6 +83,8 @@ def lib():
     L.pod_fit_gram.argtypes = [_vp, i, i, _vp, _vp, d, lg, _vp, _vp, d, i, _vp]
     L.pod_fit_solve.argtypes = [_vp, i, _vp, d, _vp, _vp]
     L.pod_opod_descriptors.argtypes = [_vp, i, i, _vp, _dp, _vp, _vp, _vp, _vp]
+    L.pod_md_verlet.argtypes = [_vp, i, i, _vp, _vp, _vp, _dp, _vp, _vp, _vp, _vp, _vp, d, d, i, _vp, _vp, _vp, _vp]
+    L.pod_md_max_displacement.argtypes = [_vp, i, _vp, _vp, _vp]
     L.pod_opod_energy_forces.argtypes = [_vp, i, i, _vp, _dp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
     L.pod_mlp_num_params.argtypes = [i]
     L.pod_mlp_forward.argtypes = [_vp, i, i, _vp, lg, _vp, _vp, _vp, _vp, _vp]
@@ -100,7 +102,8 @@ def lib():
                  "pod_energy_forces", "pod_check", "pod_set_kernel_timing", "pod_get_kernel_time",
                  "pod_neighbor_reverse", "pod_batch_assemble", "pod_mlp_num_params", "pod_mlp_forward",
                  "pod_mlp_train_step", "pod_energy_forces_surrogate", "pod_build_neighbors", "pod_fit_gram",
-                 "pod_fit_solve", "pod_opod_descriptors", "pod_opod_energy_forces"):
+                 "pod_fit_solve", "pod_opod_descriptors", "pod_opod_energy_forces", "pod_md_verlet",
+                 "pod_md_max_displacement"):
         getattr(L, name).restype = i
     _lib = L
     return L
@@ -254,6 +257,18 @@ def pod_opod_energy_forces(h: Handle, N, P, pos, cell, offsets, nbr_j, shift, c,
     _ok(lib().pod_opod_energy_forces(h.ptr, int(N), int(P), _ptr(pos), cp, _ptr(offsets), _ptr(nbr_j),
                                      _ptr(shift), _ptr(c), _ptr(E_atom), _ptr(E), _ptr(F), _ptr(W)),
         "pod_opod_energy_forces")
+
+
+def pod_md_verlet(h: Handle, N, P, pos, vel, F, cell, offsets, nbr_j, shift, rev, c, mass, dt, nsteps, E_pot=None,
+                  E_kin=None, pos_ref=None, max_disp=None):
+    arr, cp = _cell_ptr(cell)
+    _ok(lib().pod_md_verlet(h.ptr, int(N), int(P), _ptr(pos), _ptr(vel), _ptr(F), cp, _ptr(offsets), _ptr(nbr_j),
+                            _ptr(shift), _ptr(rev), _ptr(c), float(mass), float(dt), int(nsteps), _ptr(E_pot),
+                            _ptr(E_kin), _ptr(pos_ref), _ptr(max_disp)), "pod_md_verlet")
+
+
+def pod_md_max_displacement(h: Handle, N, pos, pos_ref, out):
+    _ok(lib().pod_md_max_displacement(h.ptr, int(N), _ptr(pos), _ptr(pos_ref), _ptr(out)), "pod_md_max_displacement")
 
 
 def pod_fit_gram(h: Handle, M, n_cfg, G, E_ref, w_e, n_frows, dGdR, F_ref, w_f, Z, accumulate=False):
