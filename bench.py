@@ -14,7 +14,8 @@ descriptor-matrix assembly of 2,000 uneven cells with dG/dR, FP64, at the
 autotuner's launch shape), ``rcut6`` (the same box at rcut 6 A, ~56 pairs
 per atom), ``autograd`` (the differentiable energy on the 54,000-atom box,
 FP32, forward + backward), ``neighbors`` (the device neighbour-list build,
-outside the step), ``opod_vs_fast`` (the paper's cost comparison: exclusive-sum
+outside the step), ``md`` (velocity-Verlet dynamics on the same box with the
+device skin list, per step and per atom-step), ``opod_vs_fast`` (the paper's cost comparison: exclusive-sum
 2/3-body energy + forces and exclusive 4-body descriptors against the fast
 forms at the Table 6 sizes) and ``surrogate`` (the 4-body network surrogate:
 trained on the exact 4-body energies of 19 displaced 54,000-atom boxes, then
@@ -382,6 +383,42 @@ def run_opod(steps, warmup=3):
 
 
 @on_stream
+def run_md(steps, dtype="f64", T=300.0, dt=1.0):
+    """NVE molecular dynamics on the 15,840-atom box (the use by which the
+    paper prices its potentials, Fig. 4): velocity Verlet with the 2/3/4-body
+    model of the main leg (synthetic coefficients standardised on the box's
+    descriptors and scaled to a gentle potential), Maxwell-Boltzmann
+    velocities at T, skin list built and
+    rebuilt on the device.  Reported per step and per atom-step."""
+    import torch
+
+    from paper_2212_14446_amd import md, pod, workloads as wl
+    w = wl.config2(5.0)
+    m = pod.PodModel(pod.setup_from_workload(w.setup), dtype)
+    kB = 8.617333262e-5   # eV / K
+    acc = 1.602176634e-19 / 1e-10 / 1.66053906660e-27 * 1e-20
+    rng = np.random.default_rng(21)
+    vel = rng.normal(0.0, np.sqrt(kB * T * acc / md.MASS_TA), size=w.pos.shape)
+    vel -= vel.mean(0)
+    nb0 = pod.DeviceNeighbors.from_list(w.nl)
+    D = m.descriptors(w.pos, w.cell, nb0).double().cpu().numpy()
+    c = 0.02 * wl.standardised_coefficients(D, w.setup, seed=8)   # forces below ~0.2 eV/A
+    dyn = md.MD(m, w.pos, vel, w.cell, c, skin=0.5)
+    dyn.run(20, chunk=20, dt=dt)                 # warm-up
+    torch.cuda.synchronize()
+    r0 = dyn.rebuilds
+    t0 = time.perf_counter()
+    ep, ek = dyn.run(steps, chunk=20, dt=dt)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    et = (ep + ek).cpu().numpy()
+    return {"workload": f"{w.name}: {w.N} atoms, {dtype.upper()}, {T:g} K, dt {dt:g} fs, skin 0.5 A",
+            "steps": steps, "ms_per_step": ms, "s_per_atom_step": ms * 1e-3 / w.N,
+            "atom_steps_per_s": w.N / (ms * 1e-3), "rebuilds": dyn.rebuilds - r0,
+            "energy_drift_eV_per_atom": float(np.abs(et - et[0]).max() / w.N)}
+
+
+@on_stream
 def run_surrogate(steps, epochs=30):
     """Config-5 experiment, all on the device through the library."""
     import itertools
@@ -491,6 +528,7 @@ def main():
     ap.add_argument("--no-autograd", action="store_true")
     ap.add_argument("--no-neighbors", action="store_true")
     ap.add_argument("--no-opod", action="store_true")
+    ap.add_argument("--no-md", action="store_true")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (a known-size "
                          "kernel for scaling hardware traffic counters)")
@@ -555,6 +593,9 @@ def main():
     if not args.no_neighbors:
         rec["neighbors"] = run_neighbors(10)
         print(f"[bench] neighbors {rec['neighbors']}", file=sys.stderr, flush=True)
+    if not args.no_md:
+        rec["md"] = {dt: run_md(200, dt) for dt in ("f64", "f32")}
+        print(f"[bench] md {rec['md']}", file=sys.stderr, flush=True)
     if not args.no_opod:
         rec["opod_vs_fast"] = run_opod(20)
     if not args.no_batch:

@@ -59,6 +59,7 @@ class MD:
         ep = torch.empty(max(nsteps, 1), dtype=torch.float64, device=self.m.device)
         ek = torch.empty(max(nsteps, 1), dtype=torch.float64, device=self.m.device)
         done = 0
+        d_prev = 0.0
         while done < nsteps:
             k = min(chunk, nsteps - done)
             saved = (self.x.clone(), self.v.clone(), self.F.clone())
@@ -77,5 +78,12 @@ class MD:
                     raise RuntimeError("atoms move more than half the skin in one step")
                 d = self._chunk(k, dt, ep[done:], ek[done:])
             done += k
+            if rebuilt:
+                d_prev = 0.0
+            # rebuild ahead when the next chunk would likely cross half the skin
+            if d + 1.5 * max(d - d_prev, 0.0) > 0.5 * self.skin:
+                self._rebuild()
+                d = 0.0
+            d_prev = d
         self.m.check()
         return ep[:nsteps], ek[:nsteps]
