@@ -430,3 +430,32 @@ def config3(n_cfg: int = 2000) -> Batch:
     """2,000 cells of 2-250 atoms (seed 6), 2/3/4-body parameters of the
     15,840-atom box."""
     return make_batch(n_cfg, seed=6, setup=SETUP_CFG2)
+
+
+@dataclass
+class AcsfSpec:
+    """Parameters of a set of atom-centred symmetry functions (Sec. III.B):
+    radial functions G2 (eta, r_s), angular functions G3 (eta, zeta, lambda)
+    and four-body functions G4 (eta, a, b, c, alpha, beta, gamma), with
+    non-negative integer exponents zeta, a, b, c.  Descriptor order: all G2,
+    then all G3, then all G4, each in the order given."""
+    g2: tuple = ()
+    g3: tuple = ()
+    g4: tuple = ()
+
+    @property
+    def n(self) -> int:
+        return len(self.g2) + len(self.g3) + len(self.g4)
+
+
+def acsf_standard() -> AcsfSpec:
+    """34 functions in the usual Behler-Parrinello pattern for a 5 A cut-off:
+    8 radial shells (eta = 2 / A^2, r_s = 1.5 .. 5.0 A), 18 angular functions
+    (eta in {0.005, 0.05, 0.2} / A^2, zeta in {1, 2, 4}, lambda = +-1) and 8
+    four-body functions (eta in {0.005, 0.05}, (a, b, c) in {(1,1,1),
+    (2,1,1)}, alpha = beta = gamma = +-1)."""
+    g2 = tuple((2.0, 1.5 + 0.5 * k) for k in range(8))
+    g3 = tuple((eta, z, lam) for eta in (0.005, 0.05, 0.2) for z in (1, 2, 4) for lam in (1.0, -1.0))
+    g4 = tuple((eta, a, b, c, s, s, s) for eta in (0.005, 0.05) for (a, b, c) in ((1, 1, 1), (2, 1, 1))
+               for s in (1.0, -1.0))
+    return AcsfSpec(g2, g3, g4)
