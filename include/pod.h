@@ -345,6 +345,66 @@ int pod_fit_gram(pod_handle* h, int M, int n_cfg, const double* G, const double*
  * latches POD_ESINGULAR (pod_check), with c = 0 and loss = NaN. */
 int pod_fit_solve(pod_handle* h, int M, const double* Z, double gamma, double* c, double* loss);
 
+/* Atom-centred symmetry functions (Sec. III.B) through the atomic basis of
+ * Sec. II.E, in work linear in the number of neighbours:
+ *   G2_i = sum_j exp(-eta (r_ij - r_s)^2) f_c(r_ij)                eq. (21c)
+ *   G3_i = 2^(1-zeta) sum_{j,k} (1 + lambda w_ijk)^zeta
+ *          exp(-eta (r_ij^2 + r_ik^2)) f_c(r_ij) f_c(r_ik)          eq. (22c)
+ *   G4_i = sum_{j,k,l} (1 + alpha w_ijk)^a (1 + beta w_ijl)^b (1 + gamma w_ikl)^c
+ *          exp(-eta (r_ij^2 + r_ik^2 + r_il^2)) f_c f_c f_c          eq. (22d)
+ * with f_c the cut-off of eq. (8) at the handle's rin and rcut (same
+ * cut-off contract as the POD calls) and w_ijk = rhat_ij . rhat_ik.  The sums
+ * run over all ordered neighbour tuples, repeated indices included, as the
+ * POD sums of eqs. (15) and (18a) do.  Each function is a fixed combination
+ * of the 3- and 4-body invariants (eqs. (26a), (27a), (30a)) of the atomic
+ * basis of its radial function exp(-eta (r - r_s)^2) f_c(r); functions with
+ * equal (eta, r_s) share one basis.
+ *
+ * pod_acsf_create builds a set for the handle's dtype (host arrays):
+ *   g2 : n2 x 2 (eta, r_s)
+ *   g3 : n3 x 3 (eta, zeta, lambda), zeta an integer in [0, 6]
+ *   g4 : n4 x 7 (eta, a, b, c, alpha, beta, gamma), a, b, c non-negative
+ *        integers with a + b + c <= 6
+ * Functions are numbered G2 first, then G3, then G4, in the order given;
+ * 1 <= n2 + n3 + n4 <= POD_ACSF_MAX_FUNCTIONS, at most POD_ACSF_MAX_CHANNELS
+ * distinct (eta, r_s).  POD_EINVAL for non-finite or non-integral
+ * parameters, POD_ENOTSUP beyond the limits.  *out owns device memory
+ * released by pod_acsf_free; it is used only with handles of its dtype. */
+#define POD_ACSF_MAX_FUNCTIONS 1024
+#define POD_ACSF_MAX_CHANNELS 64
+#define POD_ACSF_MAX_DEGREE 6
+typedef struct pod_acsf pod_acsf;
+int pod_acsf_create(pod_handle* h, int n2, const double* g2, int n3, const double* g3, int n4,
+                    const double* g4, pod_acsf** out);
+
+/* Number of functions and of distinct radial channels of a set (host). */
+int pod_acsf_num_functions(const pod_acsf* a, int* n_functions, int* n_channels);
+
+/* G (N x n_functions row-major, device, handle dtype) for the list of the
+ * POD calls.  Asynchronous on the handle's stream; data errors are latched
+ * as for pod_descriptors (pod_check). */
+int pod_acsf_descriptors(pod_handle* h, const pod_acsf* a, int N, int P, const void* pos,
+                         const double* cell, const int* offsets, const int* nbr_j,
+                         const int* shift, void* G);
+
+/* Forces of E = sum_i W_i . G_i (the vector-Jacobian product of the
+ * functions, i.e. the force of a network potential given dE/dG_i):
+ *   W   : weights (device, handle dtype), row i at W + i * ldw; ldw = 0 uses
+ *         one row for every atom (a linear model), else ldw >= n_functions
+ *   rev : reverse-pair index from pod_neighbor_reverse (required when P > 0)
+ *   G   : N x n_functions (device) or NULL: the functions, written as well
+ *   F   : N x 3 (device, handle dtype): F = -dE/dx
+ * Three kernels on the handle's stream (basis and adjoint per radial
+ * channel, per-pair gradients, per-atom gather: no atomics, the result is
+ * reproducible); the handle's scratch holds N x (sum of the basis sizes)
+ * adjoint values and P x 3 pair gradients.  Data errors as above. */
+int pod_acsf_forces(pod_handle* h, const pod_acsf* a, int N, int P, const void* pos,
+                    const double* cell, const int* offsets, const int* nbr_j, const int* shift,
+                    const int* rev, const void* W, long ldw, void* G, void* F);
+
+/* Release a set (no device call may still use it). NULL is allowed. */
+void pod_acsf_free(pod_acsf* a);
+
 /* Diagnostics.  pod_set_kernel_timing(h, n) with n > 0 makes the next n
  * compute calls record pairs of HIP events on the handle's stream around each
  * of their kernels (n = 0 switches recording off).  pod_get_kernel_time waits
@@ -353,7 +413,9 @@ int pod_fit_solve(pod_handle* h, int M, const double* Z, double gamma, double* c
  * basis, atomic basis, contractions, energy, adjoint, per-pair gradients)
  * and the batched-assembly kernel; kind 0: the finalize kernel (totals E, W,
  * G and the force copy-out); kind 2: the network kernels; kind 3: the Gram
- * kernels of pod_fit_gram -- then resets that count. */
+ * kernels of pod_fit_gram; for the symmetry functions, kind 1 times the
+ * basis kernels and kind 0 the pair-gradient and gather kernels -- then
+ * resets that count. */
 int pod_set_kernel_timing(pod_handle* h, int n);
 int pod_get_kernel_time(pod_handle* h, int kind, double* total_ms, int* launches);
 

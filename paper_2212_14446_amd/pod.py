@@ -91,6 +91,12 @@ def lib():
     L.pod_mlp_train_step.argtypes = [_vp, i, i, _vp, lg, _vp, _vp, _vp, _vp, _vp, _vp, i, f, f, f, f, _vp]
     L.pod_energy_forces_surrogate.argtypes = [_vp, i, i, _vp, _dp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                               _vp, _vp, _vp]
+    L.pod_acsf_create.argtypes = [_vp, i, _dp, i, _dp, i, _dp, P(_vp)]
+    L.pod_acsf_num_functions.argtypes = [_vp, P(i), P(i)]
+    L.pod_acsf_descriptors.argtypes = [_vp, _vp, i, i, _vp, _dp, _vp, _vp, _vp, _vp]
+    L.pod_acsf_forces.argtypes = [_vp, _vp, i, i, _vp, _dp, _vp, _vp, _vp, _vp, _vp, lg, _vp, _vp]
+    L.pod_acsf_free.argtypes = [_vp]
+    L.pod_acsf_free.restype = None
     L.pod_check.argtypes = [_vp]
     L.pod_set_kernel_timing.argtypes = [_vp, i]
     L.pod_get_kernel_time.argtypes = [_vp, i, _dp, P(i)]
@@ -103,7 +109,8 @@ def lib():
                  "pod_neighbor_reverse", "pod_batch_assemble", "pod_mlp_num_params", "pod_mlp_forward",
                  "pod_mlp_train_step", "pod_energy_forces_surrogate", "pod_build_neighbors", "pod_fit_gram",
                  "pod_fit_solve", "pod_opod_descriptors", "pod_opod_energy_forces", "pod_md_verlet",
-                 "pod_md_max_displacement"):
+                 "pod_md_max_displacement", "pod_acsf_create", "pod_acsf_num_functions", "pod_acsf_descriptors",
+                 "pod_acsf_forces"):
         getattr(L, name).restype = i
     _lib = L
     return L
@@ -352,6 +359,57 @@ def pod_free(h: Handle):
         h.ptr = None
 
 
+class AcsfSet:
+    """A set of symmetry functions created on the device for one handle."""
+
+    def __init__(self, ptr, h: Handle, n_functions: int, n_channels: int):
+        self.ptr = ptr
+        self.h = h            # keeps the handle alive as long as the set
+        self.n = n_functions
+        self.n_channels = n_channels
+
+    def __del__(self):
+        try:
+            pod_acsf_free(self)
+        except Exception:
+            pass
+
+
+def _acsf_rows(rows, width):
+    arr = np.ascontiguousarray(np.asarray(rows, dtype=np.float64).reshape(-1, width))
+    return arr, (arr.ctypes.data_as(_dp) if arr.size else None)
+
+
+def pod_acsf_create(h: Handle, g2=(), g3=(), g4=()) -> AcsfSet:
+    a2, p2 = _acsf_rows(g2, 2)
+    a3, p3 = _acsf_rows(g3, 3)
+    a4, p4 = _acsf_rows(g4, 7)
+    out = ctypes.c_void_p()
+    _ok(lib().pod_acsf_create(h.ptr, a2.shape[0], p2, a3.shape[0], p3, a4.shape[0], p4, ctypes.byref(out)),
+        "pod_acsf_create")
+    n, nc = ctypes.c_int(), ctypes.c_int()
+    _ok(lib().pod_acsf_num_functions(out, ctypes.byref(n), ctypes.byref(nc)), "pod_acsf_num_functions")
+    return AcsfSet(out, h, n.value, nc.value)
+
+
+def pod_acsf_descriptors(h: Handle, a: AcsfSet, N, P, pos, cell, offsets, nbr_j, shift, G):
+    arr, cp = _cell_ptr(cell)
+    _ok(lib().pod_acsf_descriptors(h.ptr, a.ptr, int(N), int(P), _ptr(pos), cp, _ptr(offsets), _ptr(nbr_j),
+                                   _ptr(shift), _ptr(G)), "pod_acsf_descriptors")
+
+
+def pod_acsf_forces(h: Handle, a: AcsfSet, N, P, pos, cell, offsets, nbr_j, shift, rev, W, ldw, F, G=None):
+    arr, cp = _cell_ptr(cell)
+    _ok(lib().pod_acsf_forces(h.ptr, a.ptr, int(N), int(P), _ptr(pos), cp, _ptr(offsets), _ptr(nbr_j),
+                              _ptr(shift), _ptr(rev), _ptr(W), int(ldw), _ptr(G), _ptr(F)), "pod_acsf_forces")
+
+
+def pod_acsf_free(a: AcsfSet):
+    if a.ptr:
+        lib().pod_acsf_free(a.ptr)
+        a.ptr = None
+
+
 # --------------------------------------------------------------------------
 # Convenience wrapper
 # --------------------------------------------------------------------------
@@ -480,6 +538,36 @@ class PodModel:
         if check:
             pod_check(self.h)
         return o
+
+    def acsf(self, spec) -> AcsfSet:
+        """A symmetry-function set (workloads.AcsfSpec or anything with g2,
+        g3, g4) on this handle: its rin, rcut, dtype and stream."""
+        return pod_acsf_create(self.h, spec.g2, spec.g3, spec.g4)
+
+    def acsf_descriptors(self, a: AcsfSet, pos, cell, nbrs: DeviceNeighbors, check=True):
+        import torch
+        pos = self._pos(pos)
+        G = torch.empty((nbrs.N, a.n), dtype=self.torch_dtype, device=self.device)
+        pod_acsf_descriptors(self.h, a, nbrs.N, nbrs.P, pos, cell, nbrs.offsets, nbrs.nbr_j, nbrs.shift, G)
+        if check:
+            pod_check(self.h)
+        return G
+
+    def acsf_forces(self, a: AcsfSet, pos, cell, nbrs: DeviceNeighbors, W, with_G=False, check=True):
+        """F = -d(sum_i W_i . G_i)/dx; W is [n] (shared) or [N, n]."""
+        import torch
+        pos = self._pos(pos)
+        W = torch.as_tensor(W, dtype=self.torch_dtype, device=self.device).contiguous()
+        ldw = 0 if W.dim() == 1 else int(W.shape[1])
+        if nbrs.rev is None:
+            nbrs.build_reverse(self, check=check)
+        F = torch.empty((nbrs.N, 3), dtype=self.torch_dtype, device=self.device)
+        G = torch.empty((nbrs.N, a.n), dtype=self.torch_dtype, device=self.device) if with_G else None
+        pod_acsf_forces(self.h, a, nbrs.N, nbrs.P, pos, cell, nbrs.offsets, nbrs.nbr_j, nbrs.shift, nbrs.rev, W,
+                        ldw, F, G)
+        if check:
+            pod_check(self.h)
+        return (F, G) if with_G else F
 
     def energy_forces_surrogate(self, pos, cell, nbrs: DeviceNeighbors, c, net, forces=True, virial=True,
                                 per_atom=True, check=True, out=None):
