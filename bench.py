@@ -383,6 +383,61 @@ def run_opod(steps, warmup=3):
 
 
 @on_stream
+def run_acsf(steps, warmup=3):
+    """Atom-centred symmetry functions (eqs. (21c), (22c), (22d)) through the
+    atomic basis on the 15,840-atom box: the 34-function set of
+    workloads.acsf_standard (8 radial, 18 angular, 8 four-body functions, 11
+    radial channels), the functions alone and the forces of E = sum_i W . G_i
+    with the functions, FP64 and FP32; per-kernel times from HIP events on
+    the leg's stream."""
+    import numpy as np
+    import torch
+
+    from paper_2212_14446_amd import pod, workloads as wl
+    w = wl.config2(5.0)
+    spec = wl.acsf_standard()
+    setup = wl.PodSetup(w.setup.rin, w.setup.rcut, 6, 2, 2, 0, 2, 0)   # rin, rcut of the box's potential
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    out = {"workload": f"{w.name}: {w.N} atoms, {w.nl.n_pairs} pairs, {spec.n} functions"}
+    for dt in ("f64", "f32"):
+        m = pod.PodModel(pod.setup_from_workload(setup), dt)
+        a = m.acsf(spec)
+        nb = pod.DeviceNeighbors.from_list(w.nl)
+        nb.build_reverse(m)
+        x = m._pos(w.pos)
+        G = torch.empty((w.N, a.n), dtype=m.torch_dtype, device="cuda")
+        F = torch.empty((w.N, 3), dtype=m.torch_dtype, device="cuda")
+        W = torch.tensor(np.random.default_rng(5).normal(size=a.n), dtype=m.torch_dtype, device="cuda")
+        args = (w.N, nb.P, x, w.cell, nb.offsets, nb.nbr_j, nb.shift)
+        t_d = timed(lambda: pod.pod_acsf_descriptors(m.h, a, *args, G))
+        t_f = timed(lambda: pod.pod_acsf_forces(m.h, a, *args, nb.rev, W, 0, F, G))
+        pod.pod_set_kernel_timing(m.h, steps)
+        for _ in range(steps):
+            pod.pod_acsf_forces(m.h, a, *args, nb.rev, W, 0, F, G)
+        kb, nkb = pod.pod_get_kernel_time(m.h, 1)
+        kp, nkp = pod.pod_get_kernel_time(m.h, 0)
+        pod.pod_set_kernel_timing(m.h, 0)
+        m.check()
+        out[dt] = {"descriptors_ms": t_d, "forces_ms": t_f, "descriptors_atoms_per_s": w.N / (t_d * 1e-3),
+                   "forces_atoms_per_s": w.N / (t_f * 1e-3), "basis_kernels_ms": kb / steps,
+                   "pair_and_gather_ms": kp / steps}
+        print(f"[bench] acsf {dt} {out[dt]}", file=sys.stderr, flush=True)
+    return out
+
+
+@on_stream
 def run_md(steps, dtype="f64", T=300.0, dt=1.0):
     """NVE molecular dynamics on the 15,840-atom box (the use by which the
     paper prices its potentials, Fig. 4): velocity Verlet with the 2/3/4-body
@@ -529,6 +584,7 @@ def main():
     ap.add_argument("--no-neighbors", action="store_true")
     ap.add_argument("--no-opod", action="store_true")
     ap.add_argument("--no-md", action="store_true")
+    ap.add_argument("--no-acsf", action="store_true")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (a known-size "
                          "kernel for scaling hardware traffic counters)")
@@ -598,6 +654,8 @@ def main():
         print(f"[bench] md {rec['md']}", file=sys.stderr, flush=True)
     if not args.no_opod:
         rec["opod_vs_fast"] = run_opod(20)
+    if not args.no_acsf:
+        rec["acsf"] = run_acsf(20)
     if not args.no_batch:
         rec["batch"] = run_batch(10, 2)
         print(f"[bench] batch {rec['batch']}", file=sys.stderr, flush=True)
