@@ -20,11 +20,11 @@
 // with coefficients built once on the host.
 //
 // Kernels (handle dtype T):
-//   basis_kernel<PD>  one thread per atom, one channel per grid row, for the
-//                     channels of angular degree class PD (0, 2, 4, 6): B in
-//                     registers, invariants, functions; with weights W, the
-//                     adjoint dL/dB of the channel (written to scratch).
-//   pair_kernel<PDM>  one wave per atom, one lane per pair: the derivative of
+//   basis_kernel<PD>  four lanes per atom, a few channels of angular degree
+//                     class PD (0, 2, 4, 6) per grid row: B in registers,
+//                     invariants, functions; with weights W, the adjoint
+//                     dL/dB of each channel (written to scratch).
+//   pair_kernel<PDM>  one thread per pair: the derivative of
 //                     sum_c dL/dB_c . B_c with respect to r_ij (eq. (24c) with
 //                     g, g' in place of R_m, R'_m), summed over channels.
 //   gather_kernel     F_i = sum over the pairs p of i of (V_p - V_rev(p)).
@@ -47,6 +47,12 @@ constexpr int ACSF_NI = 31;          // [B_0 | S_0..S_6 | T_p, p < 23]
 constexpr int ACSF_S0 = 1;
 constexpr int ACSF_T0 = 8;
 constexpr int ACSF_THREADS = 256;
+constexpr int ACSF_SPLIT = 4;                          // lanes per atom in the basis kernels
+constexpr int ACSF_APB = ACSF_THREADS / ACSF_SPLIT;    // atoms per basis block
+constexpr int GATHER_LANES = 16;                       // lanes per atom in the force gather
+
+// Channels of one degree class a basis thread carries at once.
+constexpr int channels_per_thread(int pd) { return pd == 0 ? 8 : (pd == 2 ? 2 : 1); }
 
 // Degree class of a channel: the smallest instantiated PD >= need.
 int degree_class(int need) { return need <= 0 ? 0 : (need <= 2 ? 2 : (need <= 4 ? 4 : 6)); }
@@ -158,33 +164,16 @@ __device__ __forceinline__ void cutoff(T r, T rin, T inv_h, T& fc, T& dfc) {
     dfc = fc * y * (rs * rs * rs) * (T(-3) * t2 * inv_h);
 }
 
+// Invariants of one channel from its basis B, the functions of the channel
+// and (ADJ) the adjoint dL/dB for L = sum_d W_d G_d; written when `write`.
 template <typename T, int PD, bool ADJ>
-__global__ __launch_bounds__(ACSF_THREADS) void basis_kernel(AArgs<T> g, const int* __restrict__ chans) {
+__device__ __forceinline__ void finish_channel(const AArgs<T>& g, const AChan<T>& ch, int i,
+                                               const T (&B)[n_mono(PD)], bool write) {
     constexpr MonoTable<PD> mt{};
     constexpr int NA = n_mono(PD);
     using Tab = D4Table<PD>;
     constexpr int KA = Tab::KA;
     constexpr int NT = Tab::NT;
-    const int c = chans[blockIdx.y];
-    const AChan<T> ch = g.ch[c];
-    const int i = blockIdx.x * ACSF_THREADS + threadIdx.x;
-    if (i >= g.N) return;
-
-    T B[NA];
-#pragma unroll
-    for (int mu = 0; mu < NA; ++mu) B[mu] = T(0);
-    int p0, p1;
-    pair_range(g, i, p0, p1);
-    for (int p = p0; p < p1; ++p) {
-        T r, ux, uy, uz;
-        if (!pair_geometry(g, i, p, r, ux, uy, uz)) continue;
-        T fc, dfc;
-        cutoff(r, g.rin, g.inv_h, fc, dfc);
-        const T x = r - ch.rs;
-        dev::accumulate_basis<T, PD>(B, dev::d_exp(-ch.eta * x * x) * fc, ux, uy, uz);
-    }
-
-    // invariants
     T S[PD + 1];
 #pragma unroll
     for (int n = 0; n <= PD; ++n) S[n] = T(0);
@@ -197,7 +186,7 @@ __global__ __launch_bounds__(ACSF_THREADS) void basis_kernel(AArgs<T> g, const i
     for (int t = 0; t < NT; ++t)
         Tq[Tab::build.tp[t]] += T(Tab::build.tc[t]) * B[Tab::build.tx[t]] * B[Tab::build.ty[t]] * B[Tab::build.tz[t]];
 
-    if (g.G) {
+    if (g.G && write) {
         for (int d = ch.d0; d < ch.d1; ++d) {
             const T* cf = g.coef + static_cast<size_t>(d) * ACSF_NI;
             T v = cf[0] * B[0];
@@ -248,10 +237,63 @@ __global__ __launch_bounds__(ACSF_THREADS) void basis_kernel(AArgs<T> g, const i
         bb[0] += b0;
 #pragma unroll
         for (int mu = 0; mu < NA; ++mu) bb[mu] += T(2 * mt.mult[mu]) * B[mu] * Sb[mt.deg[mu]];
-        T* out = g.bbar + static_cast<size_t>(g.N) * ch.bpre + static_cast<size_t>(i) * NA;
+        if (write) {
+            T* out = g.bbar + static_cast<size_t>(g.N) * ch.bpre + static_cast<size_t>(i) * NA;
 #pragma unroll
-        for (int mu = 0; mu < NA; ++mu) out[mu] = bb[mu];
+            for (int mu = 0; mu < NA; ++mu) out[mu] = bb[mu];
+        }
     }
+}
+
+// One atom per ACSF_SPLIT consecutive lanes, which share its neighbours (lane
+// s takes pairs s, s + ACSF_SPLIT, ...) and sum their partial bases with
+// butterfly shuffles (a fixed order, identical on the lanes); each thread
+// carries the bases of up to channels_per_thread(PD) channels of the class,
+// so the pair geometry and f_c are computed once for all of them.
+template <typename T, int PD, bool ADJ>
+__global__ __launch_bounds__(ACSF_THREADS) void basis_kernel(AArgs<T> g, const int* __restrict__ chans, int nclass) {
+    constexpr int NA = n_mono(PD);
+    constexpr int NC = channels_per_thread(PD);
+    const int c0 = blockIdx.y * NC;
+    const int nc = min(NC, nclass - c0);
+    AChan<T> ch[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) ch[k] = g.ch[chans[c0 + (k < nc ? k : 0)]];
+    const int i = blockIdx.x * ACSF_APB + static_cast<int>(threadIdx.x) / ACSF_SPLIT;
+    const int sub = static_cast<int>(threadIdx.x) % ACSF_SPLIT;
+    if (i >= g.N) return;   // the whole group of the atom
+
+    T B[NC][NA];
+#pragma unroll
+    for (int k = 0; k < NC; ++k)
+#pragma unroll
+        for (int mu = 0; mu < NA; ++mu) B[k][mu] = T(0);
+    int p0, p1;
+    pair_range(g, i, p0, p1);
+    for (int p = p0 + sub; p < p1; p += ACSF_SPLIT) {
+        T r, ux, uy, uz;
+        if (!pair_geometry(g, i, p, r, ux, uy, uz)) continue;
+        T fc, dfc;
+        cutoff(r, g.rin, g.inv_h, fc, dfc);
+#pragma unroll
+        for (int k = 0; k < NC; ++k)
+            if (k < nc) {
+                const T x = r - ch[k].rs;
+                dev::accumulate_basis<T, PD>(B[k], dev::d_exp(-ch[k].eta * x * x) * fc, ux, uy, uz);
+            }
+    }
+#pragma unroll
+    for (int k = 0; k < NC; ++k)
+#pragma unroll
+        for (int mu = 0; mu < NA; ++mu) {
+            T v = B[k][mu];
+#pragma unroll
+            for (int o = 1; o < ACSF_SPLIT; o <<= 1) v += __shfl_xor(v, o);
+            B[k][mu] = v;
+        }
+#pragma unroll
+    for (int k = 0; k < NC; ++k)
+        if (k < nc) finish_channel<T, PD, ADJ>(g, ch[k], i, B[k], sub == 0);
 }
 
 // sum_mu bb_mu A_mu (h), its u-gradient (q) and the Euler sum u . grad h =
@@ -274,68 +316,72 @@ __device__ __forceinline__ void contract(const T* __restrict__ bb, const T (&A)[
     }
 }
 
+// One thread per pair; its centre atom i (offsets[i] <= p < offsets[i + 1])
+// by binary search, so a pair outside every range gets a zero gradient.
 template <typename T, int PDM>
 __global__ __launch_bounds__(ACSF_THREADS) void pair_kernel(AArgs<T> g, int nch) {
     constexpr MonoTable<PDM> mt{};
     constexpr int NAM = n_mono(PDM);
-    const int i = __builtin_amdgcn_readfirstlane(static_cast<int>(blockIdx.x * (ACSF_THREADS / WAVE) +
-                                                                  (threadIdx.x >> 6)));
-    if (i >= g.N) return;
-    const int lane = threadIdx.x & (WAVE - 1);
-    int p0, p1;
-    pair_range(g, i, p0, p1);
-    for (int p = p0 + lane; p < p1; p += WAVE) {
-        T v0 = T(0), v1 = T(0), v2 = T(0);
-        T r, ux, uy, uz;
-        if (pair_geometry(g, i, p, r, ux, uy, uz)) {
-            T fc, dfc;
-            cutoff(r, g.rin, g.inv_h, fc, dfc);
-            const T ir = T(1) / r;
-            T A[NAM];
-            A[0] = T(1);
-#pragma unroll
-            for (int mu = 1; mu < NAM; ++mu) {
-                const T u = mt.axis[mu] == 0 ? ux : (mt.axis[mu] == 1 ? uy : uz);
-                A[mu] = A[mt.par[mu]] * u;
-            }
-            for (int c = 0; c < nch; ++c) {
-                const AChan<T> ch = g.ch[c];
-                const T x = r - ch.rs;
-                const T e = dev::d_exp(-ch.eta * x * x);
-                const T gv = e * fc;
-                const T gd = e * (dfc - T(2) * ch.eta * x * fc);
-                T h, eul, q0, q1, q2;
-                const T* bb = g.bbar + static_cast<size_t>(g.N) * ch.bpre + static_cast<size_t>(i) * n_mono(ch.pd);
-                switch (ch.pd) {
-                    case 0: contract<T, 0, PDM>(bb, A, h, eul, q0, q1, q2); break;
-                    case 2: if constexpr (PDM >= 2) contract<T, 2, PDM>(bb, A, h, eul, q0, q1, q2); break;
-                    case 4: if constexpr (PDM >= 4) contract<T, 4, PDM>(bb, A, h, eul, q0, q1, q2); break;
-                    default: if constexpr (PDM >= 6) contract<T, 6, PDM>(bb, A, h, eul, q0, q1, q2); break;
-                }
-                // d/dr_ij of g(r) h(u): g' h rhat + g (grad_u h - (u . grad_u h) u) / r
-                const T c1 = gd * h - gv * eul * ir;
-                const T c2 = gv * ir;
-                v0 += c1 * ux + c2 * q0;
-                v1 += c1 * uy + c2 * q1;
-                v2 += c1 * uz + c2 * q2;
-            }
-        }
-        g.V[3 * static_cast<size_t>(p)] = v0;
-        g.V[3 * static_cast<size_t>(p) + 1] = v1;
-        g.V[3 * static_cast<size_t>(p) + 2] = v2;
+    const int p = blockIdx.x * ACSF_THREADS + threadIdx.x;
+    if (p >= g.P) return;
+    int lo = 0, hi = g.N;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (g.offsets[mid] <= p) lo = mid; else hi = mid;
     }
+    const int i = lo;
+    T v0 = T(0), v1 = T(0), v2 = T(0);
+    T r, ux, uy, uz;
+    if (g.offsets[i] <= p && p < g.offsets[i + 1] && pair_geometry(g, i, p, r, ux, uy, uz)) {
+        T fc, dfc;
+        cutoff(r, g.rin, g.inv_h, fc, dfc);
+        const T ir = T(1) / r;
+        T A[NAM];
+        A[0] = T(1);
+#pragma unroll
+        for (int mu = 1; mu < NAM; ++mu) {
+            const T u = mt.axis[mu] == 0 ? ux : (mt.axis[mu] == 1 ? uy : uz);
+            A[mu] = A[mt.par[mu]] * u;
+        }
+        for (int c = 0; c < nch; ++c) {
+            const AChan<T> ch = g.ch[c];
+            const T x = r - ch.rs;
+            const T e = dev::d_exp(-ch.eta * x * x);
+            const T gv = e * fc;
+            const T gd = e * (dfc - T(2) * ch.eta * x * fc);
+            T h, eul, q0, q1, q2;
+            const T* bb = g.bbar + static_cast<size_t>(g.N) * ch.bpre + static_cast<size_t>(i) * n_mono(ch.pd);
+            switch (ch.pd) {
+                case 0: contract<T, 0, PDM>(bb, A, h, eul, q0, q1, q2); break;
+                case 2: if constexpr (PDM >= 2) contract<T, 2, PDM>(bb, A, h, eul, q0, q1, q2); break;
+                case 4: if constexpr (PDM >= 4) contract<T, 4, PDM>(bb, A, h, eul, q0, q1, q2); break;
+                default: if constexpr (PDM >= 6) contract<T, 6, PDM>(bb, A, h, eul, q0, q1, q2); break;
+            }
+            // d/dr_ij of g(r) h(u): g' h rhat + g (grad_u h - (u . grad_u h) u) / r
+            const T c1 = gd * h - gv * eul * ir;
+            const T c2 = gv * ir;
+            v0 += c1 * ux + c2 * q0;
+            v1 += c1 * uy + c2 * q1;
+            v2 += c1 * uz + c2 * q2;
+        }
+    }
+    g.V[3 * static_cast<size_t>(p)] = v0;
+    g.V[3 * static_cast<size_t>(p) + 1] = v1;
+    g.V[3 * static_cast<size_t>(p) + 2] = v2;
 }
 
 // F_i = -dE/dx_i: E_i depends on x_j - x_i through the pairs of i, and x_i
 // enters the pairs (j -> i) of its neighbours, which rev finds.
+// GATHER_LANES lanes per atom share its pairs and sum with butterfly shuffles.
 template <typename T>
 __global__ __launch_bounds__(ACSF_THREADS) void gather_kernel(AArgs<T> g) {
-    const int i = blockIdx.x * ACSF_THREADS + threadIdx.x;
-    if (i >= g.N) return;
+    const int i = blockIdx.x * (ACSF_THREADS / GATHER_LANES) + static_cast<int>(threadIdx.x) / GATHER_LANES;
+    const int l = static_cast<int>(threadIdx.x) % GATHER_LANES;
+    if (i >= g.N) return;   // the whole group of the atom
     T f0 = T(0), f1 = T(0), f2 = T(0);
     int p0, p1;
     pair_range(g, i, p0, p1);
-    for (int p = p0; p < p1; ++p) {
+    for (int p = p0 + l; p < p1; p += GATHER_LANES) {
         const int q = g.rev[p];
         f0 += g.V[3 * static_cast<size_t>(p)];
         f1 += g.V[3 * static_cast<size_t>(p) + 1];
@@ -348,9 +394,17 @@ __global__ __launch_bounds__(ACSF_THREADS) void gather_kernel(AArgs<T> g) {
         f1 -= g.V[3 * static_cast<size_t>(q) + 1];
         f2 -= g.V[3 * static_cast<size_t>(q) + 2];
     }
-    g.F[3 * static_cast<size_t>(i)] = f0;
-    g.F[3 * static_cast<size_t>(i) + 1] = f1;
-    g.F[3 * static_cast<size_t>(i) + 2] = f2;
+#pragma unroll
+    for (int o = 1; o < GATHER_LANES; o <<= 1) {
+        f0 += __shfl_xor(f0, o);
+        f1 += __shfl_xor(f1, o);
+        f2 += __shfl_xor(f2, o);
+    }
+    if (l == 0) {
+        g.F[3 * static_cast<size_t>(i)] = f0;
+        g.F[3 * static_cast<size_t>(i) + 1] = f1;
+        g.F[3 * static_cast<size_t>(i) + 2] = f2;
+    }
 }
 
 bool integral(double x, int lo, int hi, int* out) {
@@ -422,18 +476,19 @@ int fill_args(pod_handle* h, const pod_acsf* a, AArgs<T>& g, int N, int P, const
 
 template <typename T, bool ADJ>
 void launch_basis(pod_handle* h, const pod_acsf* a, const AArgs<T>& g) {
-    const int gx = (g.N + ACSF_THREADS - 1) / ACSF_THREADS;
+    const int gx = (g.N + ACSF_APB - 1) / ACSF_APB;
     for (int k = 0; k < 4; ++k) {
         const int n = a->cls_off[k + 1] - a->cls_off[k];
         if (n == 0) continue;
-        const dim3 grid(gx, n);
+        const int per = channels_per_thread(2 * k);
+        const dim3 grid(gx, (n + per - 1) / per);
         const int* chans = a->d_cls + a->cls_off[k];
         timing_begin(h, 1);
         switch (k) {
-            case 0: hipLaunchKernelGGL((basis_kernel<T, 0, ADJ>), grid, dim3(ACSF_THREADS), 0, h->stream, g, chans); break;
-            case 1: hipLaunchKernelGGL((basis_kernel<T, 2, ADJ>), grid, dim3(ACSF_THREADS), 0, h->stream, g, chans); break;
-            case 2: hipLaunchKernelGGL((basis_kernel<T, 4, ADJ>), grid, dim3(ACSF_THREADS), 0, h->stream, g, chans); break;
-            default: hipLaunchKernelGGL((basis_kernel<T, 6, ADJ>), grid, dim3(ACSF_THREADS), 0, h->stream, g, chans); break;
+            case 0: hipLaunchKernelGGL((basis_kernel<T, 0, ADJ>), grid, dim3(ACSF_THREADS), 0, h->stream, g, chans, n); break;
+            case 1: hipLaunchKernelGGL((basis_kernel<T, 2, ADJ>), grid, dim3(ACSF_THREADS), 0, h->stream, g, chans, n); break;
+            case 2: hipLaunchKernelGGL((basis_kernel<T, 4, ADJ>), grid, dim3(ACSF_THREADS), 0, h->stream, g, chans, n); break;
+            default: hipLaunchKernelGGL((basis_kernel<T, 6, ADJ>), grid, dim3(ACSF_THREADS), 0, h->stream, g, chans, n); break;
         }
         timing_end(h, 1);
     }
@@ -469,8 +524,7 @@ int forces_impl(pod_handle* h, const pod_acsf* a, int N, int P, const void* pos,
     g.rev = rev;
     g.F = static_cast<T*>(F);
     launch_basis<T, true>(h, a, g);
-    const int wpb = ACSF_THREADS / WAVE;
-    const dim3 pgrid((N + wpb - 1) / wpb);
+    const dim3 pgrid(P > 0 ? (P + ACSF_THREADS - 1) / ACSF_THREADS : 1);
     timing_begin(h, 0);
     switch (a->pd_max) {
         case 0: hipLaunchKernelGGL((pair_kernel<T, 0>), pgrid, dim3(ACSF_THREADS), 0, h->stream, g, a->nch); break;
@@ -478,8 +532,8 @@ int forces_impl(pod_handle* h, const pod_acsf* a, int N, int P, const void* pos,
         case 4: hipLaunchKernelGGL((pair_kernel<T, 4>), pgrid, dim3(ACSF_THREADS), 0, h->stream, g, a->nch); break;
         default: hipLaunchKernelGGL((pair_kernel<T, 6>), pgrid, dim3(ACSF_THREADS), 0, h->stream, g, a->nch); break;
     }
-    hipLaunchKernelGGL((gather_kernel<T>), dim3((N + ACSF_THREADS - 1) / ACSF_THREADS), dim3(ACSF_THREADS), 0,
-                       h->stream, g);
+    const int apg = ACSF_THREADS / GATHER_LANES;
+    hipLaunchKernelGGL((gather_kernel<T>), dim3((N + apg - 1) / apg), dim3(ACSF_THREADS), 0, h->stream, g);
     timing_end(h, 0);
     return hipGetLastError() == hipSuccess ? POD_OK : POD_EHIP;
 }
