@@ -345,6 +345,30 @@ int pod_fit_gram(pod_handle* h, int M, int n_cfg, const double* G, const double*
  * latches POD_ESINGULAR (pod_check), with c = 0 and loss = NaN. */
 int pod_fit_solve(pod_handle* h, int M, const double* Z, double gamma, double* c, double* loss);
 
+/* Five-body descriptors (the extension of Sec. II.F to higher body order,
+ * built like the four-body descriptors of eqs. (16a)-(18a)):
+ *   D5_{i m e} = sum_{j,k,l,n} R_m(r_ij) R_m(r_ik) R_m(r_il) R_m(r_in)
+ *                w_jk^e1 w_jl^e2 w_jn^e3 w_kl^e4 w_kn^e5 w_ln^e6
+ * with w_jk = rhat_ij . rhat_ik, over all ordered neighbour quadruples
+ * (repeated indices included), for exponent tuples e >= 0 with |e| <= P5.
+ * Relabelling the four neighbours permutes the six angle positions (order
+ * (j,k), (j,l), (j,n), (k,l), (k,n), (l,n)) without changing the sum; there
+ * is one descriptor per orbit, ordered by |e| ascending and, within a
+ * degree, by the orbit's lexicographically largest tuple, descending (1, 2,
+ * 5, 11, 22 descriptors for P5 = 0..4).  Evaluated through the atomic basis
+ * of eq. (24b) as sums of products of four basis values, the five-body
+ * counterpart of eq. (30a).
+ *   K5 : radial functions used, 1 <= K5 <= max(K2, K3, K4) of the handle
+ *   P5 : 0 <= P5 <= POD_FIVE_MAX_P (POD_ENOTSUP above)
+ *   D5 : N x (K5 * count) row-major (device, handle dtype), m-major
+ * Neighbour list, cut-off contract and data errors as for pod_descriptors;
+ * asynchronous on the handle's stream. */
+#define POD_FIVE_MAX_P 4
+int pod_five_body_count(int P5, int* n);
+int pod_five_body_descriptors(pod_handle* h, int N, int P, const void* pos, const double* cell,
+                              const int* offsets, const int* nbr_j, const int* shift, int K5,
+                              int P5, void* D5);
+
 /* Atom-centred symmetry functions (Sec. III.B) through the atomic basis of
  * Sec. II.E, in work linear in the number of neighbours:
  *   G2_i = sum_j exp(-eta (r_ij - r_s)^2) f_c(r_ij)                eq. (21c)

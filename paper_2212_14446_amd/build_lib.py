@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libpod.so")
 
-SOURCES = ["pod_host.cpp", "pod_kernels.hip", "pod_batch.hip", "pod_mlp.hip", "pod_neighbors.hip", "pod_fit.hip", "pod_opod.hip", "pod_md.hip", "pod_acsf.hip"]
+SOURCES = ["pod_host.cpp", "pod_kernels.hip", "pod_batch.hip", "pod_mlp.hip", "pod_neighbors.hip", "pod_fit.hip", "pod_opod.hip", "pod_md.hip", "pod_acsf.hip", "pod_five.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -1,0 +1,322 @@
+// Five-body descriptors through the atomic basis (the extension of Sec. II.F
+// to higher body order): with the four neighbours j, k, l, n of atom i and
+// the six angles between them,
+//   D5_{i m e} = sum_{j,k,l,n} R_m(r_ij) R_m(r_ik) R_m(r_il) R_m(r_in)
+//                w_jk^e1 w_jl^e2 w_jn^e3 w_kl^e4 w_kn^e5 w_ln^e6,
+// one descriptor per orbit of exponent tuples under the 24 relabellings of
+// (j, k, l, n), |e| <= P5.  Expanding every power as
+// (u . v)^a = sum_{|alpha| = a} mult(alpha) u^alpha v^alpha and collecting
+// the monomials of each neighbour,
+//   D5 = sum mult(alpha_1) ... mult(alpha_6)
+//        B_{alpha_1 + alpha_2 + alpha_3} B_{alpha_1 + alpha_4 + alpha_5}
+//        B_{alpha_2 + alpha_4 + alpha_6} B_{alpha_3 + alpha_5 + alpha_6},
+// the five-body counterpart of eq. (30a) with the atomic basis
+// B_{i m mu} = sum_j R_m(r_ij) u_ij^mu of eq. (24b).  Products with equal
+// sorted index quadruples are merged into one term at compile time.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "pod.h"
+#include "pod_device.h"
+#include "pod_internal.h"
+#include "pod_tables.h"
+
+namespace pod {
+namespace {
+
+constexpr int FIVE_MAX_ORBITS = 22;   // orbits with |e| <= 4
+constexpr int FIVE_CAP = 700;         // merged terms (at most the 680 raw products for |e| <= 4)
+constexpr int FIVE_THREADS = 256;
+constexpr int FIVE_SPLIT = 4;         // lanes per atom, sharing its neighbours
+constexpr int FIVE_APB = FIVE_THREADS / FIVE_SPLIT;
+
+// angle positions (j,k), (j,l), (j,n), (k,l), (k,n), (l,n) with j,k,l,n = 0..3
+constexpr int FIVE_EDGE[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+
+constexpr int edge_of(int a, int b) {
+    if (a > b) { const int t = a; a = b; b = t; }
+    for (int t = 0; t < 6; ++t)
+        if (FIVE_EDGE[t][0] == a && FIVE_EDGE[t][1] == b) return t;
+    return -1;
+}
+
+constexpr bool lex_less(const int (&a)[6], const int (&b)[6]) {
+    for (int t = 0; t < 6; ++t)
+        if (a[t] != b[t]) return a[t] < b[t];
+    return false;
+}
+
+// k-th monomial of degree n in the device order (c ascending, then b)
+constexpr void mono_of_degree(int n, int k, int& a, int& b, int& c) {
+    int q = 0;
+    for (int cc = 0; cc <= n; ++cc)
+        for (int bb = 0; bb <= n - cc; ++bb) {
+            if (q == k) { a = n - bb - cc; b = bb; c = cc; return; }
+            ++q;
+        }
+    a = b = c = 0;
+}
+
+template <int PD>
+struct FiveBuild {
+    int nd;                          // orbits with |e| <= PD, in descriptor order
+    int ex[FIVE_MAX_ORBITS][6];      // largest tuple of each orbit
+    int nt;
+    int td[FIVE_CAP], tx[FIVE_CAP], ty[FIVE_CAP], tz[FIVE_CAP], tw[FIVE_CAP], tc[FIVE_CAP];
+
+    constexpr FiveBuild() : nd(0), ex{}, nt(0), td{}, tx{}, ty{}, tz{}, tw{}, tc{} {
+        int perm[24][4] = {};
+        int np = 0;
+        for (int a = 0; a < 4; ++a)
+            for (int b = 0; b < 4; ++b)
+                for (int c = 0; c < 4; ++c)
+                    for (int d = 0; d < 4; ++d)
+                        if (a != b && a != c && a != d && b != c && b != d && c != d) {
+                            perm[np][0] = a; perm[np][1] = b; perm[np][2] = c; perm[np][3] = d;
+                            ++np;
+                        }
+        // orbits, degree by degree, each by its largest tuple, descending
+        for (int n = 0; n <= PD; ++n) {
+            const int first = nd;
+            int e[6] = {};
+            for (e[0] = 0; e[0] <= n; ++e[0])
+                for (e[1] = 0; e[1] <= n - e[0]; ++e[1])
+                    for (e[2] = 0; e[2] <= n - e[0] - e[1]; ++e[2])
+                        for (e[3] = 0; e[3] <= n - e[0] - e[1] - e[2]; ++e[3])
+                            for (e[4] = 0; e[4] <= n - e[0] - e[1] - e[2] - e[3]; ++e[4]) {
+                                e[5] = n - e[0] - e[1] - e[2] - e[3] - e[4];
+                                int best[6] = {};
+                                for (int q = 0; q < np; ++q) {
+                                    int img[6] = {};
+                                    for (int t = 0; t < 6; ++t)
+                                        img[edge_of(perm[q][FIVE_EDGE[t][0]], perm[q][FIVE_EDGE[t][1]])] = e[t];
+                                    if (q == 0 || lex_less(best, img))
+                                        for (int t = 0; t < 6; ++t) best[t] = img[t];
+                                }
+                                bool seen = false;
+                                for (int d = first; d < nd; ++d) {
+                                    bool same = true;
+                                    for (int t = 0; t < 6; ++t) same = same && ex[d][t] == best[t];
+                                    seen = seen || same;
+                                }
+                                if (!seen) {
+                                    for (int t = 0; t < 6; ++t) ex[nd][t] = best[t];
+                                    ++nd;
+                                }
+                            }
+            for (int x = first + 1; x < nd; ++x)          // insertion sort, descending
+                for (int y = x; y > first && lex_less(ex[y - 1], ex[y]); --y)
+                    for (int t = 0; t < 6; ++t) {
+                        const int s = ex[y][t];
+                        ex[y][t] = ex[y - 1][t];
+                        ex[y - 1][t] = s;
+                    }
+        }
+        // merged products of each orbit
+        for (int d = 0; d < nd; ++d) {
+            const int first = nt;
+            int cnt[6] = {}, idx[6] = {};
+            for (int t = 0; t < 6; ++t) cnt[t] = n_of_degree(ex[d][t]);
+            bool more = true;
+            while (more) {
+                int m[6][3] = {};
+                int coef = 1;
+                for (int t = 0; t < 6; ++t) {
+                    mono_of_degree(ex[d][t], idx[t], m[t][0], m[t][1], m[t][2]);
+                    coef *= factorial(ex[d][t]) / (factorial(m[t][0]) * factorial(m[t][1]) * factorial(m[t][2]));
+                }
+                int q[4] = {};
+                for (int v = 0; v < 4; ++v) {   // monomial of neighbour v: sum over its three angles
+                    int s[3] = {0, 0, 0};
+                    for (int t = 0; t < 6; ++t)
+                        if (FIVE_EDGE[t][0] == v || FIVE_EDGE[t][1] == v)
+                            for (int c = 0; c < 3; ++c) s[c] += m[t][c];
+                    q[v] = mono_index(s[0], s[1], s[2]);
+                }
+                for (int x = 1; x < 4; ++x)
+                    for (int y = x; y > 0 && q[y - 1] > q[y]; --y) {
+                        const int s = q[y];
+                        q[y] = q[y - 1];
+                        q[y - 1] = s;
+                    }
+                int hit = -1;
+                for (int k = first; k < nt; ++k)
+                    if (tx[k] == q[0] && ty[k] == q[1] && tz[k] == q[2] && tw[k] == q[3]) hit = k;
+                if (hit >= 0) {
+                    tc[hit] += coef;
+                } else {
+                    td[nt] = d; tx[nt] = q[0]; ty[nt] = q[1]; tz[nt] = q[2]; tw[nt] = q[3]; tc[nt] = coef;
+                    ++nt;
+                }
+                int t = 0;                    // next multi-index (odometer)
+                while (t < 6 && ++idx[t] == cnt[t]) idx[t++] = 0;
+                more = t < 6;
+            }
+        }
+    }
+};
+
+template <int PD>
+struct FiveTable {
+    static constexpr FiveBuild<PD> build{};
+    static constexpr int ND = build.nd;
+    static constexpr int NT = build.nt;
+};
+
+template <typename T>
+struct FArgs {
+    ParamsT<T> prm;   // by value: scalar loads
+    CellT<T> cell;
+    int N, P, K5, nd;
+    const T* pos;
+    const int* offsets;
+    const int* nbr_j;
+    const int* shift;
+    T* D5;
+    int* err;
+};
+
+template <typename T, int PD>
+__global__ __launch_bounds__(FIVE_THREADS) void five_kernel(FArgs<T> g) {
+    constexpr int NA = n_mono(PD);
+    using Tab = FiveTable<PD>;
+    const int m = blockIdx.y;
+    const int i = blockIdx.x * FIVE_APB + static_cast<int>(threadIdx.x) / FIVE_SPLIT;
+    const int sub = static_cast<int>(threadIdx.x) % FIVE_SPLIT;
+    if (i >= g.N) return;   // the whole group of the atom
+    T B[NA];
+#pragma unroll
+    for (int mu = 0; mu < NA; ++mu) B[mu] = T(0);
+    int p0 = max(g.offsets[i], 0), p1 = g.offsets[i + 1];
+    if (p1 > g.P) {
+        atomicOr(g.err, ERR_NEIGH);
+        p1 = g.P;
+    }
+    for (int p = p0 + sub; p < p1; p += FIVE_SPLIT) {
+        const int j = g.nbr_j[p];
+        const int sh = g.shift[p];
+        if (j < 0 || j >= g.N || (!g.cell.periodic && (sh & 0xFFFFFF) != 0)) {
+            atomicOr(g.err, ERR_NEIGH);
+            continue;
+        }
+        const T sx = static_cast<T>(dev::unpack_shift(sh, 0));
+        const T sy = static_cast<T>(dev::unpack_shift(sh, 1));
+        const T sz = static_cast<T>(dev::unpack_shift(sh, 2));
+        const T* c = g.cell.a;
+        const T d0 = g.pos[3 * j] - g.pos[3 * i] + sx * c[0] + sy * c[3] + sz * c[6];
+        const T d1 = g.pos[3 * j + 1] - g.pos[3 * i + 1] + sx * c[1] + sy * c[4] + sz * c[7];
+        const T d2 = g.pos[3 * j + 2] - g.pos[3 * i + 2] + sx * c[2] + sy * c[5] + sz * c[8];
+        const T r2 = d0 * d0 + d1 * d1 + d2 * d2;
+        if (!dev::d_finite(r2)) {
+            atomicOr(g.err, ERR_NONFINITE);
+            continue;
+        }
+        const T r = dev::d_sqrt(r2);
+        if (r <= g.prm.rin) {
+            atomicOr(g.err, ERR_RANGE);
+            continue;
+        }
+        if (r >= g.prm.rcut) continue;   // a skin-list entry: not a neighbour
+        const T ir = T(1) / r;
+        T R[POD_MAX_K], dR[POD_MAX_K];
+        dev::radial<T, false>(&g.prm, r, ir, R, dR);
+        T Rm = R[0];
+#pragma unroll
+        for (int k = 1; k < POD_MAX_K; ++k)
+            if (k == m) Rm = R[k];
+        dev::accumulate_basis<T, PD>(B, Rm, d0 * ir, d1 * ir, d2 * ir);
+    }
+#pragma unroll
+    for (int mu = 0; mu < NA; ++mu) {
+        T v = B[mu];
+#pragma unroll
+        for (int o = 1; o < FIVE_SPLIT; o <<= 1) v += __shfl_xor(v, o);
+        B[mu] = v;
+    }
+    T acc[Tab::ND];
+#pragma unroll
+    for (int d = 0; d < Tab::ND; ++d) acc[d] = T(0);
+#pragma unroll
+    for (int t = 0; t < Tab::NT; ++t)
+        acc[Tab::build.td[t]] += T(Tab::build.tc[t]) * B[Tab::build.tx[t]] * B[Tab::build.ty[t]] *
+                                 B[Tab::build.tz[t]] * B[Tab::build.tw[t]];
+    if (sub == 0) {
+        T* out = g.D5 + static_cast<size_t>(i) * g.K5 * g.nd + static_cast<size_t>(m) * g.nd;
+#pragma unroll
+        for (int d = 0; d < Tab::ND; ++d)
+            if (d < g.nd) out[d] = acc[d];
+    }
+}
+
+int n_orbits(int P5) {
+    constexpr FiveBuild<4> b{};
+    int n = 0;
+    for (int d = 0; d < b.nd; ++d) {
+        int s = 0;
+        for (int t = 0; t < 6; ++t) s += b.ex[d][t];
+        if (s <= P5) ++n;
+    }
+    return n;
+}
+
+template <typename T>
+int five_impl(pod_handle* h, const ParamsT<T>& prm, int N, int P, const void* pos, const double* cell,
+              const int* offsets, const int* nbr_j, const int* shift, int K5, int P5, void* D5) {
+    FArgs<T> g;
+    g.prm = prm;
+    g.cell.periodic = cell != nullptr;
+    for (int k = 0; k < 9; ++k) {
+        const double v = cell ? cell[k] : 0.0;
+        if (!std::isfinite(v)) return POD_EINVAL;
+        g.cell.a[k] = static_cast<T>(v);
+    }
+    g.N = N;
+    g.P = P;
+    g.K5 = K5;
+    g.nd = n_orbits(P5);
+    g.pos = static_cast<const T*>(pos);
+    g.offsets = offsets;
+    g.nbr_j = nbr_j;
+    g.shift = shift;
+    g.D5 = static_cast<T*>(D5);
+    g.err = h->d_err;
+    const dim3 grid((N + FIVE_APB - 1) / FIVE_APB, K5);
+    timing_begin(h, 1);
+    if (P5 <= 2)
+        hipLaunchKernelGGL((five_kernel<T, 2>), grid, dim3(FIVE_THREADS), 0, h->stream, g);
+    else
+        hipLaunchKernelGGL((five_kernel<T, 4>), grid, dim3(FIVE_THREADS), 0, h->stream, g);
+    timing_end(h, 1);
+    return hipGetLastError() == hipSuccess ? POD_OK : POD_EHIP;
+}
+
+static_assert(FiveTable<4>::ND == FIVE_MAX_ORBITS, "orbit count for |e| <= 4");
+static_assert(FiveTable<4>::NT <= FIVE_CAP, "merged five-body terms");
+
+}  // namespace
+}  // namespace pod
+
+extern "C" {
+
+int pod_five_body_count(int P5, int* n) {
+    if (!n || P5 < 0) return POD_EINVAL;
+    if (P5 > POD_FIVE_MAX_P) return POD_ENOTSUP;
+    *n = pod::n_orbits(P5);
+    return POD_OK;
+}
+
+int pod_five_body_descriptors(pod_handle* h, int N, int P, const void* pos, const double* cell, const int* offsets,
+                              const int* nbr_j, const int* shift, int K5, int P5, void* D5) {
+    using namespace pod;
+    if (!h || N < 0 || P < 0 || K5 < 1 || K5 > h->K || P5 < 0) return POD_EINVAL;
+    if (P5 > POD_FIVE_MAX_P) return POD_ENOTSUP;
+    if (N > 0 && (!pos || !offsets || !D5 || (P > 0 && (!nbr_j || !shift)))) return POD_EINVAL;
+    if (N == 0) return POD_OK;
+    if (h->dtype == POD_F64)
+        return five_impl<double>(h, h->hp_d, N, P, pos, cell, offsets, nbr_j, shift, K5, P5, D5);
+    return five_impl<float>(h, h->hp_f, N, P, pos, cell, offsets, nbr_j, shift, K5, P5, D5);
+}
+
+}  // extern "C"

@@ -91,6 +91,8 @@ def lib():
     L.pod_mlp_train_step.argtypes = [_vp, i, i, _vp, lg, _vp, _vp, _vp, _vp, _vp, _vp, i, f, f, f, f, _vp]
     L.pod_energy_forces_surrogate.argtypes = [_vp, i, i, _vp, _dp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                               _vp, _vp, _vp]
+    L.pod_five_body_count.argtypes = [i, P(i)]
+    L.pod_five_body_descriptors.argtypes = [_vp, i, i, _vp, _dp, _vp, _vp, _vp, i, i, _vp]
     L.pod_acsf_create.argtypes = [_vp, i, _dp, i, _dp, i, _dp, P(_vp)]
     L.pod_acsf_num_functions.argtypes = [_vp, P(i), P(i)]
     L.pod_acsf_descriptors.argtypes = [_vp, _vp, i, i, _vp, _dp, _vp, _vp, _vp, _vp]
@@ -110,7 +112,7 @@ def lib():
                  "pod_mlp_train_step", "pod_energy_forces_surrogate", "pod_build_neighbors", "pod_fit_gram",
                  "pod_fit_solve", "pod_opod_descriptors", "pod_opod_energy_forces", "pod_md_verlet",
                  "pod_md_max_displacement", "pod_acsf_create", "pod_acsf_num_functions", "pod_acsf_descriptors",
-                 "pod_acsf_forces"):
+                 "pod_acsf_forces", "pod_five_body_count", "pod_five_body_descriptors"):
         getattr(L, name).restype = i
     _lib = L
     return L
@@ -359,6 +361,18 @@ def pod_free(h: Handle):
         h.ptr = None
 
 
+def pod_five_body_count(P5: int) -> int:
+    n = ctypes.c_int()
+    _ok(lib().pod_five_body_count(int(P5), ctypes.byref(n)), "pod_five_body_count")
+    return n.value
+
+
+def pod_five_body_descriptors(h: Handle, N, P, pos, cell, offsets, nbr_j, shift, K5, P5, D5):
+    arr, cp = _cell_ptr(cell)
+    _ok(lib().pod_five_body_descriptors(h.ptr, int(N), int(P), _ptr(pos), cp, _ptr(offsets), _ptr(nbr_j),
+                                        _ptr(shift), int(K5), int(P5), _ptr(D5)), "pod_five_body_descriptors")
+
+
 class AcsfSet:
     """A set of symmetry functions created on the device for one handle."""
 
@@ -538,6 +552,18 @@ class PodModel:
         if check:
             pod_check(self.h)
         return o
+
+    def five_body_descriptors(self, pos, cell, nbrs: DeviceNeighbors, K5: int, P5: int, check=True):
+        """[N, K5 * pod_five_body_count(P5)] five-body descriptors (m-major)."""
+        import torch
+        pos = self._pos(pos)
+        n = pod_five_body_count(P5)
+        D5 = torch.empty((nbrs.N, K5 * n), dtype=self.torch_dtype, device=self.device)
+        pod_five_body_descriptors(self.h, nbrs.N, nbrs.P, pos, cell, nbrs.offsets, nbrs.nbr_j, nbrs.shift, K5, P5,
+                                  D5)
+        if check:
+            pod_check(self.h)
+        return D5
 
     def acsf(self, spec) -> AcsfSet:
         """A symmetry-function set (workloads.AcsfSpec or anything with g2,
