@@ -438,6 +438,43 @@ def run_acsf(steps, warmup=3):
 
 
 @on_stream
+def run_five(steps, warmup=3):
+    """Five-body descriptors (the extension of Sec. II.F to body order five)
+    on the 15,840-atom box with the box's radial basis (K = 6): P5 = 2 (5
+    orbits) and P5 = 4 (22 orbits) per radial function, FP64 and FP32; kernel
+    times (pair records + five-body kernel) from HIP events on the leg's
+    stream."""
+    import torch
+
+    from paper_2212_14446_amd import pod, workloads as wl
+    w = wl.config2(5.0)
+    out = {"workload": f"{w.name}: {w.N} atoms, {w.nl.n_pairs} pairs, K5 = 6"}
+    for dt in ("f64", "f32"):
+        m = pod.PodModel(pod.setup_from_workload(w.setup), dt)
+        nb = pod.DeviceNeighbors.from_list(w.nl)
+        x = m._pos(w.pos)
+        for P5 in (2, 4):
+            n = pod.pod_five_body_count(P5)
+            D5 = torch.empty((w.N, 6 * n), dtype=m.torch_dtype, device="cuda")
+            call = lambda: pod.pod_five_body_descriptors(m.h, w.N, nb.P, x, w.cell, nb.offsets, nb.nbr_j, nb.shift,
+                                                         6, P5, D5)
+            for _ in range(warmup):
+                call()
+            pod.pod_set_kernel_timing(m.h, steps)
+            for _ in range(steps):
+                call()
+            kms, kn = pod.pod_get_kernel_time(m.h, 1)
+            pms, pn = pod.pod_get_kernel_time(m.h, 0)
+            pod.pod_set_kernel_timing(m.h, 0)
+            m.check()
+            t = kms / max(kn, 1) + pms / max(pn, 1)
+            out[f"{dt}_P5_{P5}"] = {"descriptors": 6 * n, "kernel_ms": t, "pair_record_ms": pms / max(pn, 1),
+                                    "five_body_ms": kms / max(kn, 1), "atoms_per_s": w.N / (t * 1e-3)}
+            print(f"[bench] five-body {dt} P5={P5} {out[f'{dt}_P5_{P5}']}", file=sys.stderr, flush=True)
+    return out
+
+
+@on_stream
 def run_md(steps, dtype="f64", T=300.0, dt=1.0):
     """NVE molecular dynamics on the 15,840-atom box (the use by which the
     paper prices its potentials, Fig. 4): velocity Verlet with the 2/3/4-body
@@ -585,6 +622,7 @@ def main():
     ap.add_argument("--no-opod", action="store_true")
     ap.add_argument("--no-md", action="store_true")
     ap.add_argument("--no-acsf", action="store_true")
+    ap.add_argument("--no-five", action="store_true")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (a known-size "
                          "kernel for scaling hardware traffic counters)")
@@ -656,6 +694,8 @@ def main():
         rec["opod_vs_fast"] = run_opod(20)
     if not args.no_acsf:
         rec["acsf"] = run_acsf(20)
+    if not args.no_five:
+        rec["five_body"] = run_five(20)
     if not args.no_batch:
         rec["batch"] = run_batch(10, 2)
         print(f"[bench] batch {rec['batch']}", file=sys.stderr, flush=True)

@@ -29,8 +29,9 @@ namespace {
 constexpr int FIVE_MAX_ORBITS = 22;   // orbits with |e| <= 4
 constexpr int FIVE_CAP = 700;         // merged terms (at most the 680 raw products for |e| <= 4)
 constexpr int FIVE_THREADS = 256;
-constexpr int FIVE_SPLIT = 4;         // lanes per atom, sharing its neighbours
+constexpr int FIVE_SPLIT = 2;         // lanes per atom, sharing its neighbours
 constexpr int FIVE_APB = FIVE_THREADS / FIVE_SPLIT;
+constexpr int FIVE_PAIR_LANES = 16;   // lanes per atom in the pair-record kernel
 
 // angle positions (j,k), (j,l), (j,n), (k,l), (k,n), (l,n) with j,k,l,n = 0..3
 constexpr int FIVE_EDGE[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
@@ -174,9 +175,74 @@ struct FArgs {
     const int* offsets;
     const int* nbr_j;
     const int* shift;
+    T* rec;           // per pair: rhat (3), R_m (K5); zeros for a pair that is not a neighbour
     T* D5;
     int* err;
 };
+
+// FIVE_PAIR_LANES lanes per atom walk its pairs: geometry, validation and
+// the radial basis once per pair for all K5 radial functions.
+template <typename T, bool FAST>
+__global__ __launch_bounds__(FIVE_THREADS) void five_pair_kernel(FArgs<T> g) {
+    __shared__ T sQ[POD_MAX_L * POD_MAX_K];
+    if (FAST) {
+        for (int k = threadIdx.x; k < POD_MAX_L * POD_MAX_K; k += FIVE_THREADS) sQ[k] = (&g.prm.Q[0][0])[k];
+        __syncthreads();
+    }
+    const int i = blockIdx.x * (FIVE_THREADS / FIVE_PAIR_LANES) + static_cast<int>(threadIdx.x) / FIVE_PAIR_LANES;
+    const int l = static_cast<int>(threadIdx.x) % FIVE_PAIR_LANES;
+    if (i >= g.N) return;
+    const int p0 = max(g.offsets[i], 0);
+    int p1 = g.offsets[i + 1];
+    if (p1 > g.P) {
+        if (l == 0) atomicOr(g.err, ERR_NEIGH);
+        p1 = g.P;
+    }
+    const int S = 3 + g.K5;
+    for (int p = p0 + l; p < p1; p += FIVE_PAIR_LANES) {
+        T* row = g.rec + static_cast<size_t>(p) * S;
+        T u[3] = {T(0), T(0), T(0)};
+        T r = T(0.5) * (g.prm.rin + g.prm.rcut);
+        bool ok = false;
+        const int j = g.nbr_j[p];
+        const int sh = g.shift[p];
+        if (j < 0 || j >= g.N || (!g.cell.periodic && (sh & 0xFFFFFF) != 0)) {
+            atomicOr(g.err, ERR_NEIGH);
+        } else {
+            const T sx = static_cast<T>(dev::unpack_shift(sh, 0));
+            const T sy = static_cast<T>(dev::unpack_shift(sh, 1));
+            const T sz = static_cast<T>(dev::unpack_shift(sh, 2));
+            const T* c = g.cell.a;
+            const T d0 = g.pos[3 * j] - g.pos[3 * i] + sx * c[0] + sy * c[3] + sz * c[6];
+            const T d1 = g.pos[3 * j + 1] - g.pos[3 * i + 1] + sx * c[1] + sy * c[4] + sz * c[7];
+            const T d2 = g.pos[3 * j + 2] - g.pos[3 * i + 2] + sx * c[2] + sy * c[5] + sz * c[8];
+            const T r2 = d0 * d0 + d1 * d1 + d2 * d2;
+            if (!dev::d_finite(r2)) {
+                atomicOr(g.err, ERR_NONFINITE);
+            } else {
+                const T rr = dev::d_sqrt(r2);
+                if (rr <= g.prm.rin) {
+                    atomicOr(g.err, ERR_RANGE);
+                } else if (rr < g.prm.rcut) {   // beyond rcut: a skin-list entry, not a neighbour
+                    ok = true;
+                    r = rr;
+                    u[0] = d0 / rr;
+                    u[1] = d1 / rr;
+                    u[2] = d2 / rr;
+                }
+            }
+        }
+        T R[POD_MAX_K], dR[POD_MAX_K];
+        if constexpr (FAST) dev::radial_std<T, false>(&g.prm, sQ, r, T(1) / r, R, dR);
+        else dev::radial<T, false>(&g.prm, r, T(1) / r, R, dR);
+        row[0] = u[0];
+        row[1] = u[1];
+        row[2] = u[2];
+#pragma unroll
+        for (int k = 0; k < POD_MAX_K; ++k)
+            if (k < g.K5) row[3 + k] = ok ? R[k] : T(0);
+    }
+}
 
 template <typename T, int PD>
 __global__ __launch_bounds__(FIVE_THREADS) void five_kernel(FArgs<T> g) {
@@ -189,44 +255,16 @@ __global__ __launch_bounds__(FIVE_THREADS) void five_kernel(FArgs<T> g) {
     T B[NA];
 #pragma unroll
     for (int mu = 0; mu < NA; ++mu) B[mu] = T(0);
-    int p0 = max(g.offsets[i], 0), p1 = g.offsets[i + 1];
+    const int p0 = max(g.offsets[i], 0);
+    int p1 = g.offsets[i + 1];
     if (p1 > g.P) {
-        atomicOr(g.err, ERR_NEIGH);
+        if (sub == 0) atomicOr(g.err, ERR_NEIGH);
         p1 = g.P;
     }
+    const int S = 3 + g.K5;
     for (int p = p0 + sub; p < p1; p += FIVE_SPLIT) {
-        const int j = g.nbr_j[p];
-        const int sh = g.shift[p];
-        if (j < 0 || j >= g.N || (!g.cell.periodic && (sh & 0xFFFFFF) != 0)) {
-            atomicOr(g.err, ERR_NEIGH);
-            continue;
-        }
-        const T sx = static_cast<T>(dev::unpack_shift(sh, 0));
-        const T sy = static_cast<T>(dev::unpack_shift(sh, 1));
-        const T sz = static_cast<T>(dev::unpack_shift(sh, 2));
-        const T* c = g.cell.a;
-        const T d0 = g.pos[3 * j] - g.pos[3 * i] + sx * c[0] + sy * c[3] + sz * c[6];
-        const T d1 = g.pos[3 * j + 1] - g.pos[3 * i + 1] + sx * c[1] + sy * c[4] + sz * c[7];
-        const T d2 = g.pos[3 * j + 2] - g.pos[3 * i + 2] + sx * c[2] + sy * c[5] + sz * c[8];
-        const T r2 = d0 * d0 + d1 * d1 + d2 * d2;
-        if (!dev::d_finite(r2)) {
-            atomicOr(g.err, ERR_NONFINITE);
-            continue;
-        }
-        const T r = dev::d_sqrt(r2);
-        if (r <= g.prm.rin) {
-            atomicOr(g.err, ERR_RANGE);
-            continue;
-        }
-        if (r >= g.prm.rcut) continue;   // a skin-list entry: not a neighbour
-        const T ir = T(1) / r;
-        T R[POD_MAX_K], dR[POD_MAX_K];
-        dev::radial<T, false>(&g.prm, r, ir, R, dR);
-        T Rm = R[0];
-#pragma unroll
-        for (int k = 1; k < POD_MAX_K; ++k)
-            if (k == m) Rm = R[k];
-        dev::accumulate_basis<T, PD>(B, Rm, d0 * ir, d1 * ir, d2 * ir);
+        const T* row = g.rec + static_cast<size_t>(p) * S;
+        dev::accumulate_basis<T, PD>(B, row[3 + m], row[0], row[1], row[2]);
     }
 #pragma unroll
     for (int mu = 0; mu < NA; ++mu) {
@@ -282,6 +320,19 @@ int five_impl(pod_handle* h, const ParamsT<T>& prm, int N, int P, const void* po
     g.shift = shift;
     g.D5 = static_cast<T*>(D5);
     g.err = h->d_err;
+    const int rc = ensure_scratch(h, sizeof(T) * static_cast<size_t>(P) * (3 + K5) + 256);
+    if (rc != POD_OK) return rc;
+    g.rec = static_cast<T*>(h->d_scratch);
+    if (P > 0) {
+        const int apb = FIVE_THREADS / FIVE_PAIR_LANES;
+        const dim3 pgrid((N + apb - 1) / apb);
+        timing_begin(h, 0);
+        if (prm.std_ok)
+            hipLaunchKernelGGL((five_pair_kernel<T, true>), pgrid, dim3(FIVE_THREADS), 0, h->stream, g);
+        else
+            hipLaunchKernelGGL((five_pair_kernel<T, false>), pgrid, dim3(FIVE_THREADS), 0, h->stream, g);
+        timing_end(h, 0);
+    }
     const dim3 grid((N + FIVE_APB - 1) / FIVE_APB, K5);
     timing_begin(h, 1);
     if (P5 <= 2)
