@@ -1,25 +1,27 @@
 // Kernels of the fast POD path for gfx950 (CDNA4).
 //
-// Two launches per call.
-//
-// pair_kernel  (pair-parallel, 8 atoms x 32 lanes per 256-thread block):
-//   every directed pair r_ij -> one record {rhat (3), 1/r, R_k(r) (K),
-//   R'_k(r) (K)} of the radial basis (Sec. II.B, eqs. (3)-(8), (11), (12)),
-//   plus validation of the pair and zeroing of the accumulated outputs.
-//   The transcendental work sits here, at high occupancy.
-//
 // atom_kernel  (one 64-lane wavefront per workgroup, APW = 64 / K atoms):
 //   lane l serves atom a = l / K and radial index m = l % K and keeps the row
 //   B_{i m .} = sum_j R_m(r_ij) A_.(rhat_ij) of the atomic basis (Sec. II.E,
-//   eq. (24b)) in registers.  Every contraction of Sec. II.E is diagonal in m
-//   (the same radial function in all factors, eqs. (14), (17a)), so D3, D4,
-//   the energy and the adjoint dE_i/dB_{i m .} come from the lane's own row
-//   with compile-time tables.  The backward sweep reads the pair records
-//   again, forms each lane's share of dE_i/dr_ij (eq. (24c)), sums the K
-//   shares of a pair through LDS and scatters forces with device atomics;
-//   E, W and G are accumulated with device atomics as well.
-// The per-atom basis B and its adjoint never leave registers; only the
-// per-pair radial record (4 + 2K values) goes through memory.
+//   eq. (24b)) in registers.  Neighbours are taken K at a time per atom
+//   ("rounds"): in a round, lane (a, s) evaluates slot s of atom a -- pair
+//   geometry and the radial basis (Sec. II.B, eqs. (3)-(8), (11), (12)) --
+//   and stages {rhat, R_k} in LDS for the atom's K lanes, with the next
+//   slot's indices and positions prefetched.  Every contraction of Sec. II.E
+//   is diagonal in m (the same radial function in all factors, eqs. (14),
+//   (17a)), so D3, D4, the energy and the adjoint dE_i/dB_{i m .} come from
+//   the lane's own row with compile-time tables.  The backward sweep walks
+//   the slots again, forms dE_i/dr_ij (eq. (24c)) from the K adjoint rows of
+//   the atom, and either stores it at the reverse slot of the pair (gather
+//   path, with a reverse-pair index) or adds it to an FP64 accumulator with
+//   device atomics.  E, the virial and G leave as per-workgroup partials.
+// finalize_kernel  sums the partials in a fixed order (E, W, G) and forms the
+//   forces: on the gather path each atom adds its own sum_j g_ij to the
+//   values stored in its list range (32 lanes per atom); otherwise it copies
+//   and clears the accumulator.
+// reverse_kernel  builds the reverse-pair index of a list once.
+// The per-atom basis B and its adjoint never leave the chip; only the
+// pair gradients of the gather path go through memory.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
