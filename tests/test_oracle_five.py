@@ -4,7 +4,8 @@ The orbit count against Burnside's lemma; the invariance that defines the
 orbits; the exponent tuples whose angle graph splits or leaves a neighbour
 free, which reduce the quadruple sum to products of the POD oracle's own two-,
 three- and four-body descriptors (eqs. (12b), (15), (18a)); and geometric
-closed forms for environments with cosines 0 and -1."""
+closed forms for environments with cosines 0 and -1; the energy c5 . D5 and
+its forces against central finite differences."""
 import itertools
 import math
 
@@ -158,3 +159,27 @@ def test_list_entries_beyond_rcut_are_ignored():
     ref = fo.descriptors5_env(Rn, d / r[:, None], 2, 2)
     assert np.abs(got[0] - ref).max() <= 1e-12 * np.abs(ref).max()
     assert math.isclose(got.shape[1], 2 * 5)
+
+
+def test_energy_and_forces_of_the_oracle():
+    """E_i = c5 . D5_i with D5 from the quadruple sums; forces against
+    central finite differences of that energy; sum F = 0."""
+    p, Q = _pod_params(K=2, P=2)
+    pos, cell = wl.bcc(1)
+    pos = wl.displace(pos, 0.15, 3)
+    nl = wl.neighbor_list(pos, cell, p.rcut)
+    K5, P5 = 2, 3
+    n5 = len(fo.orbits(P5))
+    c5 = np.random.default_rng(6).normal(size=(K5, n5)) * 1e-3
+    E_atom, F = fo.energy_forces5(pos, cell, nl.offsets, nl.nbr_j, nl.shift3, p, Q, K5, P5, c5)
+    D = fo.descriptors5(pos, cell, nl.offsets, nl.nbr_j, nl.shift3, p, Q, K5, P5)
+    assert np.allclose(E_atom, D @ c5.reshape(-1), rtol=1e-12)
+    assert np.abs(F.sum(0)).max() <= 1e-10 * np.abs(F).max()
+    h = 1e-5
+    for a, e in ((0, 0), (1, 2)):
+        xp, xm = pos.copy(), pos.copy()
+        xp[a, e] += h
+        xm[a, e] -= h
+        Ep = (fo.descriptors5(xp, cell, nl.offsets, nl.nbr_j, nl.shift3, p, Q, K5, P5) @ c5.reshape(-1)).sum()
+        Em = (fo.descriptors5(xm, cell, nl.offsets, nl.nbr_j, nl.shift3, p, Q, K5, P5) @ c5.reshape(-1)).sum()
+        assert abs(F[a, e] + (Ep - Em) / (2 * h)) <= 1e-6 * np.abs(F).max()
