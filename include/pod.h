@@ -369,6 +369,22 @@ int pod_five_body_descriptors(pod_handle* h, int N, int P, const void* pos, cons
                               const int* offsets, const int* nbr_j, const int* shift, int K5,
                               int P5, void* D5);
 
+/* Energy E_i = sum_{m, e} c5[m count + e] D5_{i m e} of a linear five-body
+ * term and its forces F = -dE/dx (E = sum_i E_i), for the descriptors above.
+ * The adjoint dE_i/dB of each atom and radial function comes from the
+ * merged products, then the pair derivative of eq. (24c) with R_m, R'_m.
+ *   c5     : K5 x count coefficients (device, handle dtype), m-major
+ *   rev    : reverse-pair index (pod_neighbor_reverse), required with F
+ *   E_atom : N (device, handle dtype) or NULL; F : N x 3 or NULL (not both)
+ * Four kernels on the handle's stream (pair records with R', basis and
+ * adjoint, per-pair gradients, per-atom gather; no atomics, reproducible);
+ * the handle's scratch holds the records, the adjoint rows and the pair
+ * gradients.  Limits and data errors as for pod_five_body_descriptors. */
+int pod_five_body_energy_forces(pod_handle* h, int N, int P, const void* pos, const double* cell,
+                                const int* offsets, const int* nbr_j, const int* shift,
+                                const int* rev, int K5, int P5, const void* c5, void* E_atom,
+                                void* F);
+
 /* Atom-centred symmetry functions (Sec. III.B) through the atomic basis of
  * Sec. II.E, in work linear in the number of neighbours:
  *   G2_i = sum_j exp(-eta (r_ij - r_s)^2) f_c(r_ij)                eq. (21c)

@@ -17,6 +17,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <utility>
 
 #include "pod.h"
 #include "pod_device.h"
@@ -175,14 +176,22 @@ struct FArgs {
     const int* offsets;
     const int* nbr_j;
     const int* shift;
-    T* rec;           // per pair: rhat (3), R_m (K5); zeros for a pair that is not a neighbour
-    T* D5;
+    T* rec;           // per pair: rhat (3), r, R_m (K5) [, R'_m (K5)]; R = R' = 0 for a pair that is not a neighbour
+    int rs;           // record stride: 4 + K5, or 4 + 2 K5 with derivatives
+    T* D5;            // N x K5 nd, or null
+    const T* c5;      // energy: K5 x nd coefficients (m-major), or null
+    T* bbar;          // energy: dE_i/dB_{i m .}, [m][i][n_mono] (scratch)
+    T* Em;            // energy: per (atom, m) energies, [i][m] (scratch)
+    T* V;             // forces: dE_i/dr_ij per pair (3P, scratch)
+    const int* rev;
+    T* E_atom;
+    T* F;
     int* err;
 };
 
 // FIVE_PAIR_LANES lanes per atom walk its pairs: geometry, validation and
 // the radial basis once per pair for all K5 radial functions.
-template <typename T, bool FAST>
+template <typename T, bool FAST, bool DERIV>
 __global__ __launch_bounds__(FIVE_THREADS) void five_pair_kernel(FArgs<T> g) {
     __shared__ T sQ[POD_MAX_L * POD_MAX_K];
     if (FAST) {
@@ -198,9 +207,8 @@ __global__ __launch_bounds__(FIVE_THREADS) void five_pair_kernel(FArgs<T> g) {
         if (l == 0) atomicOr(g.err, ERR_NEIGH);
         p1 = g.P;
     }
-    const int S = 3 + g.K5;
     for (int p = p0 + l; p < p1; p += FIVE_PAIR_LANES) {
-        T* row = g.rec + static_cast<size_t>(p) * S;
+        T* row = g.rec + static_cast<size_t>(p) * g.rs;
         T u[3] = {T(0), T(0), T(0)};
         T r = T(0.5) * (g.prm.rin + g.prm.rcut);
         bool ok = false;
@@ -233,18 +241,22 @@ __global__ __launch_bounds__(FIVE_THREADS) void five_pair_kernel(FArgs<T> g) {
             }
         }
         T R[POD_MAX_K], dR[POD_MAX_K];
-        if constexpr (FAST) dev::radial_std<T, false>(&g.prm, sQ, r, T(1) / r, R, dR);
-        else dev::radial<T, false>(&g.prm, r, T(1) / r, R, dR);
+        if constexpr (FAST) dev::radial_std<T, DERIV>(&g.prm, sQ, r, T(1) / r, R, dR);
+        else dev::radial<T, DERIV>(&g.prm, r, T(1) / r, R, dR);
         row[0] = u[0];
         row[1] = u[1];
         row[2] = u[2];
+        row[3] = r;
 #pragma unroll
         for (int k = 0; k < POD_MAX_K; ++k)
-            if (k < g.K5) row[3 + k] = ok ? R[k] : T(0);
+            if (k < g.K5) {
+                row[4 + k] = ok ? R[k] : T(0);
+                if (DERIV) row[4 + g.K5 + k] = ok ? dR[k] : T(0);
+            }
     }
 }
 
-template <typename T, int PD>
+template <typename T, int PD, bool ADJ>
 __global__ __launch_bounds__(FIVE_THREADS) void five_kernel(FArgs<T> g) {
     constexpr int NA = n_mono(PD);
     using Tab = FiveTable<PD>;
@@ -261,10 +273,9 @@ __global__ __launch_bounds__(FIVE_THREADS) void five_kernel(FArgs<T> g) {
         if (sub == 0) atomicOr(g.err, ERR_NEIGH);
         p1 = g.P;
     }
-    const int S = 3 + g.K5;
     for (int p = p0 + sub; p < p1; p += FIVE_SPLIT) {
-        const T* row = g.rec + static_cast<size_t>(p) * S;
-        dev::accumulate_basis<T, PD>(B, row[3 + m], row[0], row[1], row[2]);
+        const T* row = g.rec + static_cast<size_t>(p) * g.rs;
+        dev::accumulate_basis<T, PD>(B, row[4 + m], row[0], row[1], row[2]);
     }
 #pragma unroll
     for (int mu = 0; mu < NA; ++mu) {
@@ -280,11 +291,136 @@ __global__ __launch_bounds__(FIVE_THREADS) void five_kernel(FArgs<T> g) {
     for (int t = 0; t < Tab::NT; ++t)
         acc[Tab::build.td[t]] += T(Tab::build.tc[t]) * B[Tab::build.tx[t]] * B[Tab::build.ty[t]] *
                                  B[Tab::build.tz[t]] * B[Tab::build.tw[t]];
-    if (sub == 0) {
-        T* out = g.D5 + static_cast<size_t>(i) * g.K5 * g.nd + static_cast<size_t>(m) * g.nd;
+    if constexpr (!ADJ) {
+        if (sub == 0) {
+            T* out = g.D5 + static_cast<size_t>(i) * g.K5 * g.nd + static_cast<size_t>(m) * g.nd;
 #pragma unroll
-        for (int d = 0; d < Tab::ND; ++d)
-            if (d < g.nd) out[d] = acc[d];
+            for (int d = 0; d < Tab::ND; ++d)
+                if (d < g.nd) out[d] = acc[d];
+        }
+    } else {
+        // E_im = sum_d c5_{m d} D5_{i m d} and dE_im/dB by the product rule on
+        // every merged product (orbits beyond P5 weigh 0)
+        const T* cm = g.c5 + static_cast<size_t>(m) * g.nd;
+        T cw[Tab::ND];
+        T e = T(0);
+#pragma unroll
+        for (int d = 0; d < Tab::ND; ++d) {
+            cw[d] = d < g.nd ? cm[d] : T(0);
+            e += cw[d] * acc[d];
+        }
+        T bb[NA];
+#pragma unroll
+        for (int mu = 0; mu < NA; ++mu) bb[mu] = T(0);
+        // one instance per merged product, so every index is a constant
+        auto term = [&]<int t>() {
+            constexpr int x = Tab::build.tx[t], y = Tab::build.ty[t], z = Tab::build.tz[t], w = Tab::build.tw[t];
+            const T c = cw[Tab::build.td[t]] * T(Tab::build.tc[t]);
+            const T pxy = B[x] * B[y], pzw = B[z] * B[w];
+            bb[x] += c * B[y] * pzw;
+            bb[y] += c * B[x] * pzw;
+            bb[z] += c * pxy * B[w];
+            bb[w] += c * pxy * B[z];
+        };
+        [&]<int... ts>(std::integer_sequence<int, ts...>) {
+            (term.template operator()<ts>(), ...);
+        }(std::make_integer_sequence<int, Tab::NT>{});
+        if (sub == 0) {
+            g.Em[static_cast<size_t>(i) * g.K5 + m] = e;
+            T* out = g.bbar + (static_cast<size_t>(m) * g.N + i) * NA;
+#pragma unroll
+            for (int mu = 0; mu < NA; ++mu) out[mu] = bb[mu];
+        }
+    }
+}
+
+// FIVE_PAIR_LANES lanes per atom: for each pair, d E_i / d r_ij =
+// sum_m [R'_m h_m rhat + R_m (grad_u h_m - (u . grad_u h_m) u) / r] with
+// h_m(u) = sum_mu dE_i/dB_{i m mu} u^mu (eq. (24c) with the five-body adjoint).
+template <typename T, int PD>
+__global__ __launch_bounds__(FIVE_THREADS) void five_grad_kernel(FArgs<T> g) {
+    constexpr MonoTable<PD> mt{};
+    constexpr int NA = n_mono(PD);
+    const int i = blockIdx.x * (FIVE_THREADS / FIVE_PAIR_LANES) + static_cast<int>(threadIdx.x) / FIVE_PAIR_LANES;
+    const int l = static_cast<int>(threadIdx.x) % FIVE_PAIR_LANES;
+    if (i >= g.N) return;
+    const int p0 = max(g.offsets[i], 0);
+    const int p1 = min(g.offsets[i + 1], g.P);
+    for (int p = p0 + l; p < p1; p += FIVE_PAIR_LANES) {
+        const T* row = g.rec + static_cast<size_t>(p) * g.rs;
+        const T ux = row[0], uy = row[1], uz = row[2], ir = T(1) / row[3];
+        T A[NA];
+        A[0] = T(1);
+#pragma unroll
+        for (int mu = 1; mu < NA; ++mu) {
+            const T u = mt.axis[mu] == 0 ? ux : (mt.axis[mu] == 1 ? uy : uz);
+            A[mu] = A[mt.par[mu]] * u;
+        }
+        T v0 = T(0), v1 = T(0), v2 = T(0);
+        for (int m = 0; m < g.K5; ++m) {
+            const T Rm = row[4 + m], dRm = row[4 + g.K5 + m];
+            const T* bb = g.bbar + (static_cast<size_t>(m) * g.N + i) * NA;
+            T h = T(0), eul = T(0), q0 = T(0), q1 = T(0), q2 = T(0);
+#pragma unroll
+            for (int mu = 0; mu < NA; ++mu) {
+                const T b = bb[mu];
+                const T ba = b * A[mu];
+                h += ba;
+                if (mt.deg[mu] > 0) eul += T(mt.deg[mu]) * ba;
+                if (mt.down[mu][0] >= 0) q0 += T(mt.ex[mu][0]) * b * A[mt.down[mu][0]];
+                if (mt.down[mu][1] >= 0) q1 += T(mt.ex[mu][1]) * b * A[mt.down[mu][1]];
+                if (mt.down[mu][2] >= 0) q2 += T(mt.ex[mu][2]) * b * A[mt.down[mu][2]];
+            }
+            const T c1 = dRm * h - Rm * eul * ir;
+            const T c2 = Rm * ir;
+            v0 += c1 * ux + c2 * q0;
+            v1 += c1 * uy + c2 * q1;
+            v2 += c1 * uz + c2 * q2;
+        }
+        g.V[3 * static_cast<size_t>(p)] = v0;
+        g.V[3 * static_cast<size_t>(p) + 1] = v1;
+        g.V[3 * static_cast<size_t>(p) + 2] = v2;
+    }
+}
+
+// F_i = sum over the pairs p of i of (V_p - V_rev(p)); E_i = sum_m E_im.
+template <typename T>
+__global__ __launch_bounds__(FIVE_THREADS) void five_gather_kernel(FArgs<T> g) {
+    const int i = blockIdx.x * (FIVE_THREADS / FIVE_PAIR_LANES) + static_cast<int>(threadIdx.x) / FIVE_PAIR_LANES;
+    const int l = static_cast<int>(threadIdx.x) % FIVE_PAIR_LANES;
+    if (i >= g.N) return;
+    if (g.E_atom && l == 0) {
+        T e = T(0);
+        for (int m = 0; m < g.K5; ++m) e += g.Em[static_cast<size_t>(i) * g.K5 + m];
+        g.E_atom[i] = e;
+    }
+    if (!g.F) return;
+    const int p0 = max(g.offsets[i], 0);
+    const int p1 = min(g.offsets[i + 1], g.P);
+    T f0 = T(0), f1 = T(0), f2 = T(0);
+    for (int p = p0 + l; p < p1; p += FIVE_PAIR_LANES) {
+        const int q = g.rev[p];
+        f0 += g.V[3 * static_cast<size_t>(p)];
+        f1 += g.V[3 * static_cast<size_t>(p) + 1];
+        f2 += g.V[3 * static_cast<size_t>(p) + 2];
+        if (q < 0 || q >= g.P) {
+            atomicOr(g.err, ERR_NEIGH);
+            continue;
+        }
+        f0 -= g.V[3 * static_cast<size_t>(q)];
+        f1 -= g.V[3 * static_cast<size_t>(q) + 1];
+        f2 -= g.V[3 * static_cast<size_t>(q) + 2];
+    }
+#pragma unroll
+    for (int o = 1; o < FIVE_PAIR_LANES; o <<= 1) {
+        f0 += __shfl_xor(f0, o);
+        f1 += __shfl_xor(f1, o);
+        f2 += __shfl_xor(f2, o);
+    }
+    if (l == 0) {
+        g.F[3 * static_cast<size_t>(i)] = f0;
+        g.F[3 * static_cast<size_t>(i) + 1] = f1;
+        g.F[3 * static_cast<size_t>(i) + 2] = f2;
     }
 }
 
@@ -299,9 +435,13 @@ int n_orbits(int P5) {
     return n;
 }
 
+size_t align256(size_t b) { return (b + 255) & ~static_cast<size_t>(255); }
+
+// Descriptors (D5), or with coefficients the energy and forces.
 template <typename T>
 int five_impl(pod_handle* h, const ParamsT<T>& prm, int N, int P, const void* pos, const double* cell,
-              const int* offsets, const int* nbr_j, const int* shift, int K5, int P5, void* D5) {
+              const int* offsets, const int* nbr_j, const int* shift, const int* rev, int K5, int P5, void* D5,
+              const void* c5, void* E_atom, void* F) {
     FArgs<T> g;
     g.prm = prm;
     g.cell.periodic = cell != nullptr;
@@ -310,6 +450,8 @@ int five_impl(pod_handle* h, const ParamsT<T>& prm, int N, int P, const void* po
         if (!std::isfinite(v)) return POD_EINVAL;
         g.cell.a[k] = static_cast<T>(v);
     }
+    const bool energy = c5 != nullptr;
+    const bool deriv = energy && F != nullptr;
     g.N = N;
     g.P = P;
     g.K5 = K5;
@@ -318,28 +460,57 @@ int five_impl(pod_handle* h, const ParamsT<T>& prm, int N, int P, const void* po
     g.offsets = offsets;
     g.nbr_j = nbr_j;
     g.shift = shift;
+    g.rs = 4 + (deriv ? 2 : 1) * K5;
     g.D5 = static_cast<T*>(D5);
+    g.c5 = static_cast<const T*>(c5);
+    g.rev = rev;
+    g.E_atom = static_cast<T*>(E_atom);
+    g.F = static_cast<T*>(F);
     g.err = h->d_err;
-    const int rc = ensure_scratch(h, sizeof(T) * static_cast<size_t>(P) * (3 + K5) + 256);
+    const int NA = P5 <= 2 ? n_mono(2) : n_mono(4);
+    const size_t b_rec = align256(sizeof(T) * static_cast<size_t>(P) * g.rs);
+    const size_t b_bar = energy ? align256(sizeof(T) * static_cast<size_t>(N) * K5 * NA) : 0;
+    const size_t b_em = energy ? align256(sizeof(T) * static_cast<size_t>(N) * K5) : 0;
+    const size_t b_v = deriv ? align256(sizeof(T) * 3 * static_cast<size_t>(P)) : 0;
+    const int rc = ensure_scratch(h, b_rec + b_bar + b_em + b_v + 256);
     if (rc != POD_OK) return rc;
-    g.rec = static_cast<T*>(h->d_scratch);
+    char* base = static_cast<char*>(h->d_scratch);
+    g.rec = reinterpret_cast<T*>(base);
+    g.bbar = energy ? reinterpret_cast<T*>(base + b_rec) : nullptr;
+    g.Em = energy ? reinterpret_cast<T*>(base + b_rec + b_bar) : nullptr;
+    g.V = deriv ? reinterpret_cast<T*>(base + b_rec + b_bar + b_em) : nullptr;
+    const int apb = FIVE_THREADS / FIVE_PAIR_LANES;
+    const dim3 agrid((N + apb - 1) / apb);
     if (P > 0) {
-        const int apb = FIVE_THREADS / FIVE_PAIR_LANES;
-        const dim3 pgrid((N + apb - 1) / apb);
         timing_begin(h, 0);
-        if (prm.std_ok)
-            hipLaunchKernelGGL((five_pair_kernel<T, true>), pgrid, dim3(FIVE_THREADS), 0, h->stream, g);
-        else
-            hipLaunchKernelGGL((five_pair_kernel<T, false>), pgrid, dim3(FIVE_THREADS), 0, h->stream, g);
+        if (prm.std_ok) {
+            if (deriv) hipLaunchKernelGGL((five_pair_kernel<T, true, true>), agrid, dim3(FIVE_THREADS), 0, h->stream, g);
+            else hipLaunchKernelGGL((five_pair_kernel<T, true, false>), agrid, dim3(FIVE_THREADS), 0, h->stream, g);
+        } else {
+            if (deriv) hipLaunchKernelGGL((five_pair_kernel<T, false, true>), agrid, dim3(FIVE_THREADS), 0, h->stream, g);
+            else hipLaunchKernelGGL((five_pair_kernel<T, false, false>), agrid, dim3(FIVE_THREADS), 0, h->stream, g);
+        }
         timing_end(h, 0);
     }
     const dim3 grid((N + FIVE_APB - 1) / FIVE_APB, K5);
     timing_begin(h, 1);
-    if (P5 <= 2)
-        hipLaunchKernelGGL((five_kernel<T, 2>), grid, dim3(FIVE_THREADS), 0, h->stream, g);
-    else
-        hipLaunchKernelGGL((five_kernel<T, 4>), grid, dim3(FIVE_THREADS), 0, h->stream, g);
+    if (P5 <= 2) {
+        if (energy) hipLaunchKernelGGL((five_kernel<T, 2, true>), grid, dim3(FIVE_THREADS), 0, h->stream, g);
+        else hipLaunchKernelGGL((five_kernel<T, 2, false>), grid, dim3(FIVE_THREADS), 0, h->stream, g);
+    } else {
+        if (energy) hipLaunchKernelGGL((five_kernel<T, 4, true>), grid, dim3(FIVE_THREADS), 0, h->stream, g);
+        else hipLaunchKernelGGL((five_kernel<T, 4, false>), grid, dim3(FIVE_THREADS), 0, h->stream, g);
+    }
     timing_end(h, 1);
+    if (energy) {
+        timing_begin(h, 0);
+        if (deriv && P > 0) {
+            if (P5 <= 2) hipLaunchKernelGGL((five_grad_kernel<T, 2>), agrid, dim3(FIVE_THREADS), 0, h->stream, g);
+            else hipLaunchKernelGGL((five_grad_kernel<T, 4>), agrid, dim3(FIVE_THREADS), 0, h->stream, g);
+        }
+        hipLaunchKernelGGL((five_gather_kernel<T>), agrid, dim3(FIVE_THREADS), 0, h->stream, g);
+        timing_end(h, 0);
+    }
     return hipGetLastError() == hipSuccess ? POD_OK : POD_EHIP;
 }
 
@@ -366,8 +537,27 @@ int pod_five_body_descriptors(pod_handle* h, int N, int P, const void* pos, cons
     if (N > 0 && (!pos || !offsets || !D5 || (P > 0 && (!nbr_j || !shift)))) return POD_EINVAL;
     if (N == 0) return POD_OK;
     if (h->dtype == POD_F64)
-        return five_impl<double>(h, h->hp_d, N, P, pos, cell, offsets, nbr_j, shift, K5, P5, D5);
-    return five_impl<float>(h, h->hp_f, N, P, pos, cell, offsets, nbr_j, shift, K5, P5, D5);
+        return five_impl<double>(h, h->hp_d, N, P, pos, cell, offsets, nbr_j, shift, nullptr, K5, P5, D5, nullptr,
+                                 nullptr, nullptr);
+    return five_impl<float>(h, h->hp_f, N, P, pos, cell, offsets, nbr_j, shift, nullptr, K5, P5, D5, nullptr,
+                            nullptr, nullptr);
+}
+
+int pod_five_body_energy_forces(pod_handle* h, int N, int P, const void* pos, const double* cell, const int* offsets,
+                                const int* nbr_j, const int* shift, const int* rev, int K5, int P5, const void* c5,
+                                void* E_atom, void* F) {
+    using namespace pod;
+    if (!h || N < 0 || P < 0 || K5 < 1 || K5 > h->K || P5 < 0) return POD_EINVAL;
+    if (P5 > POD_FIVE_MAX_P) return POD_ENOTSUP;
+    if (N > 0 && (!pos || !offsets || !c5 || (!E_atom && !F) || (P > 0 && (!nbr_j || !shift))))
+        return POD_EINVAL;
+    if (N > 0 && F && P > 0 && !rev) return POD_EINVAL;
+    if (N == 0) return POD_OK;
+    if (h->dtype == POD_F64)
+        return five_impl<double>(h, h->hp_d, N, P, pos, cell, offsets, nbr_j, shift, rev, K5, P5, nullptr, c5,
+                                 E_atom, F);
+    return five_impl<float>(h, h->hp_f, N, P, pos, cell, offsets, nbr_j, shift, rev, K5, P5, nullptr, c5, E_atom,
+                            F);
 }
 
 }  // extern "C"

@@ -93,6 +93,7 @@ def lib():
                                               _vp, _vp, _vp]
     L.pod_five_body_count.argtypes = [i, P(i)]
     L.pod_five_body_descriptors.argtypes = [_vp, i, i, _vp, _dp, _vp, _vp, _vp, i, i, _vp]
+    L.pod_five_body_energy_forces.argtypes = [_vp, i, i, _vp, _dp, _vp, _vp, _vp, _vp, i, i, _vp, _vp, _vp]
     L.pod_acsf_create.argtypes = [_vp, i, _dp, i, _dp, i, _dp, P(_vp)]
     L.pod_acsf_num_functions.argtypes = [_vp, P(i), P(i)]
     L.pod_acsf_descriptors.argtypes = [_vp, _vp, i, i, _vp, _dp, _vp, _vp, _vp, _vp]
@@ -112,7 +113,8 @@ def lib():
                  "pod_mlp_train_step", "pod_energy_forces_surrogate", "pod_build_neighbors", "pod_fit_gram",
                  "pod_fit_solve", "pod_opod_descriptors", "pod_opod_energy_forces", "pod_md_verlet",
                  "pod_md_max_displacement", "pod_acsf_create", "pod_acsf_num_functions", "pod_acsf_descriptors",
-                 "pod_acsf_forces", "pod_five_body_count", "pod_five_body_descriptors"):
+                 "pod_acsf_forces", "pod_five_body_count", "pod_five_body_descriptors",
+                 "pod_five_body_energy_forces"):
         getattr(L, name).restype = i
     _lib = L
     return L
@@ -373,6 +375,14 @@ def pod_five_body_descriptors(h: Handle, N, P, pos, cell, offsets, nbr_j, shift,
                                         _ptr(shift), int(K5), int(P5), _ptr(D5)), "pod_five_body_descriptors")
 
 
+def pod_five_body_energy_forces(h: Handle, N, P, pos, cell, offsets, nbr_j, shift, rev, K5, P5, c5, E_atom=None,
+                                F=None):
+    arr, cp = _cell_ptr(cell)
+    _ok(lib().pod_five_body_energy_forces(h.ptr, int(N), int(P), _ptr(pos), cp, _ptr(offsets), _ptr(nbr_j),
+                                          _ptr(shift), _ptr(rev), int(K5), int(P5), _ptr(c5), _ptr(E_atom), _ptr(F)),
+        "pod_five_body_energy_forces")
+
+
 class AcsfSet:
     """A set of symmetry functions created on the device for one handle."""
 
@@ -564,6 +574,23 @@ class PodModel:
         if check:
             pod_check(self.h)
         return D5
+
+    def five_body_energy_forces(self, pos, cell, nbrs: DeviceNeighbors, K5: int, P5: int, c5, check=True):
+        """Per-atom energies and forces of the linear five-body term c5 . D5."""
+        import torch
+        pos = self._pos(pos)
+        c5 = torch.as_tensor(c5, dtype=self.torch_dtype, device=self.device).contiguous()
+        if c5.numel() != K5 * pod_five_body_count(P5):
+            raise ValueError("expected K5 x pod_five_body_count(P5) coefficients")
+        if nbrs.rev is None:
+            nbrs.build_reverse(self, check=check)
+        o = {"E_atom": torch.empty(nbrs.N, dtype=self.torch_dtype, device=self.device),
+             "F": torch.empty((nbrs.N, 3), dtype=self.torch_dtype, device=self.device)}
+        pod_five_body_energy_forces(self.h, nbrs.N, nbrs.P, pos, cell, nbrs.offsets, nbrs.nbr_j, nbrs.shift, nbrs.rev,
+                                    K5, P5, c5, o["E_atom"], o["F"])
+        if check:
+            pod_check(self.h)
+        return o
 
     def acsf(self, spec) -> AcsfSet:
         """A symmetry-function set (workloads.AcsfSpec or anything with g2,

@@ -2,14 +2,16 @@
 five-body oracle, which evaluates the defining quadruple sums with the POD
 oracle's radial basis (the same Q is passed to the library).
 
-FP64 at 1e-10 normwise per descriptor column.  FP32: products of four basis
+Energies and forces of c5 . D5 against the oracle's autograd of the same
+sums.  FP64 at 1e-10 normwise per descriptor column and per array.  FP32: products of four basis
 values summed with multinomial weights, where the columns with odd exponents
 cancel between terms; measured 6e-6 normwise per column, checked at the FP32
 energy bar of the POD path, 2e-5."""
 import numpy as np
 import pytest
+import torch
 
-from gpu_common import colerr, oracle_params, say
+from gpu_common import colerr, oracle_params, relerr, say
 from oracle import five_oracle as fo
 from oracle import pod_oracle as po
 from paper_2212_14446_amd import pod, workloads as wl
@@ -79,7 +81,6 @@ def test_open_cluster_isolated_atom_and_skin_list():
 
 
 def test_arguments_and_data_errors():
-    import torch
     m, p, Q = _model()
     pos, cell = wl.bcc(2)
     nl = wl.neighbor_list(pos, cell, S.rcut)
@@ -111,3 +112,63 @@ def test_bcc_15840_sampled():
     assert D.shape == (w.N, 6 * 22) and np.all(np.isfinite(D))
     atoms = np.sort(np.random.default_rng(8).choice(w.N, 5, replace=False))
     assert colerr(D[atoms], _oracle(w.pos, w.cell, w.nl, p, Q, 6, 4, atoms)) <= 1e-10
+
+
+def _c5(K5, P5, seed):
+    return np.random.default_rng(seed).normal(size=(K5, pod.pod_five_body_count(P5)))
+
+
+@pytest.mark.parametrize("n,K5,P5", [(2, 2, 4), (3, 3, 2), (2, 3, 0), (2, 1, 3)])
+def test_energy_forces_match_oracle(n, K5, P5):
+    pos, cell = wl.bcc(n)
+    pos = wl.displace(pos, 0.12, 50 + n)
+    nl = wl.neighbor_list(pos, cell, S.rcut)
+    say(f"[gpu] five-body energy/forces N={pos.shape[0]} K5={K5} P5={P5}")
+    m, p, Q = _model()
+    c5 = _c5(K5, P5, 7)
+    o = m.five_body_energy_forces(pos, cell, pod.DeviceNeighbors.from_list(nl), K5, P5, c5)
+    E_ref, F_ref = fo.energy_forces5(pos, cell, nl.offsets, nl.nbr_j, nl.shift3, p, Q, K5, P5, c5)
+    assert relerr(o["E_atom"].cpu().numpy(), E_ref) <= 1e-10
+    assert relerr(o["F"].cpu().numpy(), F_ref) <= 1e-10
+
+
+def test_energy_forces_fp32_reproducible_and_skin():
+    pos, cell = wl.bcc(2)
+    pos = wl.displace(pos, 0.12, 61)
+    nl = wl.neighbor_list(pos, cell, S.rcut)
+    skin = wl.neighbor_list(pos, cell, S.rcut + 0.5)
+    c5 = _c5(2, 4, 8)
+    m32, p, Q = _model(dtype="f32")
+    nb = pod.DeviceNeighbors.from_list(skin)
+    a = m32.five_body_energy_forces(pos, cell, nb, 2, 4, c5)
+    b = m32.five_body_energy_forces(pos, cell, nb, 2, 4, c5)
+    assert torch.equal(a["F"], b["F"]) and torch.equal(a["E_atom"], b["E_atom"])   # no atomics
+    E_ref, F_ref = fo.energy_forces5(pos.astype(np.float32).astype(np.float64), cell, nl.offsets, nl.nbr_j,
+                                     nl.shift3, p, Q, 2, 4, c5.astype(np.float32).astype(np.float64))
+    eE = relerr(a["E_atom"].double().cpu().numpy(), E_ref)
+    eF = relerr(a["F"].double().cpu().numpy(), F_ref)
+    say(f"[gpu] five-body fp32 energy {eE:.2e} forces {eF:.2e}")
+    assert eE <= 2e-5 and eF <= 1e-4
+    F = a["F"].double().cpu().numpy()
+    assert np.abs(F.sum(0)).max() <= 1e-5 * np.abs(F).max() * pos.shape[0]
+
+
+def test_energy_forces_arguments():
+    m, p, Q = _model()
+    pos, cell = wl.bcc(2)
+    nl = wl.neighbor_list(pos, cell, S.rcut)
+    nb = pod.DeviceNeighbors.from_list(nl)
+    nb.build_reverse(m)
+    x = m._pos(pos)
+    c5 = torch.ones(2 * 5, dtype=torch.float64, device="cuda")
+    E = torch.empty(nb.N, dtype=torch.float64, device="cuda")
+    F = torch.empty((nb.N, 3), dtype=torch.float64, device="cuda")
+    args = (m.h, nb.N, nb.P, x, cell, nb.offsets, nb.nbr_j, nb.shift)
+    for rev, c, e, f in ((None, c5, E, F), (nb.rev, None, E, F), (nb.rev, c5, None, None)):
+        with pytest.raises(pod.PodError) as err:
+            pod.pod_five_body_energy_forces(*args, rev, 2, 2, c, e, f)
+        assert pod.ERRORS[err.value.code] == "POD_EINVAL"
+    pod.pod_five_body_energy_forces(*args, None, 2, 2, c5, E, None)    # energies alone need no reverse index
+    m.check()
+    D = m.five_body_descriptors(pos, cell, nb, 2, 2).cpu().numpy()
+    assert relerr(E.cpu().numpy(), D @ c5.cpu().numpy()) <= 1e-12
