@@ -441,9 +441,10 @@ def run_acsf(steps, warmup=3):
 def run_five(steps, warmup=3):
     """Five-body descriptors (the extension of Sec. II.F to body order five)
     on the 15,840-atom box with the box's radial basis (K = 6): P5 = 2 (5
-    orbits) and P5 = 4 (22 orbits) per radial function, FP64 and FP32; kernel
-    times (pair records + five-body kernel) from HIP events on the leg's
-    stream."""
+    orbits) and P5 = 4 (22 orbits) per radial function, and the energy and
+    forces of c5 . D5 at P5 = 4, FP64 and FP32; kernel times from HIP events
+    on the leg's stream."""
+    import numpy as np
     import torch
 
     from paper_2212_14446_amd import pod, workloads as wl
@@ -471,6 +472,26 @@ def run_five(steps, warmup=3):
             out[f"{dt}_P5_{P5}"] = {"descriptors": 6 * n, "kernel_ms": t, "pair_record_ms": pms / max(pn, 1),
                                     "five_body_ms": kms / max(kn, 1), "atoms_per_s": w.N / (t * 1e-3)}
             print(f"[bench] five-body {dt} P5={P5} {out[f'{dt}_P5_{P5}']}", file=sys.stderr, flush=True)
+        # energy and forces of c5 . D5 at P5 = 4
+        n = pod.pod_five_body_count(4)
+        nb.build_reverse(m)
+        c5 = torch.tensor(np.random.default_rng(3).normal(size=6 * n) * 1e-3, dtype=m.torch_dtype, device="cuda")
+        E_atom = torch.empty(w.N, dtype=m.torch_dtype, device="cuda")
+        F = torch.empty((w.N, 3), dtype=m.torch_dtype, device="cuda")
+        call = lambda: pod.pod_five_body_energy_forces(m.h, w.N, nb.P, x, w.cell, nb.offsets, nb.nbr_j, nb.shift,
+                                                       nb.rev, 6, 4, c5, E_atom, F)
+        for _ in range(warmup):
+            call()
+        pod.pod_set_kernel_timing(m.h, steps)
+        for _ in range(steps):
+            call()
+        kms, kn = pod.pod_get_kernel_time(m.h, 1)
+        pms, pn = pod.pod_get_kernel_time(m.h, 0)
+        pod.pod_set_kernel_timing(m.h, 0)
+        m.check()
+        t = (kms + pms) / steps   # all timed intervals of the calls: records, basis, gradients + gather
+        out[f"{dt}_P5_4_energy_forces"] = {"kernel_ms": t, "atoms_per_s": w.N / (t * 1e-3)}
+        print(f"[bench] five-body {dt} E+F {out[f'{dt}_P5_4_energy_forces']}", file=sys.stderr, flush=True)
     return out
 
 
