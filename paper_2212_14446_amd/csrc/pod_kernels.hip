@@ -166,7 +166,6 @@ __device__ __forceinline__ void atom_body(const KArgs<T>& g) {
     constexpr int NAP = odd_len(NA);
     using Tab = D4Table<PA>;
     constexpr int KA = Tab::KA;
-    constexpr int NT = Tab::NT;
 
     const ParamsT<T>* __restrict__ P = &g.prm;
     const int K = P->K;
@@ -255,10 +254,16 @@ __device__ __forceinline__ void atom_body(const KArgs<T>& g) {
 #pragma unroll
     for (int p = 0; p < KA; ++p)
         if (Tab::build.pb[p] == 0) d4[p] = acc[0] * d3[Tab::build.pa[p]];                   // eq. (27a)
+    // eq. (30a) for the triples the model uses (none without 4-body terms):
+    // the others only ever meet zero weights
+    const int ka_used = P->K4 > 0 ? P->Ka4 : 0;
 #pragma unroll
-    for (int t = 0; t < NT; ++t)                                                             // eq. (30a)
-        d4[Tab::build.tp[t]] += T(Tab::build.tc[t]) * acc[Tab::build.tx[t]] * acc[Tab::build.ty[t]] *
-                                acc[Tab::build.tz[t]];
+    for (int p = 0; p < KA; ++p)
+        if (p < ka_used) {
+#pragma unroll
+            for (int t = Tab::build.tbeg[p]; t < Tab::build.tend[p]; ++t)
+                d4[p] += T(Tab::build.tc[t]) * acc[Tab::build.tx[t]] * acc[Tab::build.ty[t]] * acc[Tab::build.tz[t]];
+        }
 
     const bool has2 = act && m < P->K2;
     const bool has3 = act && m < P->K3;
@@ -339,26 +344,34 @@ __device__ __forceinline__ void atom_body(const KArgs<T>& g) {
             for (int mu = 0; mu < NA; ++mu)
                 abrow[mu] = T(2 * mt.mult[mu]) * eff3[mt.deg[mu]] * acc[mu] + (mu == 0 ? eff2 : T(0));  // eq. (26c)
 #pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                const int x = Tab::build.tx[t], y = Tab::build.ty[t], z = Tab::build.tz[t];
-                const T wc = w4[Tab::build.tp[t]] * T(Tab::build.tc[t]);
-                abrow[x] += wc * acc[y] * acc[z];
-                abrow[y] += wc * acc[x] * acc[z];
-                abrow[z] += wc * acc[x] * acc[y];
-            }
+            for (int p = 0; p < KA; ++p)
+                if (p < ka_used) {
+#pragma unroll
+                    for (int t = Tab::build.tbeg[p]; t < Tab::build.tend[p]; ++t) {
+                        const int x = Tab::build.tx[t], y = Tab::build.ty[t], z = Tab::build.tz[t];
+                        const T wc = w4[p] * T(Tab::build.tc[t]);
+                        abrow[x] += wc * acc[y] * acc[z];
+                        abrow[y] += wc * acc[x] * acc[z];
+                        abrow[z] += wc * acc[x] * acc[y];
+                    }
+                }
         }
     } else {
 #pragma unroll
         for (int mu = 0; mu < NA; ++mu) ab[mu] = T(2 * mt.mult[mu]) * eff3[mt.deg[mu]] * acc[mu];  // eq. (26c)
         ab[0] += eff2;
 #pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            const int x = Tab::build.tx[t], y = Tab::build.ty[t], z = Tab::build.tz[t];
-            const T wc = w4[Tab::build.tp[t]] * T(Tab::build.tc[t]);
-            ab[x] += wc * acc[y] * acc[z];
-            ab[y] += wc * acc[x] * acc[z];
-            ab[z] += wc * acc[x] * acc[y];
-        }
+        for (int p = 0; p < KA; ++p)
+            if (p < ka_used) {
+#pragma unroll
+                for (int t = Tab::build.tbeg[p]; t < Tab::build.tend[p]; ++t) {
+                    const int x = Tab::build.tx[t], y = Tab::build.ty[t], z = Tab::build.tz[t];
+                    const T wc = w4[p] * T(Tab::build.tc[t]);
+                    ab[x] += wc * acc[y] * acc[z];
+                    ab[y] += wc * acc[x] * acc[z];
+                    ab[z] += wc * acc[x] * acc[y];
+                }
+            }
     }
 
     // per-atom energy: sum the K lanes of the atom through LDS
