@@ -10,6 +10,12 @@
  *   - 2/3/4-body descriptors by the fast contractions        Sec. II.E, eqs. (25)-(30a)
  *   - linear energy E_i = sum_m c_m D_im, E = c . G          Sec. IV.A, eqs. (57a), (58a)
  *   - forces and virial from the descriptor derivatives      Sec. II.G, eqs. (26c), (24c)
+ *   - batched descriptor matrices and the linear fit         Sec. IV.A, eqs. (58a), (63a)
+ *   - network surrogate of the 4-body term                   Sec. IV.D
+ *   - exclusive-sum descriptors (cost comparison)            Sec. II.C-D, eqs. (15b), (20a)
+ *   - five-body descriptors (higher body order)              Sec. II.F
+ *   - atom-centred symmetry functions                        Sec. III.B, eqs. (21c)-(22d)
+ *   - molecular dynamics and neighbour lists                 Sec. V, Sec. II.A
  *
  * Conventions shared by every call
  *   - Descriptor vector of one atom (length M):

@@ -120,6 +120,11 @@ def lib():
     return L
 
 
+def pod_strerror(code: int) -> str:
+    """Static description of an error code."""
+    return lib().pod_strerror(int(code)).decode()
+
+
 def _strerror(code):
     try:
         return lib().pod_strerror(int(code)).decode()
@@ -414,6 +419,13 @@ def pod_acsf_create(h: Handle, g2=(), g3=(), g4=()) -> AcsfSet:
     n, nc = ctypes.c_int(), ctypes.c_int()
     _ok(lib().pod_acsf_num_functions(out, ctypes.byref(n), ctypes.byref(nc)), "pod_acsf_num_functions")
     return AcsfSet(out, h, n.value, nc.value)
+
+
+def pod_acsf_num_functions(a: AcsfSet):
+    """(number of functions, number of radial channels) of a set."""
+    n, nc = ctypes.c_int(), ctypes.c_int()
+    _ok(lib().pod_acsf_num_functions(a.ptr, ctypes.byref(n), ctypes.byref(nc)), "pod_acsf_num_functions")
+    return n.value, nc.value
 
 
 def pod_acsf_descriptors(h: Handle, a: AcsfSet, N, P, pos, cell, offsets, nbr_j, shift, G):

@@ -18,6 +18,14 @@ def test_library_exports_every_header_symbol():
         assert hasattr(L, n), n
 
 
+def test_binding_has_every_header_symbol():
+    """The Python binding offers each C entry point under the same name."""
+    for n in pod.header_symbols():
+        assert callable(getattr(pod, n, None)), n
+    for n in ("pod_acsf_create", "pod_five_body_energy_forces", "pod_md_verlet", "pod_fit_solve"):
+        assert n in pod.header_symbols()
+
+
 def _setup(s: wl.PodSetup):
     return pod.setup_from_workload(s)
 
