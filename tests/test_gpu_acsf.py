@@ -214,3 +214,20 @@ def test_bcc_15840_sampled():
     _, Fo = ao.energy_forces(w.pos, w.cell, w.nl.offsets, w.nl.nbr_j, w.nl.shift3, RIN, RCUT, spec, W, atoms=few)
     assert relerr(F[few], Fo) <= 1e-10
     assert np.abs(F.sum(0)).max() <= 1e-11 * np.abs(F).max() * w.N
+
+
+def test_triclinic_cell_with_self_images():
+    """A sheared 2-atom cell smaller than the cut-off: every neighbour is a
+    periodic image, several of them of the atom itself."""
+    cell = np.array([[3.1, 0.0, 0.0], [1.2, 3.0, 0.0], [0.7, -0.9, 3.3]])
+    pos = np.array([[0.1, 0.2, 0.3], [1.9, 1.4, 1.8]])
+    nl = wl.neighbor_list(pos, cell, RCUT)
+    assert np.any(nl.nbr_j[: nl.offsets[1]] == 0)            # atom 0 sees its own images
+    spec = SPECS["degree2_shared"]
+    m = _model()
+    a = m.acsf(spec)
+    W = np.random.default_rng(3).normal(size=(2, spec.n))
+    F, G = m.acsf_forces(a, pos, cell, pod.DeviceNeighbors.from_list(nl), W, with_G=True)
+    assert colerr(G.cpu().numpy(), _oracle_G(pos, cell, nl, spec)) <= 1e-10
+    _, Fo = ao.energy_forces(pos, cell, nl.offsets, nl.nbr_j, nl.shift3, RIN, RCUT, spec, W)
+    assert relerr(F.cpu().numpy(), Fo) <= 1e-10

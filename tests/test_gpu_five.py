@@ -172,3 +172,17 @@ def test_energy_forces_arguments():
     m.check()
     D = m.five_body_descriptors(pos, cell, nb, 2, 2).cpu().numpy()
     assert relerr(E.cpu().numpy(), D @ c5.cpu().numpy()) <= 1e-12
+
+
+def test_energy_forces_open_cluster_with_isolated_atom():
+    rng = np.random.default_rng(9)
+    pos, _ = wl.lattice("bcc", 2, 1, 1, 3.31)
+    pos = np.vstack([pos + rng.normal(0, 0.1, pos.shape), [[30.0, 30.0, 30.0]]])
+    nl = wl.neighbor_list(pos, None, S.rcut)
+    m, p, Q = _model()
+    c5 = _c5(3, 3, 4)
+    o = m.five_body_energy_forces(pos, None, pod.DeviceNeighbors.from_list(nl), 3, 3, c5)
+    E_ref, F_ref = fo.energy_forces5(pos, None, nl.offsets, nl.nbr_j, nl.shift3, p, Q, 3, 3, c5)
+    assert relerr(o["E_atom"].cpu().numpy(), E_ref) <= 1e-10
+    assert relerr(o["F"].cpu().numpy(), F_ref) <= 1e-10
+    assert o["E_atom"][-1].item() == 0.0 and torch.count_nonzero(o["F"][-1]).item() == 0
