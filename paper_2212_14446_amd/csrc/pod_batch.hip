@@ -308,13 +308,23 @@ __global__ __launch_bounds__(MAX_THREADS) void batch_kernel(BArgs g) {
                             double hn[PA + 1];
 #pragma unroll
                             for (int n = 0; n <= PA; ++n) hn[n] = 0.0;
-                            double q0 = 0, q1 = 0, q2 = 0;
+                            // grad_u h by exponent groups: q_d = sum_n n gq[d][n], one FMA per term
+                            double gq[3][PA + 1];
+#pragma unroll
+                            for (int n = 0; n <= PA; ++n) { gq[0][n] = 0.0; gq[1][n] = 0.0; gq[2][n] = 0.0; }
 #pragma unroll
                             for (int mu = 0; mu < NA; ++mu) {
                                 hn[mt.deg[mu]] += J[mu] * A[mu];
-                                if (mt.down[mu][0] >= 0) q0 += double(mt.ex[mu][0]) * J[mu] * A[mt.down[mu][0]];
-                                if (mt.down[mu][1] >= 0) q1 += double(mt.ex[mu][1]) * J[mu] * A[mt.down[mu][1]];
-                                if (mt.down[mu][2] >= 0) q2 += double(mt.ex[mu][2]) * J[mu] * A[mt.down[mu][2]];
+#pragma unroll
+                                for (int dd = 0; dd < 3; ++dd)
+                                    if (mt.down[mu][dd] >= 0) gq[dd][mt.ex[mu][dd]] += J[mu] * A[mt.down[mu][dd]];
+                            }
+                            double q0 = 0, q1 = 0, q2 = 0;
+#pragma unroll
+                            for (int n = 1; n <= PA; ++n) {
+                                q0 += double(n) * gq[0][n];
+                                q1 += double(n) * gq[1][n];
+                                q2 += double(n) * gq[2][n];
                             }
                             double hsum = 0.0, eul = 0.0;
 #pragma unroll
