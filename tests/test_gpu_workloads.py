@@ -73,3 +73,33 @@ def test_cfg2_rcut6_sampled():
     eFg = relerr(got["F_gather"][atoms], o["F"][atoms])
     say(f"[gpu]   f64 D={eD:.2e} E={eE:.2e} F={eF:.2e} F_gather={eFg:.2e}")
     assert max(eD, eE, eF, eFg) < 1e-10
+
+
+def test_largest_box_sampled_f32():
+    """The largest workload, the 1,024,000-atom box of the surrogate
+    benchmark (25,971,800 pairs), FP32 2/3/4-body model on both force paths:
+    per-atom energies and forces of sampled atoms, and the total force,
+    against the oracle on the FP32-rounded positions."""
+    import torch
+    from oracle import pod_oracle as po
+    from paper_2212_14446_amd import pod
+    w = wl.config5_infer()
+    c = wl.coefficients(w.setup.M, 71) * 1e-2
+    case = Case(w.pos, w.cell, w.nl, w.setup, c, w.name)
+    say(f"[gpu] largest box: N={w.N} P={w.nl.n_pairs}")
+    m = case.model("f32")
+    nb = pod.DeviceNeighbors.from_list(w.nl)
+    o = m.energy_forces(w.pos, w.cell, nb, c, global_desc=False)
+    torch.cuda.synchronize()
+    E_atom, F = o["E_atom"].double().cpu().numpy(), o["F"].double().cpu().numpy()
+    nb.build_reverse(m)
+    Fg = m.energy_forces(w.pos, w.cell, nb, c, global_desc=False)["F"].double().cpu().numpy()
+    atoms = np.sort(np.random.default_rng(72).choice(w.N, 12, replace=False))
+    x32 = positions_for("f32", w.pos)
+    ref = po.energy_forces(x32, w.cell, w.nl.offsets.astype(np.int64), w.nl.nbr_j, w.nl.shift3, case.op, case.Q,
+                           case.c, force_atoms=atoms)
+    eE = relerr(E_atom[atoms], ref["E_atom"][atoms])
+    eF, eFg = relerr(F[atoms], ref["F"][atoms]), relerr(Fg[atoms], ref["F"][atoms])
+    say(f"[gpu]   f32 E_atom={eE:.2e} F={eF:.2e} F_gather={eFg:.2e}")
+    assert eE <= 2e-5 and eF <= 1e-4 and eFg <= 1e-4
+    assert np.abs(Fg.sum(0)).max() <= 1e-4 * np.abs(Fg).max() * np.sqrt(w.N)
