@@ -24,7 +24,7 @@
 //                     class PD (0, 2, 4, 6) per grid row: B in registers,
 //                     invariants, functions; with weights W, the adjoint
 //                     dL/dB of each channel (written to scratch).
-//   pair_kernel<PDM>  one thread per pair: the derivative of
+//   pair_kernel<PDM>  16 lanes per atom, one pair per lane: the derivative of
 //                     sum_c dL/dB_c . B_c with respect to r_ij (eq. (24c) with
 //                     g, g' in place of R_m, R'_m), summed over channels.
 //   gather_kernel     F_i = sum over the pairs p of i of (V_p - V_rev(p)).
@@ -54,6 +54,7 @@ constexpr int ACSF_THREADS = 256;
 template <typename T, int PD, bool ADJ>
 constexpr int acsf_split() { return (ADJ && PD >= 4 && sizeof(T) == 8) ? 2 : 4; }
 constexpr int GATHER_LANES = 16;                       // lanes per atom in the force gather
+constexpr int PAIR_LANES = 16;                         // lanes per atom in the pair-gradient kernel
 
 // Channels of one degree class a basis thread carries at once.
 constexpr int channels_per_thread(int pd) { return pd == 0 ? 8 : (pd == 2 ? 2 : 1); }
@@ -321,23 +322,21 @@ __device__ __forceinline__ void contract(const T* __restrict__ bb, const T (&A)[
     }
 }
 
-// One thread per pair; its centre atom i (offsets[i] <= p < offsets[i + 1])
-// by binary search, so a pair outside every range gets a zero gradient.
+// PAIR_LANES lanes per atom walk its pairs (pairs outside every atom's
+// range keep whatever the caller's buffer held and are never read).
 template <typename T, int PDM>
 __global__ __launch_bounds__(ACSF_THREADS) void pair_kernel(AArgs<T> g, int nch) {
     constexpr MonoTable<PDM> mt{};
     constexpr int NAM = n_mono(PDM);
-    const int p = blockIdx.x * ACSF_THREADS + threadIdx.x;
-    if (p >= g.P) return;
-    int lo = 0, hi = g.N;
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (g.offsets[mid] <= p) lo = mid; else hi = mid;
-    }
-    const int i = lo;
+    const int i = blockIdx.x * (ACSF_THREADS / PAIR_LANES) + static_cast<int>(threadIdx.x) / PAIR_LANES;
+    const int l = static_cast<int>(threadIdx.x) % PAIR_LANES;
+    if (i >= g.N) return;
+    int p0, p1;
+    pair_range(g, i, p0, p1);
+    for (int p = p0 + l; p < p1; p += PAIR_LANES) {
     T v0 = T(0), v1 = T(0), v2 = T(0);
     T r, ux, uy, uz;
-    if (g.offsets[i] <= p && p < g.offsets[i + 1] && pair_geometry(g, i, p, r, ux, uy, uz)) {
+    if (pair_geometry(g, i, p, r, ux, uy, uz)) {
         T fc, dfc;
         cutoff(r, g.rin, g.inv_h, fc, dfc);
         const T ir = T(1) / r;
@@ -373,6 +372,7 @@ __global__ __launch_bounds__(ACSF_THREADS) void pair_kernel(AArgs<T> g, int nch)
     g.V[3 * static_cast<size_t>(p)] = v0;
     g.V[3 * static_cast<size_t>(p) + 1] = v1;
     g.V[3 * static_cast<size_t>(p) + 2] = v2;
+    }
 }
 
 // F_i = -dE/dx_i: E_i depends on x_j - x_i through the pairs of i, and x_i
@@ -531,7 +531,8 @@ int forces_impl(pod_handle* h, const pod_acsf* a, int N, int P, const void* pos,
     g.rev = rev;
     g.F = static_cast<T*>(F);
     launch_basis<T, true>(h, a, g);
-    const dim3 pgrid(P > 0 ? (P + ACSF_THREADS - 1) / ACSF_THREADS : 1);
+    const int ppb = ACSF_THREADS / PAIR_LANES;
+    const dim3 pgrid((N + ppb - 1) / ppb);
     timing_begin(h, 0);
     switch (a->pd_max) {
         case 0: hipLaunchKernelGGL((pair_kernel<T, 0>), pgrid, dim3(ACSF_THREADS), 0, h->stream, g, a->nch); break;
