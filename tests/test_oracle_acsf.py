@@ -3,8 +3,9 @@
 Environments with one, two and three neighbours whose sums can be written out
 by hand (every ordered tuple enumerated), the special exponents that reduce
 the functions to powers of the radial sum, invariance under rotation and
-neighbour permutation, the cut-off contract, and forces against central
-finite differences of the weighted energy."""
+neighbour permutation, the cut-off contract, forces against central
+finite differences of the weighted energy, and the invariant expansion the
+device uses against the defining sums."""
 import math
 
 import numpy as np
@@ -167,3 +168,42 @@ def test_forces_of_a_subset_equal_the_full_evaluation():
     atoms = [1, 7, 12]
     _, Fs = ao.energy_forces(pos, cell, nl.offsets, nl.nbr_j, nl.shift3, RIN, RCUT, spec, W, atoms=atoms)
     assert np.abs(Fs - F[atoms]).max() <= 1e-12 * np.abs(F).max()
+
+
+def test_defining_sums_equal_the_invariant_expansion():
+    """The expansion the device evaluates (Sec. II.E applied to eqs. (22c),
+    (22d)): G3 = 2^(1-zeta) sum_n C(zeta, n) lambda^n S_n with
+    S_n = sum_jk g_j g_k w_jk^n, and G4 = sum C(a,n1) C(b,n2) C(c,n3)
+    alpha^n1 beta^n2 gamma^n3 T(sorted(n1, n2, n3)) with T the symmetric
+    four-body sum -- checked here against the defining sums, on the CPU."""
+    rng = np.random.default_rng(12)
+    d = rng.normal(size=(8, 3))
+    d *= (rng.uniform(1.0, 4.8, size=8) / np.linalg.norm(d, axis=1))[:, None]
+    r = np.linalg.norm(d, axis=1)
+    u = d / r[:, None]
+    w = u @ u.T
+    fc = po.cutoff(r, RIN, RCUT)[0]
+    spec = wl.AcsfSpec(g3=((0.1, 3, -0.7), (0.2, 0, 1.0), (0.05, 6, 1.0)),
+                       g4=((0.05, 2, 1, 3, 0.5, -0.3, 0.8), (0.1, 1, 1, 1, 1.0, 1.0, 1.0)))
+    G = _env(d, spec)
+
+    def S(eta, n):
+        g = np.exp(-eta * r * r) * fc
+        return float(np.einsum("jk,j,k->", w ** n, g, g))
+
+    def T(eta, n1, n2, n3):
+        g = np.exp(-eta * r * r) * fc
+        return float(np.einsum("jk,jl,kl,j,k,l->", w ** n1, w ** n2, w ** n3, g, g, g))
+
+    want = []
+    for eta, z, lam in spec.g3:
+        want.append(sum(2.0 ** (1 - z) * math.comb(z, n) * lam ** n * S(eta, n) for n in range(z + 1)))
+    for eta, a, b, c, al, be, ga in spec.g4:
+        v = 0.0
+        for n1 in range(a + 1):
+            for n2 in range(b + 1):
+                for n3 in range(c + 1):
+                    wgt = math.comb(a, n1) * al ** n1 * math.comb(b, n2) * be ** n2 * math.comb(c, n3) * ga ** n3
+                    v += wgt * T(eta, *sorted((n1, n2, n3), reverse=True))
+        want.append(v)
+    assert np.abs(G - np.array(want)).max() <= 1e-12 * np.abs(G).max()
