@@ -5,7 +5,8 @@ orbits; the exponent tuples whose angle graph splits or leaves a neighbour
 free, which reduce the quadruple sum to products of the POD oracle's own two-,
 three- and four-body descriptors (eqs. (12b), (15), (18a)); and geometric
 closed forms for environments with cosines 0 and -1; the energy c5 . D5 and
-its forces against central finite differences."""
+its forces against central finite differences; and the atomic-basis
+expansion the device uses against the defining sums."""
 import itertools
 import math
 
@@ -183,3 +184,37 @@ def test_energy_and_forces_of_the_oracle():
         Ep = (fo.descriptors5(xp, cell, nl.offsets, nl.nbr_j, nl.shift3, p, Q, K5, P5) @ c5.reshape(-1)).sum()
         Em = (fo.descriptors5(xm, cell, nl.offsets, nl.nbr_j, nl.shift3, p, Q, K5, P5) @ c5.reshape(-1)).sum()
         assert abs(F[a, e] + (Ep - Em) / (2 * h)) <= 1e-6 * np.abs(F).max()
+
+
+def test_quadruple_sums_equal_the_atomic_basis_expansion():
+    """The expansion the device evaluates: with B_mu = sum_j R_j u_j^mu,
+    D5_e = sum over multi-indices alpha_t (|alpha_t| = e_t) of
+    prod_t mult(alpha_t) times B at the monomial of each neighbour slot (the
+    sum of the alpha_t of its three angles) -- against the defining sums."""
+    d, r = _env(6, 13)
+    p, Q = _pod_params()
+    R = po.radial_basis(r, p, Q)[0][:, 0]
+    U = d / r[:, None]
+    W = U @ U.T
+
+    def B(ex):
+        return float((R * np.prod(U ** np.asarray(ex), axis=1)).sum())
+
+    def monos(n):
+        return [(a, b, n - a - b) for a in range(n + 1) for b in range(n + 1 - a)]
+
+    def mult(al):
+        return math.factorial(sum(al)) // (math.factorial(al[0]) * math.factorial(al[1]) * math.factorial(al[2]))
+
+    slots = [[t for t, (a, b) in enumerate(fo.EDGES) if v in (a, b)] for v in range(4)]
+    for e in fo.orbits(3) + [(2, 1, 0, 0, 1, 0), (1, 0, 1, 1, 0, 1)]:
+        total = 0.0
+        for als in itertools.product(*[monos(n) for n in e]):
+            wgt = np.prod([mult(al) for al in als])
+            prod = 1.0
+            for v in range(4):
+                ex = tuple(sum(als[t][k] for t in slots[v]) for k in range(3))
+                prod *= B(ex)
+            total += wgt * prod
+        ref = fo.five_body_sum(R, W, e)
+        assert abs(total - ref) <= 1e-12 * max(1.0, abs(ref)), e
