@@ -30,8 +30,10 @@ namespace {
 constexpr int FIVE_MAX_ORBITS = 22;   // orbits with |e| <= 4
 constexpr int FIVE_CAP = 700;         // merged terms (at most the 680 raw products for |e| <= 4)
 constexpr int FIVE_THREADS = 256;
-constexpr int FIVE_SPLIT = 2;         // lanes per atom, sharing its neighbours
-constexpr int FIVE_APB = FIVE_THREADS / FIVE_SPLIT;
+// Lanes per (atom, radial function) sharing its neighbours: two for the
+// descriptors; one with the adjoint, whose per-atom work both lanes would
+// otherwise repeat.
+constexpr int five_split(bool adj) { return adj ? 1 : 2; }
 constexpr int FIVE_PAIR_LANES = 16;   // lanes per atom in the pair-record kernel
 
 // angle positions (j,k), (j,l), (j,n), (k,l), (k,n), (l,n) with j,k,l,n = 0..3
@@ -261,8 +263,9 @@ __global__ __launch_bounds__(FIVE_THREADS) void five_kernel(FArgs<T> g) {
     constexpr int NA = n_mono(PD);
     using Tab = FiveTable<PD>;
     const int m = blockIdx.y;
-    const int i = blockIdx.x * FIVE_APB + static_cast<int>(threadIdx.x) / FIVE_SPLIT;
-    const int sub = static_cast<int>(threadIdx.x) % FIVE_SPLIT;
+    constexpr int SPLIT = five_split(ADJ);
+    const int i = blockIdx.x * (FIVE_THREADS / SPLIT) + static_cast<int>(threadIdx.x) / SPLIT;
+    const int sub = static_cast<int>(threadIdx.x) % SPLIT;
     if (i >= g.N) return;   // the whole group of the atom
     T B[NA];
 #pragma unroll
@@ -273,7 +276,7 @@ __global__ __launch_bounds__(FIVE_THREADS) void five_kernel(FArgs<T> g) {
         if (sub == 0) atomicOr(g.err, ERR_NEIGH);
         p1 = g.P;
     }
-    for (int p = p0 + sub; p < p1; p += FIVE_SPLIT) {
+    for (int p = p0 + sub; p < p1; p += SPLIT) {
         const T* row = g.rec + static_cast<size_t>(p) * g.rs;
         dev::accumulate_basis<T, PD>(B, row[4 + m], row[0], row[1], row[2]);
     }
@@ -281,7 +284,7 @@ __global__ __launch_bounds__(FIVE_THREADS) void five_kernel(FArgs<T> g) {
     for (int mu = 0; mu < NA; ++mu) {
         T v = B[mu];
 #pragma unroll
-        for (int o = 1; o < FIVE_SPLIT; o <<= 1) v += __shfl_xor(v, o);
+        for (int o = 1; o < SPLIT; o <<= 1) v += __shfl_xor(v, o);
         B[mu] = v;
     }
     T acc[Tab::ND];
@@ -492,7 +495,8 @@ int five_impl(pod_handle* h, const ParamsT<T>& prm, int N, int P, const void* po
         }
         timing_end(h, 0);
     }
-    const dim3 grid((N + FIVE_APB - 1) / FIVE_APB, K5);
+    const int fpb = FIVE_THREADS / five_split(energy);
+    const dim3 grid((N + fpb - 1) / fpb, K5);
     timing_begin(h, 1);
     if (P5 <= 2) {
         if (energy) hipLaunchKernelGGL((five_kernel<T, 2, true>), grid, dim3(FIVE_THREADS), 0, h->stream, g);
