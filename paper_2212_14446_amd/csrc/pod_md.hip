@@ -110,16 +110,35 @@ __global__ __launch_bounds__(MD_THREADS) void disp_kernel(int N, const T* __rest
 }
 
 // out = sum of nb partials (mode 0), their maximum (1), or the maximum of
-// *out and the partials (2); fixed order
-__global__ __launch_bounds__(64) void fold_kernel(const double* __restrict__ part, int nb, int mode,
-                                                  double* __restrict__ out) {
-    if (threadIdx.x != 0) return;
-    double s = mode == 2 ? *out : 0.0;
-    for (int b = 0; b < nb; ++b) {
+// *out and the partials (2), a NaN winning every maximum; fixed order (each
+// thread folds a strided subset, then a tree in LDS)
+__global__ __launch_bounds__(MD_THREADS) void fold_kernel(const double* __restrict__ part, int nb, int mode,
+                                                          double* __restrict__ out) {
+    __shared__ double red[MD_THREADS];
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nb; b += MD_THREADS) {
         const double x = part[b];
         s = mode ? ((x > s || x != x) ? x : s) : s + x;
     }
-    *out = s;
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = MD_THREADS / 2; o > 0; o >>= 1) {
+        if (static_cast<int>(threadIdx.x) < o) {
+            const double b = red[threadIdx.x + o];
+            const double a = red[threadIdx.x];
+            red[threadIdx.x] = mode ? ((b > a || b != b) ? b : a) : a + b;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double r = red[0];
+        if (mode == 2) {
+            const double a = *out;
+            *out = (r > a || r != r) ? r : a;
+        } else {
+            *out = r;
+        }
+    }
 }
 
 __global__ __launch_bounds__(64) void zero_kernel(double* out) {
@@ -152,7 +171,7 @@ int verlet_impl(pod_handle* h, int N, int P, void* pos, void* vel, void* F, cons
         if (N > 0) {
             hipLaunchKernelGGL((kick_drift_kernel<T>), dim3(nb1), dim3(MD_THREADS), 0, h->stream, N, x, v, f, xr, hka,
                                dt, xr ? partd : nullptr);
-            if (xr) hipLaunchKernelGGL(fold_kernel, dim3(1), dim3(64), 0, h->stream, partd, nb1, 2, max_disp);
+            if (xr) hipLaunchKernelGGL(fold_kernel, dim3(1), dim3(MD_THREADS), 0, h->stream, partd, nb1, 2, max_disp);
         }
         rc = pod_energy_forces(h, N, P, pos, cell, offsets, nbr_j, shift, rev, c, nullptr, E_pot ? E_pot + s : nullptr,
                                F, nullptr, nullptr);
@@ -161,7 +180,7 @@ int verlet_impl(pod_handle* h, int N, int P, void* pos, void* vel, void* F, cons
             hipLaunchKernelGGL((kick_kernel<T>), dim3(nb3), dim3(MD_THREADS), 0, h->stream, n3, v, f, hka,
                                half_m_over_acc, part);
         if (E_kin)
-            hipLaunchKernelGGL(fold_kernel, dim3(1), dim3(64), 0, h->stream, part, N > 0 ? nb3 : 0, 0, E_kin + s);
+            hipLaunchKernelGGL(fold_kernel, dim3(1), dim3(MD_THREADS), 0, h->stream, part, N > 0 ? nb3 : 0, 0, E_kin + s);
     }
     return hipGetLastError() == hipSuccess ? POD_OK : POD_EHIP;
 }
@@ -201,7 +220,7 @@ int pod_md_max_displacement(pod_handle* h, int N, const void* pos, const void* p
             hipLaunchKernelGGL((disp_kernel<float>), dim3(nb), dim3(MD_THREADS), 0, h->stream, N,
                                static_cast<const float*>(pos), static_cast<const float*>(pos_ref), part);
     }
-    hipLaunchKernelGGL(fold_kernel, dim3(1), dim3(64), 0, h->stream, part, N > 0 ? nb : 0, 1, out);
+    hipLaunchKernelGGL(fold_kernel, dim3(1), dim3(MD_THREADS), 0, h->stream, part, N > 0 ? nb : 0, 1, out);
     return hipGetLastError() == hipSuccess ? POD_OK : POD_EHIP;
 }
 
