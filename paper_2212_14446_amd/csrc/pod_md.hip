@@ -20,9 +20,11 @@ namespace {
 constexpr double ACC = 1.602176634e-19 / 1e-10 / 1.66053906660e-27 * 1e-20;
 constexpr int MD_THREADS = 256;
 constexpr int MD_BLOCKS = 512;   // grid-stride kernels; partial sums per block
+constexpr int KE_RING = 64;      // steps of kinetic-energy partials folded together
 
 // v += dt/2 a F, x += dt v, one atom per thread; with a reference, the
-// per-block maximum of |x - x_ref| (a NaN displacement wins)
+// block's running maximum of |x - x_ref| over the steps in its own slot of
+// `part` (a NaN displacement wins)
 template <typename T>
 __global__ __launch_bounds__(MD_THREADS) void kick_drift_kernel(int N, T* __restrict__ x, T* __restrict__ v,
                                                                 const T* __restrict__ F, const T* __restrict__ xr,
@@ -57,7 +59,10 @@ __global__ __launch_bounds__(MD_THREADS) void kick_drift_kernel(int N, T* __rest
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+    if (threadIdx.x == 0) {
+        const double r = red[0], o = part[blockIdx.x];
+        part[blockIdx.x] = (r > o || r != r) ? r : o;
+    }
 }
 
 // v += dt/2 a F; per-block partial sums of m v^2 / 2 (eV)
@@ -109,12 +114,15 @@ __global__ __launch_bounds__(MD_THREADS) void disp_kernel(int N, const T* __rest
     if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
-// out = sum of nb partials (mode 0), their maximum (1), or the maximum of
-// *out and the partials (2), a NaN winning every maximum; fixed order (each
-// thread folds a strided subset, then a tree in LDS)
+// Block b: out[b] = sum of the nb partials at part + b * stride (mode 0),
+// their maximum (1), or the maximum of out[b] and the partials (2), a NaN
+// winning every maximum; fixed order (each thread folds a strided subset,
+// then a tree in LDS)
 __global__ __launch_bounds__(MD_THREADS) void fold_kernel(const double* __restrict__ part, int nb, int mode,
-                                                          double* __restrict__ out) {
+                                                          double* __restrict__ out, long stride) {
     __shared__ double red[MD_THREADS];
+    part += blockIdx.x * stride;
+    out += blockIdx.x;
     double s = 0.0;
     for (int b = threadIdx.x; b < nb; b += MD_THREADS) {
         const double x = part[b];
@@ -141,8 +149,8 @@ __global__ __launch_bounds__(MD_THREADS) void fold_kernel(const double* __restri
     }
 }
 
-__global__ __launch_bounds__(64) void zero_kernel(double* out) {
-    if (threadIdx.x == 0) *out = 0.0;
+__global__ __launch_bounds__(MD_THREADS) void zero_kernel(double* out, int n) {
+    for (int k = threadIdx.x; k < n; k += MD_THREADS) out[k] = 0.0;
 }
 
 int md_blocks(long n) {
@@ -156,32 +164,40 @@ int verlet_impl(pod_handle* h, int N, int P, void* pos, void* vel, void* F, cons
                 double* E_pot, double* E_kin, const void* pos_ref, double* max_disp) {
     const long n3 = 3L * N;
     const int nb3 = md_blocks(n3), nb1 = md_blocks(N);
-    int rc = ensure_mscratch(h, sizeof(double) * 2 * MD_BLOCKS);
+    int rc = ensure_mscratch(h, sizeof(double) * (KE_RING + 1) * MD_BLOCKS);
     if (rc != POD_OK) return rc;
-    double* part = static_cast<double*>(h->d_mscratch);
-    double* partd = part + MD_BLOCKS;
+    double* partd = static_cast<double*>(h->d_mscratch);   // running displacement maxima
+    double* ring = partd + MD_BLOCKS;                       // kinetic-energy partials, KE_RING steps
     const double hka = 0.5 * dt * ACC / mass;
     const double half_m_over_acc = 0.5 * mass / ACC;
     T* x = static_cast<T*>(pos);
     T* v = static_cast<T*>(vel);
     T* f = static_cast<T*>(F);
     const T* xr = max_disp ? static_cast<const T*>(pos_ref) : nullptr;
-    if (max_disp) hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(64), 0, h->stream, max_disp);
+    if (max_disp) {
+        hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(MD_THREADS), 0, h->stream, max_disp, 1);
+        hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(MD_THREADS), 0, h->stream, partd, MD_BLOCKS);
+    }
     for (int s = 0; s < nsteps; ++s) {
-        if (N > 0) {
+        if (N > 0)
             hipLaunchKernelGGL((kick_drift_kernel<T>), dim3(nb1), dim3(MD_THREADS), 0, h->stream, N, x, v, f, xr, hka,
                                dt, xr ? partd : nullptr);
-            if (xr) hipLaunchKernelGGL(fold_kernel, dim3(1), dim3(MD_THREADS), 0, h->stream, partd, nb1, 2, max_disp);
-        }
         rc = pod_energy_forces(h, N, P, pos, cell, offsets, nbr_j, shift, rev, c, nullptr, E_pot ? E_pot + s : nullptr,
                                F, nullptr, nullptr);
         if (rc != POD_OK) return rc;
+        double* ke = ring + static_cast<long>(s % KE_RING) * MD_BLOCKS;
         if (N > 0)
             hipLaunchKernelGGL((kick_kernel<T>), dim3(nb3), dim3(MD_THREADS), 0, h->stream, n3, v, f, hka,
-                               half_m_over_acc, part);
-        if (E_kin)
-            hipLaunchKernelGGL(fold_kernel, dim3(1), dim3(MD_THREADS), 0, h->stream, part, N > 0 ? nb3 : 0, 0, E_kin + s);
+                               half_m_over_acc, ke);
+        // kinetic energies of up to KE_RING steps in one launch, one block per step
+        if (E_kin && (s % KE_RING == KE_RING - 1 || s == nsteps - 1)) {
+            const int cnt = s % KE_RING + 1;
+            hipLaunchKernelGGL(fold_kernel, dim3(cnt), dim3(MD_THREADS), 0, h->stream, ring, N > 0 ? nb3 : 0, 0,
+                               E_kin + (s + 1 - cnt), static_cast<long>(MD_BLOCKS));
+        }
     }
+    if (max_disp && N > 0)
+        hipLaunchKernelGGL(fold_kernel, dim3(1), dim3(MD_THREADS), 0, h->stream, partd, nb1, 2, max_disp, 0L);
     return hipGetLastError() == hipSuccess ? POD_OK : POD_EHIP;
 }
 
@@ -220,7 +236,7 @@ int pod_md_max_displacement(pod_handle* h, int N, const void* pos, const void* p
             hipLaunchKernelGGL((disp_kernel<float>), dim3(nb), dim3(MD_THREADS), 0, h->stream, N,
                                static_cast<const float*>(pos), static_cast<const float*>(pos_ref), part);
     }
-    hipLaunchKernelGGL(fold_kernel, dim3(1), dim3(MD_THREADS), 0, h->stream, part, N > 0 ? nb : 0, 1, out);
+    hipLaunchKernelGGL(fold_kernel, dim3(1), dim3(MD_THREADS), 0, h->stream, part, N > 0 ? nb : 0, 1, out, 0L);
     return hipGetLastError() == hipSuccess ? POD_OK : POD_EHIP;
 }
 
