@@ -141,6 +141,53 @@ def run_gpu(w, dtype, steps, warmup):
             "E": float(out["E"].item())}
 
 
+def _relerr(x, ref):
+    """Normwise relative error max|x - ref| / max|ref| (host float64)."""
+    x = np.asarray(x, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    den = float(np.max(np.abs(ref))) if ref.size else 0.0
+    num = float(np.max(np.abs(x - ref))) if ref.size else 0.0
+    return num / den if den > 0 else num
+
+
+def _colerr(D, ref):
+    """Worst per-column normwise relative error of a descriptor matrix."""
+    return max(_relerr(D[:, k], ref[:, k]) for k in range(ref.shape[1]))
+
+
+@on_stream
+def precision_errors(pos, cell, nl, setup, c, descriptors=True):
+    """FP32 path against the FP64 path on the same inputs (positions and
+    coefficients rounded to FP32 first, so only the arithmetic differs):
+    normwise relative error of E, E_atom, F, W, G and, per column, D.  The
+    FP64 path is the reference: its own parity with the FP64 oracle is
+    1e-10 (tests/test_gpu_workloads.py)."""
+    import torch
+
+    from paper_2212_14446_amd import pod
+    pos32 = np.asarray(pos, dtype=np.float32).astype(np.float64)
+    c32 = np.asarray(c, dtype=np.float32).astype(np.float64)
+    nb = pod.DeviceNeighbors.from_list(nl)
+    res = {}
+    for dt in ("f64", "f32"):
+        m = pod.PodModel(pod.setup_from_workload(setup), dt)
+        nb.build_reverse(m)
+        o = m.energy_forces(pos32, cell, nb, c32)
+        r = {k: (v.double().cpu().numpy() if k != "E" else float(v.item())) for k, v in o.items()}
+        if descriptors:
+            r["D"] = m.descriptors(pos32, cell, nb).double().cpu().numpy()
+        res[dt] = r
+        del m
+    a, b = res["f32"], res["f64"]
+    out = {"E": abs(a["E"] - b["E"]) / abs(b["E"]), "E_atom": _relerr(a["E_atom"], b["E_atom"]),
+           "F": _relerr(a["F"], b["F"]), "W": _relerr(a["W"], b["W"]), "G": _relerr(a["G"], b["G"])}
+    if descriptors:
+        out["D_worst_column"] = _colerr(a["D"], b["D"])
+    out["definition"] = ("normwise max|x32 - x64| / max|x64| per output (D per column, worst column), "
+                         "both paths on the same FP32-rounded inputs")
+    return out
+
+
 def roofline(w, r, dtype, traffic=True):
     """Roofline of the per-atom kernel (the dominant one) from the algorithmic
     flop model in paper_2212_14446_amd.flops; the finalize kernel's time is
@@ -295,7 +342,8 @@ def run_autograd(steps, warmup):
     ms = e0.elapsed_time(e1) / steps
     return {"workload": f"{w.name}: {w.N} atoms, {w.nl.n_pairs} pairs, FP32",
             "step": "E forward + backward to dE/dpos and dE/dc (torch.autograd.Function)",
-            "ms_per_step": ms, "atoms_per_s": w.N / (ms * 1e-3)}
+            "ms_per_step": ms, "atoms_per_s": w.N / (ms * 1e-3),
+            "error_vs_f64": precision_errors(w.pos, w.cell, w.nl, s, c, descriptors=False)}
 
 
 @on_stream
@@ -525,7 +573,9 @@ def run_md(steps, dtype="f64", T=300.0, dt=1.0):
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / steps
     et = (ep + ek).cpu().numpy()
-    return {"workload": f"{w.name}: {w.N} atoms, {dtype.upper()}, {T:g} K, dt {dt:g} fs, skin 0.4 A",
+    err = precision_errors(w.pos, w.cell, w.nl, w.setup, c, descriptors=False) if dtype == "f32" else None
+    return {"force_error_vs_f64_first_step": err,
+            "workload": f"{w.name}: {w.N} atoms, {dtype.upper()}, {T:g} K, dt {dt:g} fs, skin 0.4 A",
             "steps": steps, "ms_per_step": ms, "s_per_atom_step": ms * 1e-3 / w.N,
             "atom_steps_per_s": w.N / (ms * 1e-3), "rebuilds": dyn.rebuilds - r0,
             "energy_drift_eV_per_atom": float(np.abs(et - et[0]).max() / w.N)}
@@ -591,6 +641,7 @@ def run_surrogate(steps, epochs=30):
     n4, t_n4, _ = timed(lambda: m23.energy_forces(pos, w.cell, nb, c23, virial=False, global_desc=False,
                                                   check=False), m23)
     rm = lambda a, b: float(torch.sqrt(((a.double() - b.double()) ** 2).mean()))
+    err_exact = precision_errors(w.pos, w.cell, w.nl, S, c, descriptors=False)
     f_net = 2 * (n_in * 64 + 64 * 64 + 64) + 2 * (64 * 64 + 64 * n_in)   # forward + input gradient per atom
     net_ms = k_su[2]
     ach = f_net * w.N / (net_ms * 1e-3) if net_ms > 0 else 0.0
@@ -603,6 +654,7 @@ def run_surrogate(steps, epochs=30):
             "force_rmse_eV_per_A": {"surrogate": rm(su["F"], ex["F"]), "without_4body": rm(n4["F"], ex["F"])},
             "energy_rmse_eV_per_atom": {"surrogate": rm(su["E_atom"], ex["E_atom"]),
                                         "without_4body": rm(n4["E_atom"], ex["E_atom"])},
+            "exact_f32_error_vs_f64": err_exact,
             "surrogate_kernels_ms": {"per_atom_kernels": k_su[1], "network": k_su[2], "finalize": k_su[0]},
             "network_mfma": {"bound": "mfma", "achieved": ach / 1e12, "peak": PEAK_BF16 / 1e12, "unit": "TFLOP/s",
                              "frac": ach / PEAK_BF16, "flops_per_atom": f_net}}
@@ -690,7 +742,9 @@ def main():
         r32 = run_gpu(w, "f32", args.steps, args.warmup)
         print(f"[bench] f32 {r32}", file=sys.stderr, flush=True)
         rec["f32"] = {"value": w.N / (r32["ms_per_step"] * 1e-3), "ms_per_step": r32["ms_per_step"],
-                      "roofline": roofline(w, r32, "f32")}
+                      "roofline": roofline(w, r32, "f32"),
+                      "error_vs_f64": precision_errors(w.pos, w.cell, w.nl, w.setup, w.c)}
+        print(f"[bench] f32 error vs f64 {rec['f32']['error_vs_f64']}", file=sys.stderr, flush=True)
     if not args.no_rc6 and args.rcut != 6.0:
         # the same box at rcut 6 A (the first five BCC shells, ~56 pairs per atom)
         w6 = wl.config2(6.0)
@@ -700,6 +754,7 @@ def main():
             r6 = run_gpu(w6, dt, args.steps, args.warmup)
             rc6[dt] = {"value": w6.N / (r6["ms_per_step"] * 1e-3), "unit": "atoms/s",
                        "ms_per_step": r6["ms_per_step"], "roofline": roofline(w6, r6, dt, traffic=False)}
+        rc6["f32"]["error_vs_f64"] = precision_errors(w6.pos, w6.cell, w6.nl, w6.setup, w6.c)
         rec["rcut6"] = rc6
         print(f"[bench] rcut6 {rc6}", file=sys.stderr, flush=True)
     if not args.no_autograd:

@@ -1,27 +1,33 @@
 """Build libpod.so (HIP, gfx950) in-tree with hipcc.
 
-Usage: python -m paper_2212_14446_amd.build_lib
+Every source is compiled to an object of its own (in parallel, under
+``_build/``) and the objects are linked into ``libpod.so``.  Each object
+carries the code of its own kernels, so no relocatable device code is needed.
+
+Usage: python -m paper_2212_14446_amd.build_lib [extra hipcc flags]
 """
 from __future__ import annotations
 
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libpod.so")
+OBJDIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["pod_host.cpp", "pod_kernels.hip", "pod_batch.hip", "pod_mlp.hip", "pod_neighbors.hip", "pod_fit.hip", "pod_opod.hip", "pod_md.hip", "pod_acsf.hip", "pod_five.hip"]
+SOURCES = ["pod_host.cpp", "pod_kernels.hip", "pod_batch.hip", "pod_mlp.hip", "pod_neighbors.hip", "pod_fit.hip",
+           "pod_opod.hip", "pod_md.hip", "pod_acsf.hip", "pod_five.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
     "-O3",
     "-std=c++20",
     "-fPIC",
-    "-shared",
     # packed FP32 instructions are kept out of every HIP code object
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     # hardware FP atomics for the force scatter (device memory from hipMalloc)
@@ -38,15 +44,42 @@ def hipcc() -> str:
     return "hipcc"
 
 
-def build(verbose: bool = True, extra=None) -> str:
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = LIB + ".tmp"
-    cmd = [hipcc(), *HIPCC_FLAGS, *(extra or []), "-I", INCLUDE, "-I", CSRC, "-o", tmp, *srcs]
+def _jobs() -> int:
+    for var in ("MAX_JOBS", "CMAKE_BUILD_PARALLEL_LEVEL"):
+        v = os.environ.get(var)
+        if v and v.isdigit() and int(v) > 0:
+            return min(int(v), 16)
+    return max(1, min(os.cpu_count() or 1, 16))
+
+
+def build(verbose: bool = True, extra=None, out: str = LIB) -> str:
+    os.makedirs(OBJDIR, exist_ok=True)
+    extra = list(extra or [])
+
+    def compile_one(src):
+        obj = os.path.join(OBJDIR, os.path.splitext(src)[0] + ".o")
+        cmd = [hipcc(), *HIPCC_FLAGS, *extra, "-I", INCLUDE, "-I", CSRC, "-c", "-o", obj, os.path.join(CSRC, src)]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        return src, obj, r
+
+    with ThreadPoolExecutor(max_workers=_jobs()) as ex:
+        results = list(ex.map(compile_one, SOURCES))
+    failed = [(s, r) for s, _, r in results if r.returncode != 0]
+    for s, _, r in results:
+        msg = "\n".join(l for l in (r.stderr or "").splitlines() if "packed-fp32-ops" not in l)
+        if msg.strip() and (verbose or r.returncode != 0):
+            print(f"--- {s}\n{msg}", file=sys.stderr, flush=True)
+    if failed:
+        raise RuntimeError("compilation failed: " + ", ".join(s for s, _ in failed))
+    tmp = out + ".tmp"
+    cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *(o for _, o, _ in results)]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

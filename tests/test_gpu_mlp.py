@@ -121,14 +121,53 @@ def test_mlp_train_step_deterministic():
     assert np.array_equal(out[0], out[1])
 
 
+def _oracle_fit(theta, X, target, epochs, batch, lr, seed, lr_min=1e-4):
+    """The training schedule of surrogate.fit written out on the FP64 network
+    oracle (same bfloat16 rounding points): the FP32-rounded inputs, the
+    same standardisation, the same minibatch permutations (torch's CPU
+    generator with the same seed), Adam with the same cosine decay.
+    Returns the loss of every epoch's last batch."""
+    import math
+
+    import torch
+    n = X.shape[0]
+    f32 = lambda a: np.asarray(a, dtype=np.float32).astype(np.float64)
+    X = f32(X)
+    mu = f32(X.mean(0))
+    isg = f32(1.0 / X.std(0, ddof=1))
+    t = f32(target)
+    ts = f32((t - t.mean()) / t.std(ddof=1))
+    gen = torch.Generator(device="cpu")
+    gen.manual_seed(seed)
+    spe = max(1, n // batch)
+    total = epochs * spe
+    th, m, v = f32(theta), np.zeros_like(theta), np.zeros_like(theta)
+    hist, k = [], 0
+    for _ in range(epochs):
+        perm = torch.randperm(n, generator=gen).numpy()
+        for s in range(spe):
+            idx = perm[s * batch:(s + 1) * batch]
+            k += 1
+            cur = lr_min + 0.5 * (lr - lr_min) * (1.0 + math.cos(math.pi * (k - 1) / max(total - 1, 1)))
+            loss, g = mo.loss_and_grad(th, X[idx], ts[idx], mu, isg)
+            th, m, v = mo.adam_step(th, m, v, g, k, cur)
+        hist.append(loss)
+    return hist
+
+
 def test_mlp_training_reduces_loss():
-    """A teacher network labels random inputs; the student's loss falls."""
+    """A teacher network labels random inputs and a student is trained on
+    them by the device kernels.  The expectation is the oracle's own
+    training run on the same minibatches (it ends at ~0.11 of the untrained
+    loss after 15 epochs on this problem): the device's loss must track it
+    epoch by epoch, and the trained student must fit the teacher."""
     import torch
     n, n_in = 20000, 36
     teacher, X, mu, isg = rand_case(n, n_in, 11)
     y_t, _ = mo.input_gradient(teacher, X, mu, isg, bf16=False)
     m = handle("f32")
     net = surrogate.Network(n_in, seed=3)
+    theta0 = net.theta.double().cpu().numpy()
     Xt = torch.tensor(X, dtype=torch.float32, device="cuda")
     tt = torch.tensor(y_t, dtype=torch.float32, device="cuda")
     # loss of the untrained network in the standardised units fit() uses
@@ -137,13 +176,15 @@ def test_mlp_training_reduces_loss():
     ts = (y_t - y_t.mean()) / y_t.std()
     loss0 = float(np.mean((y0.double().cpu().numpy() - ts) ** 2))
     hist = surrogate.fit(m.h, net, Xt, tt, epochs=15, batch=1024, lr=3e-3, seed=4)
+    ref = _oracle_fit(theta0, X, y_t, epochs=15, batch=1024, lr=3e-3, seed=4)
     y, _ = net.forward(m.h, Xt)
     r = y.double().cpu().numpy() - y_t
     rmse = np.sqrt(np.mean(r ** 2))
-    say(f"[gpu] training loss: untrained {loss0:.3e}, by epoch {hist[0]:.3e} ... {hist[-1]:.3e}; "
-        f"rmse/std {rmse / np.std(y_t):.3f}")
-    assert hist[-1] < 0.25 * loss0
-    assert all(b <= 1.2 * a for a, b in zip(hist, hist[1:]))     # no divergence
+    dev = max(abs(a - b) / b for a, b in zip(hist, ref))
+    say(f"[gpu] training loss: untrained {loss0:.3e}; device {hist[0]:.4e} ... {hist[-1]:.4e}; "
+        f"oracle {ref[0]:.4e} ... {ref[-1]:.4e}; worst epoch deviation {dev:.2e}; rmse/std {rmse / np.std(y_t):.3f}")
+    assert ref[-1] < 0.15 * loss0          # what 15 epochs reach on this problem
+    assert dev < 0.05                       # the device follows the oracle's trajectory
     assert rmse < 0.5 * np.std(y_t)
 
 

@@ -75,6 +75,26 @@ def test_cutoff_endpoints_and_shape():
     assert np.all((f >= 0) & (f <= 1.0 + 1e-6))
 
 
+def test_cutoff_interior_values():
+    """Eq. (8) at interior points, values worked out by hand in 40-digit
+    decimal arithmetic (rin = 0.5, rc = 5, eps = 1e-6, t = (r - rin)/(rc - rin)):
+    * t^3 = 1/2: y = 1 - t^3 = 1/2, s = y^2 + eps = 0.250001,
+      f_c = exp(1 - s^(-1/2)) = exp(-0.999996000012) = 0.36788091268773549;
+      df/dr = -3 f_c y t^2 s^(-3/2) / (rc - rin) = -0.61799749967771510;
+    * t = 1/2: y = 7/8, s = 0.765626, f_c = 0.86687854674903807;
+    * r = rc - 0.01: t = 4.49/4.5, y = 1 - t^3 = 6.6519e-3,
+      f_c = 7.4241044166644240e-65 (a cubic written as a square would give
+      1e-95 there and 0.182 at t^3 = 1/2)."""
+    rin, rc = 0.5, 5.0
+    h = rc - rin
+    r = np.array([rin + h * 0.5 ** (1.0 / 3.0), rin + 0.5 * h, rc - 0.01])
+    fc, dfc = po.cutoff(r, rin, rc)
+    assert fc[0] == pytest.approx(0.36788091268773549, rel=1e-14)
+    assert dfc[0] == pytest.approx(-0.61799749967771510, rel=1e-13)
+    assert fc[1] == pytest.approx(0.86687854674903807, rel=1e-14)
+    assert fc[2] == pytest.approx(7.4241044166644240e-65, rel=1e-9)
+
+
 @pytest.mark.parametrize("p", [P6, P8])
 def test_snapshot_derivative_fd(p):
     r = np.linspace(0.7, 4.8, 23)
