@@ -52,10 +52,11 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def committed_traffic(dtype):
-    """HBM bytes per launch of the per-atom kernel from the committed counter
-    summary, if it was taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", "traffic_atom_kernel_bcc20_15840.md")
+def committed_traffic(dtype, kernel="atom_kernel"):
+    """HBM bytes per launch of one kernel of the energy path from the
+    committed counter summary, if it was taken on the current kernel source;
+    else None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_bcc20_15840.md")
     if not os.path.exists(path):
         return None
     vals = {}
@@ -133,10 +134,12 @@ def run_gpu(w, dtype, steps, warmup):
     total_ms = timed_pass(False)
     ev_ms = timed_pass(True)
     kms, kn = pod.pod_get_kernel_time(m.h, 1)
+    gms, gn = pod.pod_get_kernel_time(m.h, 4)
     pms, pn = pod.pod_get_kernel_time(m.h, 0)
     pod.pod_set_kernel_timing(m.h, 0)
     m.check()
     return {"ms_per_step": total_ms / steps, "kernel_ms": kms / max(kn, 1), "kernel_launches": kn,
+            "pair_kernel_ms": gms / max(gn, 1), "pair_kernel_launches": gn,
             "finalize_kernel_ms": pms / max(pn, 1), "ms_per_step_with_kernel_events": ev_ms / steps,
             "E": float(out["E"].item())}
 
@@ -189,26 +192,34 @@ def precision_errors(pos, cell, nl, setup, c, descriptors=True):
 
 
 def roofline(w, r, dtype, traffic=True):
-    """Roofline of the per-atom kernel (the dominant one) from the algorithmic
-    flop model in paper_2212_14446_amd.flops; the finalize kernel's time is
-    reported beside it."""
+    """Roofline of the energy path's two main kernels from the algorithmic
+    flop model in paper_2212_14446_amd.flops: the per-atom kernel (radial
+    basis and R, atomic basis, contractions, energy, adjoint rows) and the
+    pair kernel (R', monomials, pair gradients, virial).  The headline
+    object is the dominant (longer) kernel; both are listed, with the
+    finalize kernel's time beside them."""
     from paper_2212_14446_amd import flops as fl
     s = w.setup
     K = max(s.K2, s.K3, s.K4)
     PA = max(s.P3 if s.K3 else 0, s.P4 if s.K4 else 0)
-    cnt = fl.counts(K, s.L, PA, s.P4)
-    # the per-atom kernel evaluates the radial basis twice (forward, and with
-    # derivatives in the backward): counted once, as the algorithm needs it once
-    f_atom = ((cnt["radial_per_pair"] + cnt["forward_per_pair"] + cnt["backward_per_pair"]) * w.nl.n_pairs
-              + cnt["per_atom"] * w.N)
+    sp = fl.split_counts(K, s.L, PA, s.P4)
+    P, N = w.nl.n_pairs, w.N
+    f_atom = sp["atom_per_pair"] * P + sp["per_atom"] * N
+    f_pair = sp["pair_per_pair"] * P
     peak = PEAK_F64 if dtype == "f64" else PEAK_F32
-    achieved = f_atom / (r["kernel_ms"] * 1e-3)
-    tr = committed_traffic(dtype) if traffic else None
+    legs = {"atom_kernel": (f_atom, r["kernel_ms"]), "pair_kernel": (f_pair, r["pair_kernel_ms"])}
+    dom = max(legs, key=lambda k: legs[k][1])
+    f_dom, t_dom = legs[dom]
+    achieved = f_dom / (t_dom * 1e-3)
+    tr = committed_traffic(dtype, dom) if traffic else None
+    both = (f_atom + f_pair) / ((r["kernel_ms"] + r["pair_kernel_ms"]) * 1e-3)
     return {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
             "frac": achieved / peak, "traffic": tr,
-            "hbm_GBps": (tr / (r["kernel_ms"] * 1e-3) / 1e9) if tr else None, "hbm_peak_GBps": 8000.0,
-            "kernel": "atom_kernel (E+F)",
-            "kernel_ms": r["kernel_ms"], "flops_per_launch": f_atom,
+            "hbm_GBps": (tr / (t_dom * 1e-3) / 1e9) if tr else None, "hbm_peak_GBps": 8000.0,
+            "kernel": dom, "kernel_ms": t_dom, "flops_per_launch": f_dom,
+            "kernels": {k: {"ms": t, "flops_per_launch": f, "achieved_TFLOPs": f / (t * 1e-3) / 1e12 if t else None,
+                            "frac": f / (t * 1e-3) / peak if t else None} for k, (f, t) in legs.items()},
+            "two_kernels_frac": both / peak,
             "finalize_kernel_ms": r["finalize_kernel_ms"],
             "kernel_timing": f"HIP events around each launch on the library stream, second pass of the same "
                              f"steps ({r['ms_per_step_with_kernel_events']:.4f} ms/step with the events)"}
@@ -629,7 +640,7 @@ def run_surrogate(steps, epochs=30):
             fn()
         e1.record()
         torch.cuda.synchronize()
-        kt = {k: pod.pod_get_kernel_time(model.h, k) for k in (0, 1, 2)}
+        kt = {k: pod.pod_get_kernel_time(model.h, k) for k in (0, 1, 2, 4)}
         pod.pod_set_kernel_timing(model.h, 0)
         model.check()
         return o, e0.elapsed_time(e1) / steps, {k: (v[0] / v[1] if v[1] else 0.0) for k, v in kt.items()}
@@ -655,7 +666,8 @@ def run_surrogate(steps, epochs=30):
             "energy_rmse_eV_per_atom": {"surrogate": rm(su["E_atom"], ex["E_atom"]),
                                         "without_4body": rm(n4["E_atom"], ex["E_atom"])},
             "exact_f32_error_vs_f64": err_exact,
-            "surrogate_kernels_ms": {"per_atom_kernels": k_su[1], "network": k_su[2], "finalize": k_su[0]},
+            "surrogate_kernels_ms": {"per_atom_kernels": k_su[1], "pair_kernel": k_su[4], "network": k_su[2],
+                                     "finalize": k_su[0]},
             "network_mfma": {"bound": "mfma", "achieved": ach / 1e12, "peak": PEAK_BF16 / 1e12, "unit": "TFLOP/s",
                              "frac": ach / PEAK_BF16, "flops_per_atom": f_net}}
 

@@ -456,12 +456,13 @@ void pod_acsf_free(pod_acsf* a);
  * of their kernels (n = 0 switches recording off).  pod_get_kernel_time waits
  * for the stream and returns the summed elapsed time (ms) and the number of
  * recorded launches of one kernel -- kind 1: the per-atom kernel (radial
- * basis, atomic basis, contractions, energy, adjoint, per-pair gradients)
- * and the batched-assembly kernel; kind 0: the finalize kernel (totals E, W,
- * G and the force copy-out); kind 2: the network kernels; kind 3: the Gram
- * kernels of pod_fit_gram; for the symmetry functions, kind 1 times the
- * basis kernels and kind 0 the pair-gradient and gather kernels -- then
- * resets that count. */
+ * basis, atomic basis, contractions, energy, adjoint rows) and the
+ * batched-assembly kernel; kind 4: the pair-gradient kernel of the energy
+ * calls (per-pair gradients, own-atom sums, virial); kind 0: the finalize
+ * kernel (totals E, W, G and the force gather or copy-out); kind 2: the
+ * network kernels; kind 3: the Gram kernels of pod_fit_gram; for the
+ * symmetry functions, kind 1 times the basis kernels and kind 0 the
+ * pair-gradient and gather kernels -- then resets that count. */
 int pod_set_kernel_timing(pod_handle* h, int n);
 int pod_get_kernel_time(pod_handle* h, int kind, double* total_ms, int* launches);
 

@@ -35,15 +35,82 @@ template <> __device__ __forceinline__ void d_sincos(double x, double* s, double
 template <> __device__ __forceinline__ void d_sincos(float x, float* s, float* c) { sincosf(x, s, c); }
 template <typename T> __device__ __forceinline__ bool d_finite(T x) { return isfinite(x); }
 
+// Ordering point for a workgroup of one wavefront.  A wavefront performs its
+// LDS accesses in program order, so lanes see each other's LDS writes once
+// the compiler keeps the accesses on their side of this point; unlike a
+// workgroup barrier it does not wait for outstanding global-memory loads.
+__device__ __forceinline__ void wave_sync() { __builtin_amdgcn_wave_barrier(); }
+
+__device__ __forceinline__ int wave_or(int v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v |= __shfl_xor(v, o);
+    return v;
+}
 __device__ __forceinline__ int wave_max(int v) {
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = min(v, __shfl_xor(v, o));
     return v;
 }
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
     return v;
+}
+
+// Sums of nine values over the 64 lanes of a wavefront, in a fixed order:
+// halving exchanges in which each lane keeps half of the values it still
+// carries (a transposed reduction: 17 exchanges instead of 54).  Returns
+// the sum of value c in lane 4 c (c = 0..8); other lanes get c >= 9.
+__device__ __forceinline__ double wave_sum9(const double (&v)[9], int lane, int& c) {
+    double a[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) a[i] = i < 9 ? v[i] : 0.0;
+    // xor 32: lanes < 32 keep values 0..7, lanes >= 32 keep 8..15
+    const bool hi32 = (lane & 32) != 0;
+    double b[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const double send = hi32 ? a[i] : a[i + 8];
+        const double recv = __shfl_xor(send, 32);
+        b[i] = (hi32 ? a[i + 8] : a[i]) + recv;
+    }
+    // xor 16: keep 4
+    const bool hi16 = (lane & 16) != 0;
+    double e[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const double send = hi16 ? b[i] : b[i + 4];
+        const double recv = __shfl_xor(send, 16);
+        e[i] = (hi16 ? b[i + 4] : b[i]) + recv;
+    }
+    // xor 8: keep 2
+    const bool hi8 = (lane & 8) != 0;
+    double f[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const double send = hi8 ? e[i] : e[i + 2];
+        const double recv = __shfl_xor(send, 8);
+        f[i] = (hi8 ? e[i + 2] : e[i]) + recv;
+    }
+    // xor 4: keep 1
+    const bool hi4 = (lane & 4) != 0;
+    double t;
+    {
+        const double send = hi4 ? f[0] : f[1];
+        const double recv = __shfl_xor(send, 4);
+        t = (hi4 ? f[1] : f[0]) + recv;
+    }
+    t += __shfl_xor(t, 2);
+    t += __shfl_xor(t, 1);
+    // lane bits 5, 4, 3, 2 chose halves 8, 4, 2, 1 of the 16 values
+    const int idx = (hi32 ? 8 : 0) + (hi16 ? 4 : 0) + (hi8 ? 2 : 0) + (hi4 ? 1 : 0);
+    c = (lane & 3) == 0 ? idx : 16;
+    return t;
 }
 
 __device__ __forceinline__ int unpack_shift(int sh, int d) {
@@ -182,7 +249,8 @@ __device__ __forceinline__ void sincospi_unit(T x, T* sp, T* cp) {
 // Radial functions for the standard snapshot family (Bessel alpha = 1..nb at
 // one beta, inverse powers gamma = 1..ni): one expm1, one sincos and one exp
 // per pair; sin/cos(alpha pi x) by angle addition; Q read from LDS.
-template <typename T, bool DERIV>
+// KR: number of radial functions to form (the others are left zero).
+template <typename T, bool DERIV, int KR = POD_MAX_K>
 __device__ __forceinline__ void radial_std(const ParamsT<T>* __restrict__ P, const T* __restrict__ sQ, T r,
                                            T rinv, T (&R)[POD_MAX_K], T (&dR)[POD_MAX_K]) {
     const T inv_h = P->inv_h;
@@ -224,7 +292,7 @@ __device__ __forceinline__ void radial_std(const ParamsT<T>* __restrict__ P, con
             const T dph = DERIV ? dfci * sk + fci * (T(l + 1) * pdx * ck - sk * idist) : T(0);
             const T* q = sQ + l * POD_MAX_K;
 #pragma unroll
-            for (int k = 0; k < POD_MAX_K; ++k) {
+            for (int k = 0; k < KR; ++k) {
                 R[k] += q[k] * ph;
                 if (DERIV) dR[k] += q[k] * dph;
             }
@@ -237,7 +305,7 @@ __device__ __forceinline__ void radial_std(const ParamsT<T>* __restrict__ P, con
         const T dph = DERIV ? (dfc - T(g) * fc * rinv) * pw : T(0);
         const T* q = sQ + (nb + g - 1) * POD_MAX_K;
 #pragma unroll
-        for (int k = 0; k < POD_MAX_K; ++k) {
+        for (int k = 0; k < KR; ++k) {
             R[k] += q[k] * ph;
             if (DERIV) dR[k] += q[k] * dph;
         }

@@ -17,8 +17,9 @@ constexpr int ERR_NONFINITE = 2;
 constexpr int ERR_NEIGH = 4;
 constexpr int ERR_SINGULAR = 8;   // fit matrix not positive definite
 
-// Kernel kinds with their own timing events.
-constexpr int TIMING_KINDS = 4;
+// Kernel kinds with their own timing events: 0 finalize kernels, 1 per-atom
+// and batch kernels, 2 network, 3 fit Gram, 4 pair-gradient kernel.
+constexpr int TIMING_KINDS = 5;
 
 // One snapshot tuple as the kernels evaluate it (Sec. II.B, eqs. (3)-(6)).
 //   bessel  : kappa != 0; phi = sin(alpha pi x)/(r - rin)
@@ -87,7 +88,7 @@ struct pod_handle {
     void* d_mscratch;          // network outputs and gradient partials (separate from d_scratch,
     size_t mscratch_bytes;     // which the energy kernels reuse within one call)
     // kernel timing per kernel kind (0 finalize, 1 per-atom and batch, 2 network,
-    // 3 fit Gram), 2 events per launch
+    // 3 fit Gram, 4 pair gradients), 2 events per launch
     std::vector<hipEvent_t> ev[pod::TIMING_KINDS];
     int ev_used[pod::TIMING_KINDS];
 };

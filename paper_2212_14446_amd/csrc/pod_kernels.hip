@@ -49,13 +49,12 @@ struct KArgs {
     const T* coef;     // energy coefficients (mode 1)
     T* D;              // descriptors (mode 0)
     T* E_atom;         // per-atom energy or null (mode 1)
-    double* Facc;      // force accumulator (3N, zero on entry) (mode 1, backward, no gbuf)
-    T* gbuf;           // gather path: g_ij stored at the reverse slot rev[p] (3P)
-    double* fown;      // gather path: own-atom force sum_j g_ij (3N)
-    const int* rev;    // reverse-pair index (gather path)
+    T* abar;           // adjoint rows dE_i/dB_i, [N][K][NA] (forces or virial requested)
+    int* centre;       // centre atom of every pair, for the pair kernel
+    T* pdv;            // pair vectors r_ij of every pair (zero when not a neighbour), for the pair kernel
     double* part;      // block partials, column-major [10 + M][nblk] (mode 1)
     int want_G;        // block partials of G requested
-    int want_back;     // run the backward sweep (forces or virial requested)
+    int want_back;     // adjoint rows requested (forces or virial)
     const float* y_net;  // mode 2: per-atom network energy (N)
     const float* g_net;  // mode 2: per-atom dy/dD for descriptor columns 1.. (N x n_net)
     int n_net;
@@ -68,40 +67,40 @@ struct KArgs {
 struct SlotIdx {
     int j;    // neighbour index, -1 for an empty slot
     int sh;   // packed image shift
-    int rv;   // reverse pair (gather path), -1 otherwise
 };
 
-template <typename T>
-__device__ __forceinline__ SlotIdx slot_index(const KArgs<T>& g, bool valid, int p) {
+// The loads of a slot are issued on every lane (an empty slot reads entry 0,
+// which exists whenever the list is not empty): with a fixed number of
+// loads per round the compiler can wait for exactly the ones a round needs
+// and leave the prefetched ones in flight.
+template <typename A>
+__device__ __forceinline__ SlotIdx slot_index(const A& g, bool valid, int p) {
+    const int pc = valid ? p : 0;
     SlotIdx s;
-    s.j = -1; s.sh = 0; s.rv = -1;
-    if (valid) {
-        s.j = g.nbr_j[p]; s.sh = g.shift[p];
-        if (g.rev) s.rv = g.rev[p];
-    }
+    s.j = g.nbr_j[pc];
+    s.sh = g.shift[pc];
+    if (!valid) { s.j = -1; s.sh = 0; }
     return s;
 }
 
-template <typename T>
-__device__ __forceinline__ void slot_pos(const KArgs<T>& g, const SlotIdx& s, T (&pj)[3]) {
-    pj[0] = pj[1] = pj[2] = T(0);
-    if (s.j >= 0 && s.j < g.N) {
-        pj[0] = g.pos[3 * s.j + 0];
-        pj[1] = g.pos[3 * s.j + 1];
-        pj[2] = g.pos[3 * s.j + 2];
-    }
+template <typename T, typename A>
+__device__ __forceinline__ void slot_pos(const A& g, const SlotIdx& s, T (&pj)[3]) {
+    const int jc = (s.j >= 0 && s.j < g.N) ? s.j : 0;
+    pj[0] = g.pos[3 * jc + 0];
+    pj[1] = g.pos[3 * jc + 1];
+    pj[2] = g.pos[3 * jc + 2];
 }
 
 // r_ij = r_j + n.cell - r_i, |r_ij| and validity of one fetched slot.  Data
-// errors are latched in the error word when `report` is set.
-template <typename T>
-__device__ __forceinline__ bool slot_geometry(const KArgs<T>& g, bool valid, const SlotIdx& s, const T (&pj)[3],
-                                              const T (&pi)[3], bool report, T (&d)[3], T& r) {
+// errors are collected in `eb` (error-word bits).
+template <typename T, typename A>
+__device__ __forceinline__ bool slot_geometry(const A& g, bool valid, const SlotIdx& s, const T (&pj)[3],
+                                              const T (&pi)[3], int& eb, T (&d)[3], T& r) {
     d[0] = d[1] = d[2] = T(0);
     r = T(0.5) * (g.prm.rin + g.prm.rcut);
     if (!valid) return false;
     if (s.j < 0 || s.j >= g.N || (!g.cell.periodic && (s.sh & 0xFFFFFF) != 0)) {
-        if (report) atomicOr(g.err, ERR_NEIGH);
+        eb |= ERR_NEIGH;
         return false;
     }
     const T sx = T(unpack_shift(s.sh, 0)), sy = T(unpack_shift(s.sh, 1)), sz = T(unpack_shift(s.sh, 2));
@@ -111,12 +110,12 @@ __device__ __forceinline__ bool slot_geometry(const KArgs<T>& g, bool valid, con
     const T d2 = pj[2] - pi[2] + sx * a[2] + sy * a[5] + sz * a[8];
     const T r2 = d0 * d0 + d1 * d1 + d2 * d2;
     if (!d_finite(r2)) {
-        if (report) atomicOr(g.err, ERR_NONFINITE);
+        eb |= ERR_NONFINITE;
         return false;
     }
     const T rr = d_sqrt(r2);
     if (rr <= g.prm.rin) {
-        if (report) atomicOr(g.err, ERR_RANGE);
+        eb |= ERR_RANGE;
         return false;
     }
     if (rr >= g.prm.rcut) return false;   // not a neighbour (Sec. II.A): no contribution
@@ -125,34 +124,46 @@ __device__ __forceinline__ bool slot_geometry(const KArgs<T>& g, bool valid, con
     return true;
 }
 
-template <typename T, bool DERIV, bool FAST>
+// KR: radial functions formed on the standard-family path (K when it is
+// fixed at compile time, else all POD_MAX_K, zero beyond K).
+template <typename T, bool DERIV, bool FAST, int KR = POD_MAX_K>
 __device__ __forceinline__ void radial_any(const ParamsT<T>* __restrict__ P, const T* sQ, T r, T rinv,
                                            T (&R)[POD_MAX_K], T (&dR)[POD_MAX_K]) {
-    if constexpr (FAST) radial_std<T, DERIV>(P, sQ, r, rinv, R, dR);
+    if constexpr (FAST) radial_std<T, DERIV, KR>(P, sQ, r, rinv, R, dR);
     else radial<T, DERIV>(P, r, rinv, R, dR);
 }
 
 // LDS layout of atom_kernel (per 64-lane workgroup), in bytes:
-//   [Q (L x POD_MAX_K)] [per-lane double scratch (max(64, M), 3 x 64)]
-//   [T area: union { round staging [64][stage_stride(K)], adjoint rows [APW][K][NA | 1] }]
+//   [per-lane double scratch (max(64, M))]
+//   [T area: union { round staging [64][stage_stride(K)], G staging
+//    [2 + PA + KA][64] doubles, adjoint rows [APW][K][NA] }]
+// Per-atom stride of the adjoint rows in memory and LDS, in elements: K * NA
+// rounded up to a multiple of 16 bytes (the direct loads into LDS move 16
+// bytes per lane).
+__host__ __device__ constexpr int abar_stride(int K, int NA, int tsize) {
+    return ((K * NA * tsize + 15) / 16 * 16) / tsize;
+}
+
 __host__ __device__ constexpr int stage_stride(int K) { return (3 + K) | 1; }
 __host__ __device__ constexpr int odd_len(int n) { return n | 1; }
 
 struct AtomLds {
-    size_t off_q, off_e, off_f, off_t, total;
+    size_t off_e, off_t, total;
 };
 
-__host__ __device__ inline AtomLds atom_lds_layout(int K, int NA, int M, size_t tsize) {
+__host__ __device__ inline AtomLds atom_lds_layout(int K, int NA, int M, size_t tsize, int KA, int PA) {
     const int apw = WAVE / K;
     AtomLds L;
-    L.off_q = 0;
-    L.off_e = ((static_cast<size_t>(POD_MAX_L) * POD_MAX_K * tsize + 15) / 16) * 16;
+    L.off_e = 0;
     const size_t ne = static_cast<size_t>(M > WAVE ? M : WAVE);
-    L.off_f = L.off_e + ((ne * sizeof(double) + 15) / 16) * 16;
-    L.off_t = L.off_f + static_cast<size_t>(3) * WAVE * sizeof(double);
+    L.off_t = L.off_e + ((ne * sizeof(double) + 15) / 16) * 16;
     const size_t stage = static_cast<size_t>(WAVE) * stage_stride(K) * tsize;
-    const size_t adj = static_cast<size_t>(apw) * K * odd_len(NA) * tsize;
-    L.total = L.off_t + (stage > adj ? stage : adj);
+    const size_t adj = static_cast<size_t>(apw) * abar_stride(K, NA, static_cast<int>(tsize)) * tsize;
+    // G staging: [1 + (PA + 1) + KA][64] doubles
+    const size_t gst = static_cast<size_t>(2 + PA + KA) * WAVE * sizeof(double);
+    size_t t = stage > adj ? stage : adj;
+    t = t > gst ? t : gst;
+    L.total = L.off_t + t;
     return L;
 }
 
@@ -160,67 +171,6 @@ __host__ __device__ inline AtomLds atom_lds_layout(int K, int NA, int M, size_t 
 // (eq. (24c)): d/dr [R_k(r) h_k(rhat)] = R'_k h_k rhat + R_k (grad_u h_k -
 // (rhat . grad_u h_k) rhat) / r with h_k = sum_mu Abar_{k mu} A_mu, and
 // rhat . grad_u h = sum_n n h_n over the degree-n parts (Euler).
-//
-// pair_gradient_k contracts over the radial index first, for a K fixed at
-// compile time: W1_mu = sum_k Abar_{k mu} R'_k, W2_mu = sum_k Abar_{k mu} R_k,
-// then g = (sum_mu W1_mu A_mu - sum_n n H_n / r) rhat + (1/r) sum_mu W2_mu
-// grad A_mu with H_n = sum_{deg mu = n} W2_mu A_mu: 2 K + ~3 FMAs per
-// monomial instead of ~3 K.
-//
-// Each monomial is its own basic block, entered under a condition the
-// compiler cannot fold (an SGPR set to 1 by an s_mov_b32): within one block
-// the code generator would otherwise issue all K * NA reads of the adjoint
-// rows before the first FMA and spill them.  The K values of monomial mu + 1
-// are read at the top of the block that contracts monomial mu.
-template <typename T, int PA, int KK>
-__device__ __forceinline__ void pair_gradient_k(const T* __restrict__ abr, const T (&A)[n_mono(PA)],
-                                                const T (&R)[POD_MAX_K], const T (&dR)[POD_MAX_K], T ri, T ux,
-                                                T uy, T uz, T& gx, T& gy, T& gz) {
-    constexpr MonoTable<PA> mt{};
-    constexpr int NA = n_mono(PA);
-    constexpr int NAP = odd_len(NA);
-    T s1 = 0;
-    T hd[PA + 1];
-    T gp[3][PA + 1];   // gradient sums grouped by the exponent being lowered
-#pragma unroll
-    for (int n = 0; n <= PA; ++n) { hd[n] = 0; gp[0][n] = 0; gp[1][n] = 0; gp[2][n] = 0; }
-    T buf[2][KK];      // double buffer: values of monomial mu in buf[mu & 1]
-#pragma unroll
-    for (int k = 0; k < KK; ++k) buf[0][k] = abr[k * NAP];
-#pragma unroll
-    for (int mu = 0; mu < NA; ++mu) {
-        int on;
-        asm volatile("s_mov_b32 %0, 1" : "=s"(on));
-        if (on) {
-            const int cb = mu & 1;
-            if (mu + 1 < NA) {
-#pragma unroll
-                for (int k = 0; k < KK; ++k) buf[cb ^ 1][k] = abr[k * NAP + mu + 1];
-            }
-            T w1 = 0, w2 = 0;
-#pragma unroll
-            for (int k = 0; k < KK; ++k) {
-                w1 += buf[cb][k] * dR[k];
-                w2 += buf[cb][k] * R[k];
-            }
-            s1 += w1 * A[mu];
-            hd[mt.deg[mu]] += w2 * A[mu];
-#pragma unroll
-            for (int dd = 0; dd < 3; ++dd)
-                if (mt.down[mu][dd] >= 0) gp[dd][mt.ex[mu][dd]] += w2 * A[mt.down[mu][dd]];
-        }
-    }
-    T eul = 0, g0 = 0, g1 = 0, g2 = 0;
-#pragma unroll
-    for (int n = 1; n <= PA; ++n) {
-        eul += T(n) * hd[n];
-        g0 += T(n) * gp[0][n]; g1 += T(n) * gp[1][n]; g2 += T(n) * gp[2][n];
-    }
-    const T a1 = s1 - eul * ri;
-    gx = a1 * ux + ri * g0;
-    gy = a1 * uy + ri * g1;
-    gz = a1 * uz + ri * g2;
-}
 
 // The same for any K: one pass over the monomials per radial function.
 template <typename T, int PA>
@@ -229,7 +179,7 @@ __device__ __forceinline__ void pair_gradient_any(const T* __restrict__ abr, int
                                                   T uy, T uz, T& gx, T& gy, T& gz) {
     constexpr MonoTable<PA> mt{};
     constexpr int NA = n_mono(PA);
-    constexpr int NAP = odd_len(NA);
+    constexpr int NAP = NA;    // rows of one atom are contiguous
     gx = 0; gy = 0; gz = 0;
 #pragma unroll
     for (int k = 0; k < POD_MAX_K; ++k) {
@@ -277,6 +227,7 @@ __device__ __forceinline__ void atom_body(const KArgs<T>& g) {
     const int K = P->K;
     const int M = P->M;
     const int SS = stage_stride(K);
+    const int AST = abar_stride(K, NA, sizeof(T));   // per-atom stride of the adjoint rows
     const int lane = threadIdx.x;
     const int apw = WAVE / K;
     const int al = lane / K;
@@ -286,66 +237,73 @@ __device__ __forceinline__ void atom_body(const KArgs<T>& g) {
     const bool act = (al < apw) && (atom < g.N);
 
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const AtomLds LY = atom_lds_layout(K, NA, M, sizeof(T));
-    T* sQ = reinterpret_cast<T*>(smem_raw + LY.off_q);
+    const AtomLds LY = atom_lds_layout(K, NA, M, sizeof(T), KA, PA);
     double* sE = reinterpret_cast<double*>(smem_raw + LY.off_e);
-    double* sF = reinterpret_cast<double*>(smem_raw + LY.off_f);
     T* sT = reinterpret_cast<T*>(smem_raw + LY.off_t);
 
-    if (FAST)
-        for (int i = lane; i < POD_MAX_L * POD_MAX_K; i += WAVE) sQ[i] = (&P->Q[0][0])[i];
-
     int beg = 0, cnt = 0;
+    int eb = 0;                         // error-word bits found by this lane
     if (act) {
         const int b = g.offsets[atom], e = g.offsets[atom + 1];
-        if (b < 0 || e < b || e > g.P) {
-            if (q == 0) atomicOr(g.err, ERR_NEIGH);
-        } else {
-            beg = b; cnt = e - b;
-        }
+        if (b < 0 || e < b || e > g.P) eb |= ERR_NEIGH;
+        else { beg = b; cnt = e - b; }
     }
     const int nround = (wave_max(cnt) + K - 1) / K;
     T pi[3] = {T(0), T(0), T(0)};
     if (act) { pi[0] = g.pos[3 * atom + 0]; pi[1] = g.pos[3 * atom + 1]; pi[2] = g.pos[3 * atom + 2]; }
-    __syncthreads();
 
     // ---------------- forward: atomic basis row B_{i, m, .} (eq. (24b)) ----------------
     T acc[NA];
 #pragma unroll
     for (int mu = 0; mu < NA; ++mu) acc[mu] = 0;
-    SlotIdx i0 = slot_index(g, act && q < cnt, beg + q);
-    T p0[3];
-    slot_pos(g, i0, p0);
-    SlotIdx i1 = slot_index(g, act && K + q < cnt, beg + K + q);
-    for (int rd = 0; rd < nround; ++rd) {
-        {
-            // pair stage: rhat and R_k of slot rd*K + q, staged for the atom's K lanes
-            const int slot = rd * K + q;
-            const SlotIdx ic = i0;
-            T pc[3] = {p0[0], p0[1], p0[2]};
-            slot_pos(g, i1, p0);
-            i0 = i1;
-            i1 = slot_index(g, act && slot + 2 * K < cnt, beg + slot + 2 * K);
-            T d[3], r;
-            const bool ok = slot_geometry<T>(g, act && slot < cnt, ic, pc, pi, true, d, r);
-            const T rinv = T(1) / r;
-            T R[POD_MAX_K], dR[POD_MAX_K];
-            radial_any<T, false, FAST>(P, sQ, r, rinv, R, dR);
-            const T z = ok ? T(1) : T(0);
-            T* row = sT + lane * SS;
-            row[0] = d[0] * rinv; row[1] = d[1] * rinv; row[2] = d[2] * rinv;
+    if (nround > 0) {   // some atom has pairs: the list is not empty
+        SlotIdx i0 = slot_index(g, act && q < cnt, beg + q);
+        T p0[3];
+        slot_pos(g, i0, p0);
+        SlotIdx i1 = slot_index(g, act && K + q < cnt, beg + K + q);
+        for (int rd = 0; rd < nround; ++rd) {
+            {
+                // pair stage: rhat and R_k of slot rd*K + q, staged for the atom's K lanes
+                const int slot = rd * K + q;
+                const bool live = act && slot < cnt;
+                const SlotIdx ic = i0;
+                T pc[3] = {p0[0], p0[1], p0[2]};
+                slot_pos(g, i1, p0);
+                i0 = i1;
+                i1 = slot_index(g, act && slot + 2 * K < cnt, beg + slot + 2 * K);
+                T d[3], r;
+                const bool ok = slot_geometry<T>(g, live, ic, pc, pi, eb, d, r);
+                if constexpr (MODE != 0) {
+                    // centre atom and pair vector for the pair kernel (an empty
+                    // slot writes the spare entry P)
+                    const int pw = live ? beg + slot : g.P;
+                    g.centre[pw] = atom;
+                    T* pv = g.pdv + 3 * static_cast<size_t>(pw);
+                    pv[0] = d[0]; pv[1] = d[1]; pv[2] = d[2];
+                }
+                const T rinv = T(1) / r;
+                T R[POD_MAX_K], dR[POD_MAX_K];
+                radial_any<T, false, FAST>(P, &P->Q[0][0], r, rinv, R, dR);
+                const T z = ok ? T(1) : T(0);
+                T* row = sT + lane * SS;
+                row[0] = d[0] * rinv; row[1] = d[1] * rinv; row[2] = d[2] * rinv;
 #pragma unroll
-            for (int k = 0; k < POD_MAX_K; ++k)
-                if (k < K) row[3 + k] = R[k] * z;
-        }
-        __syncthreads();
-        if (act) {
-            for (int s = 0; s < K; ++s) {
-                const T* row = sT + (al * K + s) * SS;
-                accumulate_basis<T, PA>(acc, row[3 + m], row[0], row[1], row[2]);
+                for (int k = 0; k < POD_MAX_K; ++k)
+                    if (k < K) row[3 + k] = R[k] * z;
             }
+            wave_sync();
+            if (act) {
+                for (int s = 0; s < K; ++s) {
+                    const T* row = sT + (al * K + s) * SS;
+                    accumulate_basis<T, PA>(acc, row[3 + m], row[0], row[1], row[2]);
+                }
+            }
+            wave_sync();
         }
-        __syncthreads();
+    }
+    {
+        const int ew = wave_or(eb);
+        if (lane == 0 && ew != 0) atomicOr(g.err, ew);
     }
 
     // ---------------- contractions (Sec. II.E) ----------------
@@ -393,6 +351,47 @@ __device__ __forceinline__ void atom_body(const KArgs<T>& g) {
             }
         }
         return;
+    }
+
+    // global descriptors G = sum_i D_i (eq. (58a)): block partial.  Lane
+    // (atom, m) holds the values of columns that belong to radial index m
+    // only -- D2 (j = 0), D3 (j = 1 .. P3 + 1), D4 (j = P3 + 2 ..) -- so the
+    // block sum of column (m, j) adds lanes m, K + m, 2K + m, ...: the values
+    // go to LDS as [j][lane] (the round staging area, free here) and thread
+    // (m, j) sums its atoms in order.
+    if (g.want_G) {
+        constexpr int NJ = 1 + (PA + 1) + KA;
+        const int P3e = P->K3 > 0 ? P3 : -1;     // D3 rows j = 1 .. P3e + 1, D4 rows after them
+        double* sG = reinterpret_cast<double*>(sT);
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) sG[j * WAVE + lane] = 0.0;
+        if (has2) sG[lane] = static_cast<double>(acc[0]);
+        if (has3) {
+#pragma unroll
+            for (int n = 0; n <= PA; ++n)
+                if (n <= P3) sG[(1 + n) * WAVE + lane] = static_cast<double>(d3[n]);
+        }
+        if (has4) {
+#pragma unroll
+            for (int p = 0; p < KA; ++p)
+                if (p < Ka4) sG[(2 + P3e + p) * WAVE + lane] = static_cast<double>(d4[p]);
+        }
+        wave_sync();
+        const int na = (g.N - blockIdx.x * apw < apw) ? g.N - blockIdx.x * apw : apw;
+        const int nj3 = 2 + P3e + Ka4;     // columns per radial index
+        for (int t = lane; t < K * nj3; t += WAVE) {
+            const int mm = t / nj3, j = t - mm * nj3;
+            int col = -1;
+            if (j == 0) col = mm < P->K2 ? 1 + mm : -1;
+            else if (j <= P3e + 1) col = mm < P->K3 ? P->off3 + mm * (P3 + 1) + (j - 1) : -1;
+            else col = mm < P->K4 ? P->off4 + mm * Ka4 + (j - P3e - 2) : -1;
+            if (col < 0) continue;
+            double sum = 0.0;
+            for (int a2 = 0; a2 < na; ++a2) sum += sG[j * WAVE + a2 * K + mm];
+            g.part[static_cast<size_t>(10 + col) * gridDim.x + blockIdx.x] = sum;
+        }
+        if (lane == 0) g.part[static_cast<size_t>(10) * gridDim.x + blockIdx.x] = static_cast<double>(na);
+        wave_sync();
     }
 
     // ---------------- energy (eq. (57a)) and adjoint dE_i/dB ----------------
@@ -445,7 +444,7 @@ __device__ __forceinline__ void atom_body(const KArgs<T>& g) {
     T ab[AB_LDS ? 1 : NA];
     if constexpr (AB_LDS) {
         if (act) {
-            T* abrow = sT + (al * K + m) * odd_len(NA);
+            T* abrow = sT + al * AST + m * NA;
 #pragma unroll
             for (int mu = 0; mu < NA; ++mu)
                 abrow[mu] = T(2 * mt.mult[mu]) * eff3[mt.deg[mu]] * acc[mu] + (mu == 0 ? eff2 : T(0));  // eq. (26c)
@@ -483,141 +482,36 @@ __device__ __forceinline__ void atom_body(const KArgs<T>& g) {
     // per-atom energy: sum the K lanes of the atom through LDS
     {
         sE[lane] = e;
-        __syncthreads();
+        wave_sync();
         double ei = 0.0;
         if (act && q == 0) {
             for (int k = 0; k < K; ++k) ei += sE[al * K + k];
             if (g.E_atom) g.E_atom[atom] = static_cast<T>(ei);
         }
-        __syncthreads();
+        wave_sync();
         const double eb = wave_sum(ei);
         if (lane == 0) g.part[blockIdx.x] = eb;
     }
-    // global descriptors G = sum_i D_i (eq. (58a)): block partial in LDS
-    if (g.want_G) {
-        for (int k = lane; k < M; k += WAVE) sE[k] = 0.0;
-        __syncthreads();
-        for (int a2 = 0; a2 < apw; ++a2) {
-            if (al == a2 && act) {
-                if (q == 0) sE[0] += 1.0;
-                if (has2) sE[1 + m] += static_cast<double>(acc[0]);
-                if (has3)
-#pragma unroll
-                    for (int n = 0; n <= PA; ++n)
-                        if (n <= P3) sE[P->off3 + m * (P3 + 1) + n] += static_cast<double>(d3[n]);
-                if (has4)
-#pragma unroll
-                    for (int p = 0; p < KA; ++p)
-                        if (p < Ka4) sE[P->off4 + m * Ka4 + p] += static_cast<double>(d4[p]);
-            }
-            __syncthreads();
-        }
-        for (int k = lane; k < M; k += WAVE) g.part[static_cast<size_t>(10 + k) * gridDim.x + blockIdx.x] = sE[k];
-    }
-
     if (!g.want_back) return;
 
-    // ---------------- backward: g_ij = dE_i/dr_ij (eq. (24c)) ----------------
-    // adjoint rows to LDS; then lane (a, s) takes neighbour slot s of atom a in
-    // every round, re-evaluates its radial functions with derivatives and
-    // contracts them with the K adjoint rows of atom a
+    // ---------------- adjoint rows to memory ----------------
+    // rows dE_i/dB_{i k .} of the workgroup's atoms, [atom][k][mu] (K * NA
+    // values per atom, contiguous over the workgroup's atoms): staged in LDS
+    // (the round staging area is free) and copied out coalesced
     T* sAb = sT;
     if constexpr (!AB_LDS) {
         if (act) {
 #pragma unroll
-            for (int mu = 0; mu < NA; ++mu) sAb[(al * K + m) * NAP + mu] = ab[mu];
+            for (int mu = 0; mu < NA; ++mu) sAb[al * AST + m * NA + mu] = ab[mu];
         }
     }
-    __syncthreads();
-
-    double vir[9];
-#pragma unroll
-    for (int k = 0; k < 9; ++k) vir[k] = 0.0;
-    double fo0 = 0.0, fo1 = 0.0, fo2 = 0.0;
-    SlotIdx b0 = slot_index(g, act && q < cnt, beg + q);
-    T bp0[3];
-    slot_pos(g, b0, bp0);
-    SlotIdx b1 = slot_index(g, act && K + q < cnt, beg + K + q);
-    for (int rd = 0; rd < nround; ++rd) {
-        const int slot = rd * K + q;
-        const SlotIdx ic = b0;
-        T pc[3] = {bp0[0], bp0[1], bp0[2]};
-        slot_pos(g, b1, bp0);
-        b0 = b1;
-        b1 = slot_index(g, act && slot + 2 * K < cnt, beg + slot + 2 * K);
-        if (act && slot < cnt) {
-            T d[3], r;
-            const bool ok = slot_geometry<T>(g, true, ic, pc, pi, false, d, r);
-            if (ok) {
-                const T ri = T(1) / r;
-                T R[POD_MAX_K], dR[POD_MAX_K];
-                radial_any<T, true, FAST>(P, sQ, r, ri, R, dR);
-                const T ux = d[0] * ri, uy = d[1] * ri, uz = d[2] * ri;
-                T A[NA];
-                A[0] = T(1);
-#pragma unroll
-                for (int mu = 1; mu < NA; ++mu) {
-                    const T u = mt.axis[mu] == 0 ? ux : (mt.axis[mu] == 1 ? uy : uz);
-                    A[mu] = A[mt.par[mu]] * u;
-                }
-                T gx, gy, gz;
-                const T* abr = sAb + (al * K) * NAP;
-                // radial index first for the K of the benchmark models (FP64
-                // per-atom kernel on the 15,840-atom box 90.5 -> 79.6 us, FP32
-                // unchanged at 55.6 us); one pass per radial function otherwise
-                if (K == 6) pair_gradient_k<T, PA, 6>(abr, A, R, dR, ri, ux, uy, uz, gx, gy, gz);
-                else if (K == 4) pair_gradient_k<T, PA, 4>(abr, A, R, dR, ri, ux, uy, uz, gx, gy, gz);
-                else pair_gradient_any<T, PA>(abr, K, A, R, dR, ri, ux, uy, uz, gx, gy, gz);
-                if (g.gbuf) {
-                    // stored at the reverse slot: the neighbour's gather reads its own list range
-                    if (ic.rv >= 0 && ic.rv < g.P) {
-                        T* gp3 = g.gbuf + 3 * static_cast<size_t>(ic.rv);
-                        gp3[0] = gx; gp3[1] = gy; gp3[2] = gz;
-                    } else {
-                        atomicOr(g.err, ERR_NEIGH);
-                    }
-                } else {
-                    const int j = ic.j;
-                    atomicAdd(&g.Facc[3 * j + 0], -static_cast<double>(gx));
-                    atomicAdd(&g.Facc[3 * j + 1], -static_cast<double>(gy));
-                    atomicAdd(&g.Facc[3 * j + 2], -static_cast<double>(gz));
-                }
-                fo0 += gx; fo1 += gy; fo2 += gz;
-                const double dd3[3] = {double(d[0]), double(d[1]), double(d[2])};
-                const double gg[3] = {double(gx), double(gy), double(gz)};
-#pragma unroll
-                for (int x = 0; x < 3; ++x)
-#pragma unroll
-                    for (int y = 0; y < 3; ++y) vir[3 * x + y] -= dd3[x] * gg[y];
-            } else if (g.gbuf && ic.rv >= 0 && ic.rv < g.P) {
-                T* gp3 = g.gbuf + 3 * static_cast<size_t>(ic.rv);
-                gp3[0] = T(0); gp3[1] = T(0); gp3[2] = T(0);
-            }
-        }
-    }
-    // own-atom force F_i += sum_j g_ij: sum the K lanes of the atom
-    sF[3 * lane + 0] = fo0; sF[3 * lane + 1] = fo1; sF[3 * lane + 2] = fo2;
-    __syncthreads();
-    if (act && q == 0) {
-        double f0 = 0.0, f1 = 0.0, f2 = 0.0;
-        for (int k = 0; k < K; ++k) {
-            const int l2 = al * K + k;
-            f0 += sF[3 * l2]; f1 += sF[3 * l2 + 1]; f2 += sF[3 * l2 + 2];
-        }
-        if (g.gbuf) {
-            g.fown[3 * atom + 0] = f0;
-            g.fown[3 * atom + 1] = f1;
-            g.fown[3 * atom + 2] = f2;
-        } else {
-            atomicAdd(&g.Facc[3 * atom + 0], f0);
-            atomicAdd(&g.Facc[3 * atom + 1], f1);
-            atomicAdd(&g.Facc[3 * atom + 2], f2);
-        }
-    }
-#pragma unroll
-    for (int k = 0; k < 9; ++k) {
-        const double v = wave_sum(vir[k]);
-        if (lane == 0) g.part[static_cast<size_t>(1 + k) * gridDim.x + blockIdx.x] = v;
+    wave_sync();
+    {
+        const int a0 = blockIdx.x * apw;
+        const int na = (g.N - a0 < apw) ? g.N - a0 : apw;
+        const int nv = na * AST;
+        T* dst = g.abar + static_cast<size_t>(a0) * AST;
+        for (int idx = lane; idx < nv; idx += WAVE) dst[idx] = sAb[idx];
     }
 }
 
@@ -634,23 +528,320 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void at
     atom_body<T, PA, MODE, FAST>(g);
 }
 
+// ---------------------------------------------------------------------------
+// Pair kernel: g_ij = dE_i/dr_ij for one pair per lane (eq. (24c)).
+//
+// Block w (one 64-lane wavefront) takes pairs 64 w .. 64 w + 63 of the list.
+// The centre atom of every pair was written by the atom kernel.  The adjoint
+// rows of the block's atoms, K * NA values per atom, are copied from memory
+// into LDS (the loads for the first pair_acap atoms are issued before the
+// radial functions are evaluated; a block whose pairs span more atoms takes
+// the rest in further chunks).  Each lane re-evaluates the radial functions
+// with their derivatives and contracts the monomials of its pair with the K
+// rows of its centre atom.
+//
+// Outputs: on the gather path g is stored at the pair's own slot p and at
+// its reverse slot rev(p), and the finalize kernel forms each atom's force
+// from its own list range in a fixed order; without a reverse index, g is
+// added to an FP64 accumulator with atomics.  The virial leaves as one
+// partial per block.
+template <typename T>
+struct PArgs {
+    ParamsT<T> prm;    // by value: read with scalar loads
+    int N, P;
+    const T* pos;
+    CellT<T> cell;
+    const int* offsets;
+    const int* nbr_j;
+    const int* shift;
+    const int* rev;          // reverse-pair index (gather path) or null
+    const T* abar;           // adjoint rows [N][K][NA]
+    const int* centre;       // centre atom of every pair (written by the atom kernel)
+    const T* pdv;            // pair vectors r_ij, zero for a listed pair that is not a neighbour (same)
+    T* gbuf;                 // gather: g_ij stored at slot rev(p) (3P)
+    T* gown;                 // gather: g_ij stored at slot p (3P)
+    double* Facc;            // scatter: FP64 accumulator (3N, zero on entry)
+    double* wpart;           // virial partials, column-major [9][nblk]
+    int want_W;
+    int gate;                // always 1 (see pair_gradient_blocks)
+    int* err;
+};
+
+// Pairs per pair-kernel block: one per lane.
+constexpr int PAIR_BLOCK = WAVE;
+
+// Atoms whose adjoint rows one pair block holds in LDS at a time (at most
+// 8 KB; 64 pairs of atoms with 21 or more pairs each span at most 5 atoms).
+__host__ __device__ constexpr int pair_acap(int K, int NA, int tsize) {
+    const int per = abar_stride(K, NA, tsize) * tsize;
+    const int a = 8192 / per;
+    return a < 1 ? 1 : (a > 8 ? 8 : a);
+}
+
+__host__ __device__ inline size_t pair_lds_bytes(int K, int NA, size_t tsize) {
+    const int t = static_cast<int>(tsize);
+    return static_cast<size_t>(pair_acap(K, NA, t)) * abar_stride(K, NA, t) * tsize;
+}
+
+// dE_i/dr_ij of one pair for a radial count KK fixed at compile time
+// (eq. (24c)): W1_mu = sum_k Abar_{k mu} R'_k, W2_mu = sum_k Abar_{k mu} R_k,
+// then g = (sum_mu W1_mu A_mu - sum_n n H_n / r) rhat + (1/r) sum_mu W2_mu
+// grad A_mu with H_n = sum_{deg mu = n} W2_mu A_mu and the gradient sums
+// grouped by the exponent being lowered.
+//
+// Each monomial is contracted in a basic block of its own, entered under
+// `gate`, a kernel argument that is always 1 but unknown to the compiler:
+// with all monomials in one block the code generator issues the K * NA LDS
+// reads of the adjoint rows ahead of the arithmetic and runs out of
+// registers (FP64: 256 VGPRs + 256 AGPRs and scratch, against 180 VGPRs).
+template <typename T, int PA, int KK>
+__device__ __forceinline__ void pair_gradient_blocks(const T* __restrict__ abr, const T (&R)[POD_MAX_K],
+                                                     const T (&dR)[POD_MAX_K], T ri, T ux, T uy, T uz, int gate,
+                                                     T& gx, T& gy, T& gz) {
+    constexpr MonoTable<PA> mt{};
+    constexpr int NA = n_mono(PA);
+    constexpr int NAP = NA;    // rows of one atom are contiguous
+    T A[NA];           // monomials, formed in the block that contracts them
+    T s1 = 0, eul = 0, g0 = 0, g1 = 0, g2 = 0;
+    T buf[2][KK];      // the K values of monomial mu in buf[mu & 1]; mu + 1 read ahead
+#pragma unroll
+    for (int k = 0; k < KK; ++k) buf[0][k] = abr[k * NAP];
+#pragma unroll
+    for (int mu = 0; mu < NA; ++mu) {
+        if (gate) {
+            const int cb = mu & 1;
+            if (mu + 1 < NA) {
+#pragma unroll
+                for (int k = 0; k < KK; ++k) buf[cb ^ 1][k] = abr[k * NAP + mu + 1];
+            }
+            if (mu == 0) {
+                A[0] = T(1);
+            } else {
+                const T u = mt.axis[mu] == 0 ? ux : (mt.axis[mu] == 1 ? uy : uz);
+                A[mu] = A[mt.par[mu]] * u;
+            }
+            T w1 = 0, w2 = 0;
+#pragma unroll
+            for (int k = 0; k < KK; ++k) {
+                w1 += buf[cb][k] * dR[k];
+                w2 += buf[cb][k] * R[k];
+            }
+            s1 += w1 * A[mu];
+            // Euler sum n H_n and the gradient sums, each term weighted by its exponent
+            const int dg = mt.deg[mu];
+            if (dg == 1) eul += w2 * A[mu];
+            else if (dg > 1) eul += (T(dg) * w2) * A[mu];
+            T* gd[3] = {&g0, &g1, &g2};
+#pragma unroll
+            for (int dd = 0; dd < 3; ++dd) {
+                if (mt.down[mu][dd] >= 0) {
+                    const int e = mt.ex[mu][dd];
+                    *gd[dd] += (e == 1 ? w2 : T(e) * w2) * A[mt.down[mu][dd]];
+                }
+            }
+        }
+    }
+    const T a1 = s1 - eul * ri;
+    gx = a1 * ux + ri * g0;
+    gy = a1 * uy + ri * g1;
+    gz = a1 * uz + ri * g2;
+}
+
+// Copy nbytes (a multiple of 16) from global memory into LDS with the
+// direct global-to-LDS loads of gfx950: each lane moves 16 bytes, one
+// instruction fills 1 KB of consecutive LDS.  Completion is awaited with
+// lds_copy_wait.
+__device__ __forceinline__ void lds_copy_issue(const void* src, void* dst, int nbytes, int lane) {
+    typedef __attribute__((address_space(1))) void* gptr_t;
+    typedef __attribute__((address_space(3))) void* lptr_t;
+    const char* s = static_cast<const char*>(src);
+    char* d = static_cast<char*>(dst);
+    for (int off = 0; off < nbytes; off += 16 * WAVE) {
+        if (off + 16 * lane < nbytes)
+            __builtin_amdgcn_global_load_lds((gptr_t)(s + off + 16 * lane), (lptr_t)(d + off), 16, 0, 0);
+    }
+}
+
+__device__ __forceinline__ void lds_copy_wait() {
+    __builtin_amdgcn_s_waitcnt(0);
+    wave_sync();
+}
+
+// Geometry and radial functions (with derivatives) of one pair.
+template <typename T>
+struct PairGeom {
+    T d[3], r, ri, ux, uy, uz;
+    T R[POD_MAX_K], dR[POD_MAX_K];
+    bool ok;
+};
+
+template <typename T, int KK, bool FAST>
+__device__ __forceinline__ void pair_setup(const PArgs<T>& g, bool valid, const T (&dv)[3], PairGeom<T>& q) {
+    const ParamsT<T>* __restrict__ P = &g.prm;
+    q.d[0] = dv[0]; q.d[1] = dv[1]; q.d[2] = dv[2];
+    const T r2 = dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2];
+    // the atom kernel stored zero for a listed pair outside (rin, rcut)
+    q.ok = valid && r2 > T(0);
+    q.r = q.ok ? d_sqrt(r2) : T(0.5) * (P->rin + P->rcut);
+    q.ri = T(1) / q.r;
+    // Q from the parameter block (uniform addresses: scalar loads)
+    radial_any<T, true, FAST, (KK > 0 ? KK : POD_MAX_K)>(P, &P->Q[0][0], q.r, q.ri, q.R, q.dR);
+    q.ux = q.d[0] * q.ri; q.uy = q.d[1] * q.ri; q.uz = q.d[2] * q.ri;
+}
+
+template <typename T, int PA, int KK>
+__device__ __forceinline__ void pair_contract(const PArgs<T>& g, int K, const PairGeom<T>& q, const T* abr, T& gx,
+                                              T& gy, T& gz) {
+    constexpr MonoTable<PA> mt{};
+    constexpr int NA = n_mono(PA);
+    if constexpr (KK > 0) {
+        pair_gradient_blocks<T, PA, KK>(abr, q.R, q.dR, q.ri, q.ux, q.uy, q.uz, g.gate, gx, gy, gz);
+    } else {
+        T A[NA];
+        A[0] = T(1);
+#pragma unroll
+        for (int mu = 1; mu < NA; ++mu) {
+            const T u = mt.axis[mu] == 0 ? q.ux : (mt.axis[mu] == 1 ? q.uy : q.uz);
+            A[mu] = A[mt.par[mu]] * u;
+        }
+        pair_gradient_any<T, PA>(abr, K, A, q.R, q.dR, q.ri, q.ux, q.uy, q.uz, gx, gy, gz);
+    }
+}
+
+// g_ij of pair p: stored at the pair's own slot and at its reverse slot (the
+// finalize kernel gathers F_n = sum over n's slots of own - reverse), or
+// added to both atoms with atomics.
+template <typename T>
+__device__ __forceinline__ void pair_store(const PArgs<T>& g, int p, int ci, int j, int rv, bool ok, T gx, T gy,
+                                           T gz) {
+    if (g.gbuf) {
+        T* go = g.gown + 3 * static_cast<size_t>(p);
+        go[0] = gx; go[1] = gy; go[2] = gz;
+        if (rv >= 0 && rv < g.P) {
+            T* gp3 = g.gbuf + 3 * static_cast<size_t>(rv);
+            gp3[0] = gx; gp3[1] = gy; gp3[2] = gz;
+        } else {
+            atomicOr(g.err, ERR_NEIGH);
+        }
+    } else if (ok) {
+        atomicAdd(&g.Facc[3 * j + 0], -static_cast<double>(gx));
+        atomicAdd(&g.Facc[3 * j + 1], -static_cast<double>(gy));
+        atomicAdd(&g.Facc[3 * j + 2], -static_cast<double>(gz));
+        atomicAdd(&g.Facc[3 * ci + 0], static_cast<double>(gx));
+        atomicAdd(&g.Facc[3 * ci + 1], static_cast<double>(gy));
+        atomicAdd(&g.Facc[3 * ci + 2], static_cast<double>(gz));
+    }
+}
+
+// One block of 64 consecutive pairs, one pair per lane.  The rows of the
+// first acap atoms from the block's first centre atom are loaded into LDS
+// while the radial functions are evaluated; a block whose pairs span more
+// atoms takes the others in further chunks.  The virial of the lane's pair
+// is added to vir.
+template <typename T, int PA, int KK, bool FAST>
+__device__ __forceinline__ void pair_block(const PArgs<T>& g, int blk, T* sAb, double (&vir)[9]) {
+    constexpr int NA = n_mono(PA);
+    const ParamsT<T>* __restrict__ P = &g.prm;
+    const int K = KK > 0 ? KK : P->K;
+    const int AST = abar_stride(K, NA, sizeof(T));
+    const int acap = pair_acap(K, NA, sizeof(T));
+    const int lane = threadIdx.x;
+    const int p = blk * WAVE + lane;
+    const bool valid = p < g.P;
+    // everything the pair needs, requested at once: centre atom, pair vector,
+    // reverse slot (gather path) or neighbour index (atomic path)
+    // (issued on every lane: a lane past the end reads the last pair)
+    const int pc = valid ? p : g.P - 1;
+    int ci = g.centre[pc], rv = -1, j = -1;
+    T dv[3] = {g.pdv[3 * static_cast<size_t>(pc) + 0], g.pdv[3 * static_cast<size_t>(pc) + 1],
+               g.pdv[3 * static_cast<size_t>(pc) + 2]};
+    if (g.gbuf) rv = g.rev[pc];
+    else j = g.nbr_j[pc];
+    int lo = g.centre[blk * WAVE];
+    lo = lo < 0 ? 0 : (lo > g.N - 1 ? g.N - 1 : lo);
+    const int na0 = (g.N - lo < acap) ? g.N - lo : acap;
+    wave_sync();   // rows of a previous block are no longer read
+    lds_copy_issue(g.abar + static_cast<size_t>(lo) * AST, sAb, na0 * AST * static_cast<int>(sizeof(T)), lane);
+    ci = ci < 0 ? 0 : (ci > g.N - 1 ? g.N - 1 : ci);
+    if (!g.gbuf && (j < 0 || j >= g.N)) j = ci;   // malformed list: reported by the atom kernel
+
+    PairGeom<T> q;
+    pair_setup<T, KK, FAST>(g, valid, dv, q);
+    T gx = T(0), gy = T(0), gz = T(0);
+    lds_copy_wait();
+    if (q.ok && ci >= lo && ci < lo + na0)
+        pair_contract<T, PA, KK>(g, K, q, sAb + static_cast<size_t>(ci - lo) * AST, gx, gy, gz);
+    // further chunks, skipping atoms without pairs in this block
+    constexpr int INF = 0x7fffffff;
+    const int key = valid ? ci : INF;
+    int base = wave_min(key >= lo + na0 ? key : INF);
+    while (base != INF) {
+        const int na = (g.N - base < acap) ? g.N - base : acap;
+        wave_sync();
+        lds_copy_issue(g.abar + static_cast<size_t>(base) * AST, sAb, na * AST * static_cast<int>(sizeof(T)), lane);
+        lds_copy_wait();
+        if (q.ok && ci >= base && ci < base + na)
+            pair_contract<T, PA, KK>(g, K, q, sAb + static_cast<size_t>(ci - base) * AST, gx, gy, gz);
+        base = wave_min(key >= base + na ? key : INF);
+    }
+    if (valid) pair_store<T>(g, p, ci, j, rv, q.ok, gx, gy, gz);
+    if (q.ok) {
+        const double dd[3] = {double(q.d[0]), double(q.d[1]), double(q.d[2])};
+        const double gg[3] = {double(gx), double(gy), double(gz)};
+#pragma unroll
+        for (int x = 0; x < 3; ++x)
+#pragma unroll
+            for (int y = 0; y < 3; ++y) vir[3 * x + y] -= dd[x] * gg[y];
+    }
+}
+
+// KK: the radial count when fixed at compile time (4 or 6), 0 for any K.
+// Wavefront w takes pairs 64 w .. 64 w + 63.
+template <typename T, int PA, int KK, bool FAST>
+__device__ __forceinline__ void pair_body(const PArgs<T>& g) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* sAb = reinterpret_cast<T*>(smem_raw);
+    const int lane = threadIdx.x;
+    const int w = blockIdx.x;
+    const int nblk = gridDim.x;
+    double vir[9];
+#pragma unroll
+    for (int x = 0; x < 9; ++x) vir[x] = 0.0;
+    pair_block<T, PA, KK, FAST>(g, w, sAb, vir);
+    if (g.want_W) {
+        // W_ab -= r_ij,a g_ij,b, summed over the wavefront's pairs
+        int c;
+        const double sw = wave_sum9(vir, lane, c);
+        if (c < 9) g.wpart[static_cast<size_t>(c) * nblk + w] = sw;
+    }
+}
+
+template <typename T, int PA, int KK, bool FAST>
+__global__ __launch_bounds__(64) void pair_kernel(PArgs<T> g) {
+    pair_body<T, PA, KK, FAST>(g);
+}
+
 // Totals and forces.  Blocks 0 .. 9 + M: column sums of the block partials
-// (column 0 -> E, 1..9 -> W, 10.. -> G).  Remaining blocks, with a reverse
-// index: F_n = sum over the pairs p of n of g_p - g_rev(p) (8 atoms x 32
+// in a fixed order (column 0 -> E and 10.. -> G from the atom kernel's
+// blocks, 1..9 -> W from the pair kernel's blocks).  Remaining blocks, with
+// a reverse index: F_n = sum over the slots p of n of gown[p] - gbuf[p],
+// where gown[p] holds g of pair p and gbuf[p] g of its reverse (8 atoms x 32
 // lanes per block, deterministic); without one: F = Facc (accumulated with
 // atomics) and Facc cleared for the next call.
 template <typename T>
 struct FinArgs {
-    const double* part;
+    const double* part;    // atom-kernel partials [10 + M][nblk]
     int nblk, ncol;
+    const double* wpart;   // pair-kernel virial partials [9][nblk_p]
+    int nblk_p;
     double* E;
     double* W;
     double* G;
     double* Facc;
     T* F;
     long n3;
-    const T* gbuf;     // gather path: g stored at reverse slots
-    const double* fown;  // gather path: own-atom sums
+    const T* gbuf;         // gather path: g stored at reverse slots
+    const T* gown;         // gather path: g stored at own slots
     const int* rev;
     const int* offsets;
     int N, P;
@@ -669,11 +860,12 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinArgs<T> f) {
             if (a < f.N) {
                 const int b = f.offsets[a], e = f.offsets[a + 1];
                 if (b >= 0 && e >= b && e <= f.P) {
-                    // slot p of atom a holds g of the pair (j -> a) whose reverse is p
+                    // slot p of atom a: g of pair p (a -> j) and g of its reverse (j -> a)
                     for (int p = b + s0; p < e; p += 32) {
-                        f0 -= static_cast<double>(f.gbuf[3 * static_cast<size_t>(p) + 0]);
-                        f1 -= static_cast<double>(f.gbuf[3 * static_cast<size_t>(p) + 1]);
-                        f2 -= static_cast<double>(f.gbuf[3 * static_cast<size_t>(p) + 2]);
+                        const size_t o = 3 * static_cast<size_t>(p);
+                        f0 += static_cast<double>(f.gown[o + 0]) - static_cast<double>(f.gbuf[o + 0]);
+                        f1 += static_cast<double>(f.gown[o + 1]) - static_cast<double>(f.gbuf[o + 1]);
+                        f2 += static_cast<double>(f.gown[o + 2]) - static_cast<double>(f.gbuf[o + 2]);
                     }
                 }
             }
@@ -684,9 +876,9 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinArgs<T> f) {
                 f2 += __shfl_xor(f2, o, 32);
             }
             if (a < f.N && s0 == 0 && f.F) {
-                f.F[3 * a + 0] = static_cast<T>(f.fown[3 * a + 0] + f0);
-                f.F[3 * a + 1] = static_cast<T>(f.fown[3 * a + 1] + f1);
-                f.F[3 * a + 2] = static_cast<T>(f.fown[3 * a + 2] + f2);
+                f.F[3 * a + 0] = static_cast<T>(f0);
+                f.F[3 * a + 1] = static_cast<T>(f1);
+                f.F[3 * a + 2] = static_cast<T>(f2);
             }
         } else {
             const long i = static_cast<long>(fb) * 256 + threadIdx.x;
@@ -697,15 +889,24 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinArgs<T> f) {
         }
         return;
     }
-    const double* part = f.part;
-    const int nblk = f.nblk;
     double* E = f.E;
     double* W = f.W;
     double* G = f.G;
     if ((col == 0 && !E) || (col >= 1 && col < 10 && !W) || (col >= 10 && !G)) return;
-    const double* src = part + static_cast<size_t>(col) * nblk;
+    const bool wcol = col >= 1 && col < 10;
+    const int nb = wcol ? f.nblk_p : f.nblk;
+    const double* src = wcol ? f.wpart + static_cast<size_t>(col - 1) * nb : f.part + static_cast<size_t>(col) * nb;
+    // every thread adds b = t, t + 256, ... in order; eight loads in flight
     double s = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += 256) s += src[b];
+    int b = threadIdx.x;
+    for (; b + 7 * 256 < nb; b += 8 * 256) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = src[b + u * 256];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; b < nb; b += 256) s += src[b];
     __shared__ double red[256];
     red[threadIdx.x] = s;
     __syncthreads();
@@ -778,7 +979,38 @@ hipError_t dispatch_pa(int PA, const KArgs<T>& a, bool fast, int nblk, size_t ld
     }
 }
 
-size_t lds_bytes(int K, int PA, size_t tsize, int M) { return atom_lds_layout(K, n_mono(PA), M, tsize).total; }
+template <typename T, int PA, int KK>
+void launch_pair_k(const PArgs<T>& a, bool fast, int nblk, size_t lds, hipStream_t st) {
+    if (fast) hipLaunchKernelGGL((pair_kernel<T, PA, KK, true>), dim3(nblk), dim3(WAVE), lds, st, a);
+    else hipLaunchKernelGGL((pair_kernel<T, PA, KK, false>), dim3(nblk), dim3(WAVE), lds, st, a);
+}
+
+template <typename T, int PA>
+hipError_t launch_pair(const PArgs<T>& a, bool fast, int nblk, size_t lds, hipStream_t st) {
+    const int K = a.prm.K;
+    if (K == 6) launch_pair_k<T, PA, 6>(a, fast, nblk, lds, st);
+    else if (K == 4) launch_pair_k<T, PA, 4>(a, fast, nblk, lds, st);
+    else launch_pair_k<T, PA, 0>(a, fast, nblk, lds, st);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t dispatch_pair(int PA, const PArgs<T>& a, bool fast, int nblk, size_t lds, hipStream_t st) {
+    switch (PA) {
+        case 0: return launch_pair<T, 0>(a, fast, nblk, lds, st);
+        case 1: return launch_pair<T, 1>(a, fast, nblk, lds, st);
+        case 2: return launch_pair<T, 2>(a, fast, nblk, lds, st);
+        case 3: return launch_pair<T, 3>(a, fast, nblk, lds, st);
+        case 4: return launch_pair<T, 4>(a, fast, nblk, lds, st);
+        case 5: return launch_pair<T, 5>(a, fast, nblk, lds, st);
+        case 6: return launch_pair<T, 6>(a, fast, nblk, lds, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+size_t lds_bytes(int K, int PA, size_t tsize, int M) {
+    return atom_lds_layout(K, n_mono(PA), M, tsize, n_partitions(PA), PA).total;
+}
 
 template <typename T>
 const ParamsT<T>& host_params(const pod_handle* h);
@@ -800,8 +1032,7 @@ int fill_args(pod_handle* h, KArgs<T>& a, int N, int P, const void* pos, const d
         a.cell.a[k] = static_cast<T>(v);
     }
     a.offsets = offsets; a.nbr_j = nbr_j; a.shift = shift;
-    a.coef = nullptr; a.D = nullptr; a.E_atom = nullptr; a.Facc = nullptr; a.gbuf = nullptr; a.part = nullptr;
-    a.fown = nullptr; a.rev = nullptr;
+    a.coef = nullptr; a.D = nullptr; a.E_atom = nullptr; a.abar = nullptr; a.centre = nullptr; a.pdv = nullptr; a.part = nullptr;
     a.want_G = 0; a.want_back = 0;
     a.y_net = nullptr; a.g_net = nullptr; a.n_net = 0;
     a.err = h->d_err;
@@ -825,34 +1056,58 @@ int descriptors_impl(pod_handle* h, int N, int P, const void* pos, const double*
     return e == hipSuccess ? POD_OK : POD_EHIP;
 }
 
+// Scratch of one energy call, carved from one device buffer (256-byte
+// aligned pieces): atom-kernel partials [10 + M][nblk], pair-kernel virial
+// partials [9][nblk_p], adjoint rows [N][K][NA] (per-atom stride padded to
+// 16 bytes), centre atom and pair vector of each pair, and on the gather path the pair gradients [P][3] at reverse and at own
+// slots.
+struct EfScratch {
+    size_t part, wpart, abar, centre, pdv, gbuf, gown, total;
+};
+
+EfScratch ef_scratch_layout(int N, int P, int K, int PA, int M, size_t tsize, bool back, bool gather) {
+    auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+    const int apw = WAVE / K;
+    const size_t nblk = N > 0 ? (static_cast<size_t>(N) + apw - 1) / apw : 0;
+    const size_t nblk_p = back ? (static_cast<size_t>(P) + PAIR_BLOCK - 1) / PAIR_BLOCK : 0;
+    EfScratch L;
+    size_t o = 0;
+    L.part = o; o += al(static_cast<size_t>(10 + M) * (nblk > 0 ? nblk : 1) * sizeof(double));
+    L.wpart = o; o += al(9 * (nblk_p > 0 ? nblk_p : 1) * sizeof(double));
+    L.abar = o; o += back ? al(static_cast<size_t>(N) * abar_stride(K, n_mono(PA), static_cast<int>(tsize)) * tsize) : 0;
+    L.centre = o; o += al((static_cast<size_t>(P) + 1) * sizeof(int));      // entry P: spare for empty slots
+    L.pdv = o; o += al((static_cast<size_t>(P) + 1) * 3 * tsize);
+    L.gbuf = o; o += gather ? al(static_cast<size_t>(P > 0 ? P : 1) * 3 * tsize) : 0;
+    L.gown = o; o += gather ? al(static_cast<size_t>(P > 0 ? P : 1) * 3 * tsize) : 0;
+    L.total = o;
+    return L;
+}
+
+// The energy path on a given scratch buffer (at least the layout's total)
+// and, for the atomic force path, a zeroed FP64 accumulator of 3 N doubles.
 template <typename T, int MODE = 1>
-int energy_forces_impl(pod_handle* h, int N, int P, const void* pos, const double* cell, const int* offsets,
-                       const int* nbr_j, const int* shift, const int* rev, const void* c, void* E_atom, double* E,
-                       void* F, double* W, double* G, const float* y_net = nullptr, const float* g_net = nullptr,
-                       int n_net = 0) {
+int energy_forces_run(pod_handle* h, char* scratch, double* facc, int N, int P, const void* pos, const double* cell,
+                      const int* offsets, const int* nbr_j, const int* shift, const int* rev, const void* c,
+                      void* E_atom, double* E, void* F, double* W, double* G, const float* y_net = nullptr,
+                      const float* g_net = nullptr, int n_net = 0) {
     KArgs<T> a;
     int rc = fill_args<T>(h, a, N, P, pos, cell, offsets, nbr_j, shift);
     if (rc != POD_OK) return rc;
     const int apw = WAVE / h->K;
     const int nblk = (N + apw - 1) / apw;
     const int ncol = 10 + h->M;
+    const bool back = (F != nullptr) || (W != nullptr);
     const bool gather = rev != nullptr && F != nullptr;
-    const size_t part_bytes = (static_cast<size_t>(ncol) * (nblk > 0 ? nblk : 1) * sizeof(double) + 255) & ~size_t(255);
-    const size_t g_bytes = gather ? (static_cast<size_t>(P > 0 ? P : 1) * 3 * sizeof(T) + 255) & ~size_t(255) : 0;
-    const size_t o_bytes = gather ? static_cast<size_t>(N > 0 ? N : 1) * 3 * sizeof(double) : 0;
-    rc = ensure_scratch(h, part_bytes + g_bytes + o_bytes);
-    if (rc != POD_OK) return rc;
-    rc = ensure_force_acc(h, N);
-    if (rc != POD_OK) return rc;
+    const int nblk_p = back ? (P + PAIR_BLOCK - 1) / PAIR_BLOCK : 0;
+    const EfScratch L = ef_scratch_layout(N, P, h->K, h->PA, h->M, sizeof(T), back, gather);
     a.coef = static_cast<const T*>(c);
     a.E_atom = static_cast<T*>(E_atom);
-    a.Facc = h->d_facc;
-    a.part = static_cast<double*>(h->d_scratch);
-    a.gbuf = gather ? reinterpret_cast<T*>(static_cast<char*>(h->d_scratch) + part_bytes) : nullptr;
-    a.fown = gather ? reinterpret_cast<double*>(static_cast<char*>(h->d_scratch) + part_bytes + g_bytes) : nullptr;
-    a.rev = gather ? rev : nullptr;
+    a.part = reinterpret_cast<double*>(scratch + L.part);
+    a.abar = back ? reinterpret_cast<T*>(scratch + L.abar) : nullptr;
+    a.centre = reinterpret_cast<int*>(scratch + L.centre);
+    a.pdv = reinterpret_cast<T*>(scratch + L.pdv);
     a.want_G = G != nullptr;
-    a.want_back = (F != nullptr) || (W != nullptr);
+    a.want_back = back;
     a.y_net = y_net; a.g_net = g_net; a.n_net = n_net;
     if (nblk > 0) {
         timing_begin(h, 1);
@@ -861,27 +1116,62 @@ int energy_forces_impl(pod_handle* h, int N, int P, const void* pos, const doubl
         timing_end(h, 1);
         if (e != hipSuccess) return POD_EHIP;
     }
+    PArgs<T> b;
+    b.prm = a.prm; b.N = N; b.P = P; b.pos = a.pos; b.cell = a.cell;
+    b.offsets = offsets; b.nbr_j = nbr_j; b.shift = shift;
+    b.rev = gather ? rev : nullptr;
+    b.abar = a.abar; b.centre = a.centre; b.pdv = a.pdv;
+    b.gbuf = gather ? reinterpret_cast<T*>(scratch + L.gbuf) : nullptr;
+    b.gown = gather ? reinterpret_cast<T*>(scratch + L.gown) : nullptr;
+    b.Facc = facc;
+    b.wpart = reinterpret_cast<double*>(scratch + L.wpart);
+    b.want_W = W != nullptr;
+    b.gate = 1;
+    b.err = h->d_err;
+    if (nblk_p > 0) {
+        timing_begin(h, 4);
+        const hipError_t e = dispatch_pair<T>(h->PA, b, h->std_ok != 0, nblk_p,
+                                              pair_lds_bytes(h->K, n_mono(h->PA), sizeof(T)), h->stream);
+        timing_end(h, 4);
+        if (e != hipSuccess) return POD_EHIP;
+    }
     // totals, and the forces: gathered from the per-pair gradients, or copied
     // out of the atomic accumulator (which is re-zeroed)
     FinArgs<T> fa;
-    fa.part = static_cast<const double*>(h->d_scratch);
+    fa.part = a.part;
     fa.nblk = nblk; fa.ncol = ncol;
-    fa.E = E; fa.W = a.want_back ? W : nullptr; fa.G = G;
-    fa.Facc = h->d_facc; fa.F = static_cast<T*>(F);
-    fa.n3 = (a.want_back && !gather) ? 3L * N : 0L;
-    fa.gbuf = a.gbuf; fa.fown = a.fown; fa.rev = gather ? rev : nullptr; fa.offsets = offsets;
+    fa.wpart = b.wpart; fa.nblk_p = nblk_p;
+    fa.E = E; fa.W = back ? W : nullptr; fa.G = G;
+    fa.Facc = facc; fa.F = static_cast<T*>(F);
+    fa.n3 = (back && !gather) ? 3L * N : 0L;
+    fa.gbuf = b.gbuf; fa.gown = b.gown; fa.rev = gather ? rev : nullptr; fa.offsets = offsets;
     fa.N = N; fa.P = P; fa.err = h->d_err;
     const int nfb = gather ? (N + 7) / 8 : static_cast<int>((fa.n3 + 255) / 256);
     if (E || W || G || nfb > 0) {
         timing_begin(h, 0);
         hipLaunchKernelGGL((finalize_kernel<T>), dim3(ncol + nfb), dim3(256), 0, h->stream, fa);
         timing_end(h, 0);
-        if (hipGetLastError() != hipSuccess) {
-            h->facc_dirty = 1;
-            return POD_EHIP;
-        }
+        if (hipGetLastError() != hipSuccess) return POD_EHIP;
     }
     return POD_OK;
+}
+
+template <typename T, int MODE = 1>
+int energy_forces_impl(pod_handle* h, int N, int P, const void* pos, const double* cell, const int* offsets,
+                       const int* nbr_j, const int* shift, const int* rev, const void* c, void* E_atom, double* E,
+                       void* F, double* W, double* G, const float* y_net = nullptr, const float* g_net = nullptr,
+                       int n_net = 0) {
+    const bool back = (F != nullptr) || (W != nullptr);
+    const bool gather = rev != nullptr && F != nullptr;
+    const EfScratch L = ef_scratch_layout(N, P, h->K, h->PA, h->M, sizeof(T), back, gather);
+    int rc = ensure_scratch(h, L.total);
+    if (rc != POD_OK) return rc;
+    rc = ensure_force_acc(h, N);
+    if (rc != POD_OK) return rc;
+    rc = energy_forces_run<T, MODE>(h, static_cast<char*>(h->d_scratch), h->d_facc, N, P, pos, cell, offsets, nbr_j,
+                                    shift, rev, c, E_atom, E, F, W, G, y_net, g_net, n_net);
+    if (rc == POD_EHIP && back && !gather) h->facc_dirty = 1;
+    return rc;
 }
 
 // Network surrogate of the 4-body term: descriptors, network forward and

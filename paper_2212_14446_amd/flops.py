@@ -88,3 +88,16 @@ def batch_counts(K, L, PA, P4, M, n_pairs, n_atoms):
     fwd = (c["radial_per_pair"] + c["forward_per_pair"]) * n_pairs + K * (3 * Na + 4 * NT) * n_atoms
     deriv = n_pairs * ((M - 1) * per_col + K * (Na - 1))
     return {"forward": fwd, "derivatives": deriv, "total": fwd + deriv, "per_pair_column": per_col}
+
+
+def split_counts(K, L, PA, P4=None):
+    """The same work divided between the two kernels of the energy path:
+    the per-atom kernel evaluates the snapshots and R = Phi Q, the atomic
+    basis, the contractions, energy and adjoint rows; the pair kernel
+    evaluates R' = Phi' Q and the backward sweep of each pair."""
+    c = counts(K, L, PA, P4)
+    proj = 2 * L * K
+    snap = c["radial_per_pair"] - 2 * proj
+    return {"atom_per_pair": snap + proj + c["forward_per_pair"], "per_atom": c["per_atom"],
+            "pair_per_pair": proj + c["backward_per_pair"]}
+

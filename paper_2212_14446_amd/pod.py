@@ -355,7 +355,8 @@ def pod_set_kernel_timing(h: Handle, n: int):
 
 
 def pod_get_kernel_time(h: Handle, kind: int = 1):
-    """(total ms, launches) of kernel `kind` (0 pair stage, 1 per-atom kernel)."""
+    """(total ms, launches) of kernel `kind` (0 finalize, 1 per-atom, 2 network,
+    3 fit Gram, 4 pair gradients)."""
     ms = ctypes.c_double()
     n = ctypes.c_int()
     _ok(lib().pod_get_kernel_time(h.ptr, int(kind), ctypes.byref(ms), ctypes.byref(n)), "pod_get_kernel_time")
