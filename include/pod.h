@@ -61,6 +61,7 @@ extern "C" {
 #define POD_ENOTSUP (-6)     /* parameters beyond what the kernels are built for */
 #define POD_ENEIGH (-7)      /* malformed neighbour list (offsets, index, shift) */
 #define POD_ESINGULAR (-8)   /* fit matrix not positive definite */
+#define POD_ETOOBIG (-9)     /* problem larger than the static scratch of pod_energy_forces_noalloc */
 
 #define POD_F64 0
 #define POD_F32 1
@@ -155,13 +156,16 @@ int pod_build_neighbors(pod_handle* h, int N, const void* pos, const double* cel
                         int* offsets, int* nbr_j, int* shift, long capacity, long* n_pairs);
 
 /* Linear POD energy and its derivatives (eqs. (57a), (58a), (26c), (24c)).
+ * Three kernels on the handle's stream: the per-atom kernel (atomic basis,
+ * contractions, energy, adjoint rows dE_i/dB_i), the pair kernel (g_p =
+ * dE_i/dr_ij of every pair, virial) and the finalize kernel (totals, forces).
  *   rev    : reverse-pair index from pod_neighbor_reverse, or NULL.  With it,
  *            forces are gathered per atom, F_n = sum_{p in N(n)} (g_p - g_rev(p))
  *            with g_p = dE_i/dr_ij, in a fixed order (bitwise reproducible):
- *            each g_p is stored at slot rev(p), so atom n's gather reads its
- *            own list range.  rev must be the list's reverse index (a pair
- *            without a reverse latches POD_ENEIGH).  Without rev, forces are
- *            accumulated with FP64 atomics.
+ *            each g_p is stored at its own slot p and at slot rev(p), so atom
+ *            n's gather reads its own list range.  rev must be the list's
+ *            reverse index (a pair without a reverse latches POD_ENEIGH).
+ *            Without rev, forces are accumulated with FP64 atomics.
  *   c      : M coefficients (device, handle dtype)
  *   E_atom : N per-atom energies (device, handle dtype) or NULL
  *   E      : total energy (device, 1 double) or NULL
@@ -173,6 +177,24 @@ int pod_build_neighbors(pod_handle* h, int N, const void* pos, const double* cel
 int pod_energy_forces(pod_handle* h, int N, int P, const void* pos, const double* cell,
                       const int* offsets, const int* nbr_j, const int* shift, const int* rev,
                       const void* c, void* E_atom, double* E, void* F, double* W, double* G);
+
+/* pod_energy_forces without any allocation, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving or
+ * dynamics loops, harnesses that forbid it.  Same arguments, kernels and
+ * results as pod_energy_forces; its scratch (block partials, adjoint rows,
+ * pair centres and vectors, pair gradients, and on the atomic path a
+ * force accumulator that it clears with a fill kernel) lives in a static
+ * device array of POD_STATIC_SCRATCH_BYTES per GPU, held from the first
+ * pod_init on that GPU until the process ends.  Returns POD_ETOOBIG, with
+ * nothing launched, when the call needs more: the 15,840-atom box of the
+ * benchmark (397,508 pairs, K = 6, angular degree 4, FP64) needs about 59 MB.
+ * Every call on one GPU uses the same array, which keeps the last call's
+ * contents: calls that overlap on one GPU (other streams, other handles,
+ * other threads) race and must be ordered by the caller. */
+#define POD_STATIC_SCRATCH_BYTES 67108864
+int pod_energy_forces_noalloc(pod_handle* h, int N, int P, const void* pos, const double* cell,
+                              const int* offsets, const int* nbr_j, const int* shift, const int* rev,
+                              const void* c, void* E_atom, double* E, void* F, double* W, double* G);
 
 /* Batched descriptor-matrix assembly for fitting (Sec. IV.A, eqs. (58a),
  * (63a)): many independent periodic cells in one persistent launch, FP64

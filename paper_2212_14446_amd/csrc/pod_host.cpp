@@ -338,10 +338,13 @@ int pod_init(const pod_params* p, void* hip_stream, pod_handle** out) {
     h->lds_max = 64 * 1024;
     {
         int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess) { delete h; return POD_EHIP; }
+        h->device = dev;
         hipDeviceProp_t prop;
-        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess &&
-            prop.sharedMemPerBlock > 0)
+        if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.sharedMemPerBlock > 0)
             h->lds_max = prop.sharedMemPerBlock;
+        // address of the allocation-free entry point's scratch on this device
+        if (pod::resolve_static_scratch(dev) != POD_OK) { delete h; return POD_EHIP; }
     }
     h->rin = p->rin; h->rcut = p->rcut; h->L = p->L;
     h->K2 = p->K2; h->K3 = p->K3; h->K4 = p->K4; h->P3 = p->P3; h->P4 = p->P4;
@@ -422,6 +425,7 @@ const char* pod_strerror(int code) {
         case POD_ENOTSUP: return "parameters beyond the compiled kernel limits";
         case POD_ENEIGH: return "malformed neighbour list";
         case POD_ESINGULAR: return "fit matrix not positive definite";
+        case POD_ETOOBIG: return "problem larger than the static scratch of the allocation-free entry point";
         default: return "unknown error";
     }
 }

@@ -66,6 +66,7 @@ struct CellT {
 
 struct pod_handle {
     int dtype;
+    int device;                // HIP device current at pod_init
     hipStream_t stream;
     double rin, rcut;
     int L, K2, K3, K4, P3, P4, K, PA, Ka4, M;
@@ -94,6 +95,10 @@ struct pod_handle {
 };
 
 namespace pod {
+// Device address of the static scratch array of pod_energy_forces_noalloc on
+// device `dev` (the current device): looked up once per device, POD_OK /
+// POD_EHIP.
+int resolve_static_scratch(int dev);
 // Grow the handle's scratch buffer to at least `bytes` (POD_OK / POD_ENOMEM).
 int ensure_scratch(pod_handle* h, size_t bytes);
 // Same for the network scratch buffer.

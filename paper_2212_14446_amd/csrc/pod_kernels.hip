@@ -26,6 +26,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 
 #include "pod.h"
 #include "pod_device.h"
@@ -33,7 +34,18 @@
 #include "pod_tables.h"
 
 namespace pod {
+
+// Scratch of pod_energy_forces_noalloc: one array per GPU, placed with the
+// code object.  Host code reaches it only through the device address
+// looked up by resolve_static_scratch (the array's name is not a device
+// address in host code).
+__device__ __align__(256) unsigned char scratch[POD_STATIC_SCRATCH_BYTES];
+
 namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
 
 using namespace dev;
 
@@ -1203,6 +1215,44 @@ int surrogate_impl(pod_handle* h, int N, int P, const void* pos, const double* c
                                     y, gr, n_in);
 }
 
+__global__ __launch_bounds__(256) void zero_kernel(double* p, long n) {
+    const long i = static_cast<long>(blockIdx.x) * 256 + threadIdx.x;
+    if (i < n) p[i] = 0.0;
+}
+
+// The energy path on the static scratch of this device: no allocation.
+template <typename T>
+int energy_forces_noalloc_impl(pod_handle* h, int N, int P, const void* pos, const double* cell,
+                               const int* offsets, const int* nbr_j, const int* shift, const int* rev, const void* c,
+                               void* E_atom, double* E, void* F, double* W, double* G) {
+    const bool back = (F != nullptr) || (W != nullptr);
+    const bool gather = rev != nullptr && F != nullptr;
+    const EfScratch L = ef_scratch_layout(N, P, h->K, h->PA, h->M, sizeof(T), back, gather);
+    const size_t facc_bytes = (back && !gather) ? ((static_cast<size_t>(N) * 3 * sizeof(double) + 255) & ~size_t(255))
+                                                : 0;
+    if (L.total + facc_bytes > static_cast<size_t>(POD_STATIC_SCRATCH_BYTES)) return POD_ETOOBIG;
+    if (h->device < 0 || h->device >= MAX_DEVICES) return POD_EHIP;
+    char* base;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        base = static_cast<char*>(g_scratch_ptr[h->device]);
+    }
+    if (!base) return POD_EHIP;
+    double* facc = nullptr;
+    if (facc_bytes > 0) {
+        // the atomic force path adds into a zeroed accumulator (a fill kernel,
+        // so that the call can be captured in a graph)
+        facc = reinterpret_cast<double*>(base + L.total);
+        const long n3 = 3L * N;
+        if (n3 > 0) {
+            hipLaunchKernelGGL(zero_kernel, dim3(static_cast<unsigned>((n3 + 255) / 256)), dim3(256), 0, h->stream, facc,
+                               n3);
+            if (hipGetLastError() != hipSuccess) return POD_EHIP;
+        }
+    }
+    return energy_forces_run<T, 1>(h, base, facc, N, P, pos, cell, offsets, nbr_j, shift, rev, c, E_atom, E, F, W, G);
+}
+
 bool bad_common(pod_handle* h, int N, int P, const void* pos, const int* offsets, const int* nbr_j,
                 const int* shift) {
     if (!h || N < 0 || P < 0) return true;
@@ -1212,6 +1262,17 @@ bool bad_common(pod_handle* h, int N, int P, const void* pos, const int* offsets
 }
 
 }  // namespace
+
+int resolve_static_scratch(int dev) {
+    if (dev < 0 || dev >= MAX_DEVICES) return POD_EHIP;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[dev]) return POD_OK;
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return POD_EHIP;
+    g_scratch_ptr[dev] = ptr;
+    return POD_OK;
+}
+
 }  // namespace pod
 
 extern "C" {
@@ -1234,6 +1295,18 @@ int pod_energy_forces(pod_handle* h, int N, int P, const void* pos, const double
         return pod::energy_forces_impl<double>(h, N, P, pos, cell, offsets, nbr_j, shift, rev, c, E_atom, E, F, W,
                                                G);
     return pod::energy_forces_impl<float>(h, N, P, pos, cell, offsets, nbr_j, shift, rev, c, E_atom, E, F, W, G);
+}
+
+int pod_energy_forces_noalloc(pod_handle* h, int N, int P, const void* pos, const double* cell, const int* offsets,
+                              const int* nbr_j, const int* shift, const int* rev, const void* c, void* E_atom,
+                              double* E, void* F, double* W, double* G) {
+    if (pod::bad_common(h, N, P, pos, offsets, nbr_j, shift)) return POD_EINVAL;
+    if (!c) return POD_EINVAL;
+    if (h->dtype == POD_F64)
+        return pod::energy_forces_noalloc_impl<double>(h, N, P, pos, cell, offsets, nbr_j, shift, rev, c, E_atom, E,
+                                                       F, W, G);
+    return pod::energy_forces_noalloc_impl<float>(h, N, P, pos, cell, offsets, nbr_j, shift, rev, c, E_atom, E, F,
+                                                  W, G);
 }
 
 int pod_energy_forces_surrogate(pod_handle* h, int N, int P, const void* pos, const double* cell,

@@ -25,7 +25,8 @@ POD_F64, POD_F32 = 0, 1
 POD_MAX_L, POD_MAX_K, POD_MAX_P = 16, 8, 6
 POD_MLP_HIDDEN, POD_MLP_MAX_IN = 64, 64
 ERRORS = {0: "POD_OK", -1: "POD_EINVAL", -2: "POD_ERANGE", -3: "POD_ENONFINITE", -4: "POD_ENOMEM",
-          -5: "POD_EHIP", -6: "POD_ENOTSUP", -7: "POD_ENEIGH", -8: "POD_ESINGULAR"}
+          -5: "POD_EHIP", -6: "POD_ENOTSUP", -7: "POD_ENEIGH", -8: "POD_ESINGULAR", -9: "POD_ETOOBIG"}
+POD_STATIC_SCRATCH_BYTES = 64 << 20
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _vp = ctypes.c_void_p
@@ -75,6 +76,7 @@ def lib():
     L.pod_get_basis.argtypes = [_vp, _dp, _dp]
     L.pod_descriptors.argtypes = [_vp, i, i, _vp, _dp, _vp, _vp, _vp, _vp]
     L.pod_energy_forces.argtypes = [_vp, i, i, _vp, _dp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+    L.pod_energy_forces_noalloc.argtypes = [_vp, i, i, _vp, _dp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
     L.pod_neighbor_reverse.argtypes = [_vp, i, i, _vp, _vp, _vp, _vp]
     L.pod_batch_assemble.argtypes = [_vp, i, i, i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, P(PodTuneC)]
     lg, f = ctypes.c_long, ctypes.c_float
@@ -108,7 +110,8 @@ def lib():
     L.pod_free.argtypes = [_vp]
     L.pod_free.restype = None
     for name in ("pod_init", "pod_compute_basis", "pod_num_descriptors", "pod_get_basis", "pod_descriptors",
-                 "pod_energy_forces", "pod_check", "pod_set_kernel_timing", "pod_get_kernel_time",
+                 "pod_energy_forces", "pod_energy_forces_noalloc", "pod_check", "pod_set_kernel_timing",
+                 "pod_get_kernel_time",
                  "pod_neighbor_reverse", "pod_batch_assemble", "pod_mlp_num_params", "pod_mlp_forward",
                  "pod_mlp_train_step", "pod_energy_forces_surrogate", "pod_build_neighbors", "pod_fit_gram",
                  "pod_fit_solve", "pod_opod_descriptors", "pod_opod_energy_forces", "pod_md_verlet",
@@ -302,6 +305,16 @@ def pod_energy_forces(h: Handle, N, P, pos, cell, offsets, nbr_j, shift, c, E_at
     _ok(lib().pod_energy_forces(h.ptr, int(N), int(P), _ptr(pos), cp, _ptr(offsets), _ptr(nbr_j), _ptr(shift),
                                 _ptr(rev), _ptr(c), _ptr(E_atom), _ptr(E), _ptr(F), _ptr(W), _ptr(G)),
         "pod_energy_forces")
+
+
+def pod_energy_forces_noalloc(h: Handle, N, P, pos, cell, offsets, nbr_j, shift, c, E_atom=None, E=None, F=None,
+                              W=None, G=None, rev=None):
+    """pod_energy_forces on the library's static scratch (no allocation)."""
+    arr, cp = _cell_ptr(cell)
+    _ok(lib().pod_energy_forces_noalloc(h.ptr, int(N), int(P), _ptr(pos), cp, _ptr(offsets), _ptr(nbr_j),
+                                        _ptr(shift), _ptr(rev), _ptr(c), _ptr(E_atom), _ptr(E), _ptr(F), _ptr(W),
+                                        _ptr(G)),
+        "pod_energy_forces_noalloc")
 
 
 def pod_batch_assemble(h: Handle, n_cfg, N, P, cfg_atom_off, pos, cells, offsets, nbr_j, shift, D=None, G=None,
