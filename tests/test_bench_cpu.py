@@ -26,3 +26,18 @@ def test_flop_model_counts():
     b = fl.batch_counts(6, 8, 4, 4, 103, 1000, 40)
     assert b["per_pair_column"] == 212
     assert b["derivatives"] == 1000 * (102 * 212 + 6 * 34)
+
+
+def test_flop_split_between_kernels():
+    # the two kernels of the energy path share the per-pair work without
+    # double counting: snapshots and R in the atom kernel, R' and the
+    # backward sweep in the pair kernel
+    sys.path.insert(0, ROOT)
+    from paper_2212_14446_amd import flops as fl
+    c = fl.counts(6, 8, 4, 4)
+    sp = fl.split_counts(6, 8, 4, 4)
+    assert sp["atom_per_pair"] + sp["pair_per_pair"] == (c["radial_per_pair"] + c["forward_per_pair"]
+                                                         + c["backward_per_pair"])
+    assert sp["per_atom"] == c["per_atom"]
+    assert sp["pair_per_pair"] == 2 * 8 * 6 + c["backward_per_pair"]
+
