@@ -807,6 +807,17 @@ __device__ __forceinline__ void pair_block(const PArgs<T>& g, int blk, T* sAb, d
     }
 }
 
+// Workgroups are dealt to the eight XCDs of the chip in turn (workgroup i
+// runs on XCD i mod 8).  The pair blocks are renumbered so that each XCD
+// takes one contiguous range of them: neighbouring blocks share centre
+// atoms, whose adjoint rows are then fetched once into that XCD's L2.
+__device__ __forceinline__ int xcd_block(int i, int n) {
+    constexpr int NX = 8;
+    const int x = i % NX, k = i / NX;
+    const int per = n / NX, rem = n % NX;
+    return x * per + (x < rem ? x : rem) + k;
+}
+
 // KK: the radial count when fixed at compile time (4 or 6), 0 for any K.
 // Wavefront w takes pairs 64 w .. 64 w + 63.
 template <typename T, int PA, int KK, bool FAST>
@@ -814,8 +825,8 @@ __device__ __forceinline__ void pair_body(const PArgs<T>& g) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* sAb = reinterpret_cast<T*>(smem_raw);
     const int lane = threadIdx.x;
-    const int w = blockIdx.x;
     const int nblk = gridDim.x;
+    const int w = xcd_block(blockIdx.x, nblk);
     double vir[9];
 #pragma unroll
     for (int x = 0; x < 9; ++x) vir[x] = 0.0;
