@@ -20,8 +20,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libpod.so")
 OBJDIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["pod_host.cpp", "pod_kernels.hip", "pod_batch.hip", "pod_mlp.hip", "pod_neighbors.hip", "pod_fit.hip",
-           "pod_opod.hip", "pod_md.hip", "pod_acsf.hip", "pod_five.hip"]
+SOURCES = ["pod_host.cpp", "pod_plan.cpp", "pod_kernels.hip", "pod_batch.hip", "pod_mlp.hip", "pod_neighbors.hip",
+           "pod_fit.hip", "pod_opod.hip", "pod_md.hip", "pod_acsf.hip", "pod_five.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
@@ -50,6 +50,40 @@ def _jobs() -> int:
         if v and v.isdigit() and int(v) > 0:
             return min(int(v), 16)
     return max(1, min(os.cpu_count() or 1, 16))
+
+
+def kernel_resources(src: str = "pod_kernels.hip") -> dict:
+    """Register and scratch use of every kernel instance of one source, from
+    the compiler's resource-usage remarks of a device-only gfx950 compile
+    with the library's flags: {demangled name: {"vgpr", "agpr", "scratch"
+    (bytes per lane), "occupancy" (waves per SIMD)}}."""
+    import re
+    import tempfile
+    with tempfile.TemporaryDirectory() as td:
+        cmd = [hipcc(), *HIPCC_FLAGS, "--offload-device-only", "-Rpass-analysis=kernel-resource-usage",
+               "-I", INCLUDE, "-I", CSRC, "-c", "-o", os.path.join(td, "k.o"), os.path.join(CSRC, src)]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"compilation of {src} failed:\n{r.stderr[-4000:]}")
+    rows, cur = [], None
+    keys = {"VGPRs:": "vgpr", "AGPRs:": "agpr", "ScratchSize [bytes/lane]:": "scratch",
+            "Occupancy [waves/SIMD]:": "occupancy"}
+    for line in r.stderr.splitlines():
+        m = re.search(r"Function Name: (\S+)", line)
+        if m:
+            cur = {"mangled": m.group(1)}
+            rows.append(cur)
+            continue
+        for k, name in keys.items():
+            if cur is not None and k in line:
+                cur[name] = int(line.split(k)[1].split()[0])
+    names = subprocess.run(["c++filt"], input="\n".join(r_["mangled"] for r_ in rows), capture_output=True,
+                           text=True, check=True).stdout.splitlines()
+    out = {}
+    for row, name in zip(rows, names):
+        name = name.replace("pod::(anonymous namespace)::", "")
+        out[name] = {k: row.get(k) for k in keys.values()}
+    return out
 
 
 def build(verbose: bool = True, extra=None, out: str = LIB) -> str:

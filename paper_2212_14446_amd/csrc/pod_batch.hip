@@ -27,6 +27,7 @@
 #include "pod.h"
 #include "pod_device.h"
 #include "pod_internal.h"
+#include "pod_plan.h"
 #include "pod_tables.h"
 
 namespace pod {
@@ -34,7 +35,7 @@ namespace {
 
 using namespace dev;
 
-constexpr int MAX_THREADS = 512;
+constexpr int MAX_THREADS = BATCH_MAX_THREADS;
 
 struct BArgs {
     ParamsT<double> prm;  // by value: read with scalar loads
@@ -55,21 +56,6 @@ struct BArgs {
     int cw, nc_max;
     int* err;
 };
-
-struct BatchLds {
-    size_t q, gsum, acc, off, total;
-};
-
-__host__ __device__ inline BatchLds batch_lds(int M, int cw, int nc_max) {
-    BatchLds L;
-    const size_t d = sizeof(double);
-    L.q = 0;
-    L.gsum = L.q + static_cast<size_t>(POD_MAX_L) * POD_MAX_K * d;
-    L.acc = L.gsum + static_cast<size_t>(M + 1) * d;
-    L.off = L.acc + static_cast<size_t>(nc_max) * 3 * cw * d;
-    L.total = L.off + static_cast<size_t>(nc_max + 1) * sizeof(int);
-    return L;
-}
 
 // Global column of local column lc of radial index m, laid out per m as
 // [D2_m] [D3_m,0..P3] [D4_m,0..Ka4-1] (each present when m is below K2, K3, K4).
@@ -406,37 +392,18 @@ int pod_batch_assemble(pod_handle* h, int n_cfg, int N, int P, const int* cfg_at
         hipMemcpyAsync(off.data(), offsets, sizeof(int) * (N + 1), hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
         hipStreamSynchronize(h->stream) != hipSuccess)
         return POD_EHIP;
-    if (coff[0] != 0 || coff[n_cfg] != N || off[0] != 0 || off[N] != P) return POD_EINVAL;
-    std::vector<int> npair(n_cfg);
-    int max_nc = 0, max_pc = 0;
-    for (int c = 0; c < n_cfg; ++c) {
-        if (coff[c + 1] < coff[c]) return POD_EINVAL;
-        const int nc = coff[c + 1] - coff[c];
-        for (int a = coff[c]; a < coff[c + 1]; ++a)
-            if (off[a + 1] < off[a]) return POD_ENEIGH;
-        npair[c] = off[coff[c + 1]] - off[coff[c]];
-        max_nc = std::max(max_nc, nc);
-        max_pc = std::max(max_pc, npair[c]);
-    }
+    BatchPlan plan;
+    int rc = plan_batch(n_cfg, N, P, coff.data(), off.data(), h->M, h->lds_max, tune, &plan);
+    if (rc != POD_OK) return rc;
     const int NA = n_mono(h->PA);
-    int cw = tune && tune->cw > 0 ? tune->cw : 17;
-    int nblk = tune && tune->nblocks > 0 ? tune->nblocks : 512;
-    const int nth = tune && tune->threads > 0 ? tune->threads : 512;
-    if (nth % 64 != 0 || nth > MAX_THREADS) return POD_EINVAL;
-    nblk = std::min(nblk, n_cfg);
-    const int nc_max = ((max_nc + 15) / 16) * 16;
-    while (cw > 1 && batch_lds(h->M, cw, nc_max).total > h->lds_max) --cw;
-    const size_t lds = batch_lds(h->M, cw, nc_max).total;
-    if (lds > h->lds_max) return POD_ENOTSUP;   // a cell too large for the LDS accumulator
-    // cells by decreasing pair count, dealt round-robin to the workgroups
-    std::vector<int> order(n_cfg);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return npair[x] > npair[y]; });
+    const int nblk = plan.nblk, nth = plan.nth;
+    const size_t lds = plan.lds;
+    const std::vector<int>& order = plan.order;
     const int SR = 4 + 2 * h->K;
-    const long rec_cap = std::max(max_pc, 1), b_cap = std::max(max_nc, 1);
+    const long rec_cap = std::max(plan.max_pc, 1), b_cap = std::max(plan.max_nc, 1);
     const size_t per_blk = static_cast<size_t>(rec_cap) * SR + static_cast<size_t>(b_cap) * h->K * NA;
     const size_t order_bytes = ((sizeof(int) * n_cfg + 255) / 256) * 256;
-    int rc = ensure_scratch(h, order_bytes + per_blk * nblk * sizeof(double));
+    rc = ensure_scratch(h, order_bytes + per_blk * nblk * sizeof(double));
     if (rc != POD_OK) return rc;
     int* d_order = static_cast<int*>(h->d_scratch);
     if (hipMemcpyAsync(d_order, order.data(), sizeof(int) * n_cfg, hipMemcpyHostToDevice, h->stream) != hipSuccess)
@@ -450,7 +417,7 @@ int pod_batch_assemble(pod_handle* h, int n_cfg, int N, int P, const int* cfg_at
     a.D = D; a.G = G; a.dGdR = dGdR;
     a.scratch = reinterpret_cast<double*>(static_cast<char*>(h->d_scratch) + order_bytes);
     a.rec_cap = rec_cap; a.b_cap = b_cap;
-    a.cw = cw; a.nc_max = nc_max;
+    a.cw = plan.cw; a.nc_max = plan.nc_max;
     a.err = h->d_err;
     timing_begin(h, 1);
     const hipError_t e = dispatch_batch(h->PA, a, h->std_ok != 0, nblk, nth, lds, h->stream);

@@ -1,5 +1,6 @@
-// Host side of libpod: parameter validation, the POD radial basis (Sec. II.B,
-// eq. (12)), device parameter upload, error reporting and teardown.
+// Host side of libpod: handle set-up (kernel parameter block, device buffers),
+// error-word readout, kernel timing and teardown.  Validation and the POD basis
+// live in pod_plan.cpp.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -10,130 +11,12 @@
 
 #include "pod.h"
 #include "pod_internal.h"
+#include "pod_plan.h"
 #include "pod_tables.h"
 
 namespace {
 
 constexpr double kPi = 3.14159265358979323846;
-constexpr double kEpsCut = 1e-6;  // epsilon of the cut-off function, eq. (8)
-
-bool finite(double v) { return std::isfinite(v); }
-
-int validate(const pod_params* p) {
-    if (!p) return POD_EINVAL;
-    if (!finite(p->rin) || !finite(p->rcut) || p->rin < 0.0 || !(p->rin < p->rcut)) return POD_EINVAL;
-    if (p->L < 1) return POD_EINVAL;
-    if (p->L > POD_MAX_L) return POD_ENOTSUP;
-    if (!p->alpha || !p->beta || !p->gamma || !p->kappa) return POD_EINVAL;
-    for (int l = 0; l < p->L; ++l) {
-        if (!finite(p->alpha[l]) || !finite(p->beta[l]) || !finite(p->gamma[l]) || !finite(p->kappa[l]))
-            return POD_EINVAL;
-        if (p->kappa[l] < 0.0 || p->kappa[l] > 1.0 || p->beta[l] < 0.0) return POD_EINVAL;
-    }
-    if (p->K2 < 0 || p->K3 < 0 || p->K4 < 0 || p->P3 < 0 || p->P4 < 0) return POD_EINVAL;
-    const int K = std::max(p->K2, std::max(p->K3, p->K4));
-    if (K < 1 || K > p->L) return POD_EINVAL;
-    if (K > POD_MAX_K) return POD_ENOTSUP;
-    if (p->P3 > POD_MAX_P || p->P4 > POD_MAX_P) return POD_ENOTSUP;
-    if (p->dtype != POD_F64 && p->dtype != POD_F32) return POD_EINVAL;
-    if (p->n_quad != 0 && p->n_quad < 2 * p->L) return POD_EINVAL;
-    if (p->Q) {
-        for (int i = 0; i < p->L * K; ++i)
-            if (!finite(p->Q[i])) return POD_EINVAL;
-    }
-    return POD_OK;
-}
-
-// Snapshot l at distance r (host, double), straight from eqs. (3)-(8).
-double snapshot_host(const pod_params* p, int l, double r) {
-    const double h = p->rcut - p->rin;
-    const double t = (r - p->rin) / h;
-    const double y = 1.0 - t * t * t;
-    const double fc = std::exp(1.0 - 1.0 / std::sqrt(y * y + kEpsCut));
-    double psi = 0.0;
-    const double kap = p->kappa[l];
-    if (kap != 0.0) {
-        const double b = p->beta[l];
-        const double x = (b == 0.0) ? t : std::expm1(-b * t) / std::expm1(-b);
-        psi += kap * std::sin(p->alpha[l] * kPi * x) / (r - p->rin);
-    }
-    if (kap != 1.0) psi += (1.0 - kap) * std::pow(r, -p->gamma[l]);
-    return fc * psi;
-}
-
-// Cyclic Jacobi eigensolver for a small symmetric matrix (row-major, n x n).
-// On return A's diagonal holds the eigenvalues and V (row-major) the
-// eigenvectors as columns.
-void jacobi_eigen(std::vector<double>& A, std::vector<double>& V, int n) {
-    V.assign(static_cast<size_t>(n) * n, 0.0);
-    for (int i = 0; i < n; ++i) V[i * n + i] = 1.0;
-    for (int sweep = 0; sweep < 100; ++sweep) {
-        double off = 0.0, tot = 0.0;
-        for (int i = 0; i < n; ++i)
-            for (int j = 0; j < n; ++j) {
-                tot += A[i * n + j] * A[i * n + j];
-                if (i != j) off += A[i * n + j] * A[i * n + j];
-            }
-        if (off <= 1e-30 * tot) break;
-        for (int pidx = 0; pidx < n - 1; ++pidx)
-            for (int q = pidx + 1; q < n; ++q) {
-                const double apq = A[pidx * n + q];
-                if (std::fabs(apq) < 1e-300) continue;
-                const double app = A[pidx * n + pidx], aqq = A[q * n + q];
-                const double theta = (aqq - app) / (2.0 * apq);
-                const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
-                const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
-                for (int k = 0; k < n; ++k) {  // A <- A J (columns p, q)
-                    const double akp = A[k * n + pidx], akq = A[k * n + q];
-                    A[k * n + pidx] = c * akp - s * akq;
-                    A[k * n + q] = s * akp + c * akq;
-                }
-                for (int k = 0; k < n; ++k) {  // A <- J^T A (rows p, q)
-                    const double apk = A[pidx * n + k], aqk = A[q * n + k];
-                    A[pidx * n + k] = c * apk - s * aqk;
-                    A[q * n + k] = s * apk + c * aqk;
-                }
-                for (int k = 0; k < n; ++k) {
-                    const double vkp = V[k * n + pidx], vkq = V[k * n + q];
-                    V[k * n + pidx] = c * vkp - s * vkq;
-                    V[k * n + q] = s * vkp + c * vkq;
-                }
-            }
-    }
-}
-
-int compute_basis(const pod_params* p, std::vector<double>& Q, std::vector<double>& eig) {
-    const int L = p->L;
-    const int nq = p->n_quad > 0 ? p->n_quad : 2000;
-    const double h = (p->rcut - p->rin) / nq;
-    std::vector<double> C(static_cast<size_t>(L) * L, 0.0), phi(L);
-    for (int s = 0; s < nq; ++s) {
-        const double r = p->rin + (s + 0.5) * h;
-        for (int l = 0; l < L; ++l) phi[l] = snapshot_host(p, l, r);
-        for (int a = 0; a < L; ++a)
-            for (int b = 0; b < L; ++b) C[a * L + b] += phi[a] * phi[b];
-    }
-    for (double& v : C) v /= nq;
-    std::vector<double> V;
-    jacobi_eigen(C, V, L);
-    std::vector<int> order(L);
-    for (int i = 0; i < L; ++i) order[i] = i;
-    std::sort(order.begin(), order.end(), [&](int a, int b) { return C[a * L + a] > C[b * L + b]; });
-    Q.assign(static_cast<size_t>(L) * L, 0.0);
-    eig.assign(L, 0.0);
-    for (int k = 0; k < L; ++k) {
-        const int src = order[k];
-        eig[k] = C[src * L + src];
-        int big = 0;
-        for (int l = 1; l < L; ++l)
-            if (std::fabs(V[l * L + src]) > std::fabs(V[big * L + src])) big = l;
-        const double sgn = V[big * L + src] < 0 ? -1.0 : 1.0;
-        for (int l = 0; l < L; ++l) Q[l * L + k] = sgn * V[l * L + src];
-        for (int l = 0; l < L; ++l)
-            if (!std::isfinite(Q[l * L + k])) return POD_EINVAL;
-    }
-    return POD_OK;
-}
 
 template <typename T>
 void fill_params(const pod_handle* h, pod::ParamsT<T>& d) {
@@ -315,21 +198,10 @@ int pod_get_kernel_time(pod_handle* h, int kind, double* total_ms, int* launches
     return POD_OK;
 }
 
-int pod_compute_basis(const pod_params* p, double* Q, double* eigvals) {
-    const int rc = validate(p);
-    if (rc != POD_OK) return rc;
-    std::vector<double> q, e;
-    const int r2 = compute_basis(p, q, e);
-    if (r2 != POD_OK) return r2;
-    if (Q) std::memcpy(Q, q.data(), q.size() * sizeof(double));
-    if (eigvals) std::memcpy(eigvals, e.data(), e.size() * sizeof(double));
-    return POD_OK;
-}
-
 int pod_init(const pod_params* p, void* hip_stream, pod_handle** out) {
     if (!out) return POD_EINVAL;
     *out = nullptr;
-    int rc = validate(p);
+    int rc = pod::validate_params(p);
     if (rc != POD_OK) return rc;
     pod_handle* h = new (std::nothrow) pod_handle();
     if (!h) return POD_ENOMEM;
@@ -365,7 +237,7 @@ int pod_init(const pod_params* p, void* hip_stream, pod_handle** out) {
         h->eig.assign(p->L, 0.0);
     } else {
         std::vector<double> qfull;
-        rc = compute_basis(p, qfull, h->eig);
+        rc = pod::compute_basis(p, qfull, h->eig);
         if (rc != POD_OK) { delete h; return rc; }
         h->Q.assign(static_cast<size_t>(p->L) * h->K, 0.0);
         for (int l = 0; l < p->L; ++l)
@@ -412,22 +284,6 @@ int pod_check(pod_handle* h) {
     if (word & pod::ERR_NONFINITE) return POD_ENONFINITE;
     if (word & pod::ERR_RANGE) return POD_ERANGE;
     return POD_OK;
-}
-
-const char* pod_strerror(int code) {
-    switch (code) {
-        case POD_OK: return "ok";
-        case POD_EINVAL: return "invalid argument";
-        case POD_ERANGE: return "pair distance at or below rin";
-        case POD_ENONFINITE: return "non-finite coordinate";
-        case POD_ENOMEM: return "device allocation failed";
-        case POD_EHIP: return "HIP runtime error";
-        case POD_ENOTSUP: return "parameters beyond the compiled kernel limits";
-        case POD_ENEIGH: return "malformed neighbour list";
-        case POD_ESINGULAR: return "fit matrix not positive definite";
-        case POD_ETOOBIG: return "problem larger than the static scratch of the allocation-free entry point";
-        default: return "unknown error";
-    }
 }
 
 void pod_free(pod_handle* h) {

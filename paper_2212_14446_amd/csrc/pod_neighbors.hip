@@ -11,7 +11,8 @@
 // pass writes (j, packed image shift) in the same fixed order.
 #include <hip/hip_runtime.h>
 
-#include <hipcub/hipcub.hpp>
+#include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_scan.hpp>
 
 #include <algorithm>
 #include <cmath>
@@ -19,25 +20,13 @@
 
 #include "pod.h"
 #include "pod_internal.h"
+#include "pod_plan.h"
 
 namespace pod {
 namespace {
 
 constexpr int NB_THREADS = 256;
-constexpr int NB_MAX_BINS = 256;   // per direction (wider bins stay correct)
-constexpr int NB_MAX_SPAN = 64;    // search half-width in bins
 constexpr int NB_MAX_WRAP = 1 << 20;   // |lattice vectors| between an atom and its home cell
-
-struct NbGeom {
-    double a[9];     // periodic: lattice vectors as rows
-    double inv[9];   // periodic: inverse of a, fractional s = r inv
-    double lo[3];    // open: bounding-box origin
-    double bw[3];    // open: bin width
-    double rl2;      // r_list^2
-    int nb[3];       // bins per direction
-    int ns[3];       // search half-width in bins
-    int periodic;
-};
 
 __device__ __forceinline__ int floor_div(int a, int b) {
     const int q = a / b;
@@ -186,27 +175,10 @@ __global__ __launch_bounds__(NB_THREADS) void offsets_kernel(int N, const long* 
     if (i == N) total[0] = v;
 }
 
-double det3(const double* a) {
-    return a[0] * (a[4] * a[8] - a[5] * a[7]) - a[1] * (a[3] * a[8] - a[5] * a[6]) + a[2] * (a[3] * a[7] - a[4] * a[6]);
-}
-
-void invert3(const double* a, double* inv, double det) {
-    const double id = 1.0 / det;
-    inv[0] = (a[4] * a[8] - a[5] * a[7]) * id;
-    inv[1] = (a[2] * a[7] - a[1] * a[8]) * id;
-    inv[2] = (a[1] * a[5] - a[2] * a[4]) * id;
-    inv[3] = (a[5] * a[6] - a[3] * a[8]) * id;
-    inv[4] = (a[0] * a[8] - a[2] * a[6]) * id;
-    inv[5] = (a[2] * a[3] - a[0] * a[5]) * id;
-    inv[6] = (a[3] * a[7] - a[4] * a[6]) * id;
-    inv[7] = (a[1] * a[6] - a[0] * a[7]) * id;
-    inv[8] = (a[0] * a[4] - a[1] * a[3]) * id;
-}
-
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 // Bounding box of an open system (host copy of the positions).
-int open_geometry(pod_handle* h, int N, const void* pos, double rlist, NbGeom* g) {
+int open_geometry_dev(pod_handle* h, int N, const void* pos, double rlist, NbGeom* g) {
     std::vector<double> hp(3 * static_cast<size_t>(N));
     if (h->dtype == POD_F64) {
         if (hipMemcpyAsync(hp.data(), pos, hp.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream) !=
@@ -221,24 +193,7 @@ int open_geometry(pod_handle* h, int N, const void* pos, double rlist, NbGeom* g
             return POD_EHIP;
         for (size_t k = 0; k < hf.size(); ++k) hp[k] = hf[k];
     }
-    for (int d = 0; d < 3; ++d) {
-        double lo = 0.0, hi = 0.0;
-        bool any = false;
-        for (int i = 0; i < N; ++i) {
-            const double v = hp[3 * static_cast<size_t>(i) + d];
-            if (!std::isfinite(v)) continue;   // latched by the bin kernel
-            lo = any ? std::min(lo, v) : v;
-            hi = any ? std::max(hi, v) : v;
-            any = true;
-        }
-        const double ext = hi - lo;
-        const int nbd = static_cast<int>(std::min<double>(NB_MAX_BINS, std::floor(ext / rlist) + 1.0));
-        g->lo[d] = lo;
-        g->nb[d] = std::max(1, nbd);
-        g->bw[d] = std::max(rlist, ext / g->nb[d] * (1.0 + 1e-12));
-        g->ns[d] = 1;
-    }
-    return POD_OK;
+    return open_geometry(hp.data(), N, rlist, g);
 }
 
 }  // namespace
@@ -262,47 +217,25 @@ int pod_build_neighbors(pod_handle* h, int N, const void* pos, const double* cel
         return hipStreamSynchronize(h->stream) == hipSuccess ? POD_OK : POD_EHIP;
     }
     NbGeom g{};
-    g.rl2 = rlist * rlist;
-    g.periodic = cell != nullptr;
-    if (g.periodic) {
-        for (int k = 0; k < 9; ++k) {
-            if (!std::isfinite(cell[k])) return POD_EINVAL;
-            g.a[k] = cell[k];
-        }
-        const double det = det3(g.a);
-        if (!(std::fabs(det) > 0.0) || !std::isfinite(det)) return POD_EINVAL;
-        invert3(g.a, g.inv, det);
-        for (int d = 0; d < 3; ++d) {
-            // spacing of the lattice planes normal to direction d: V / |a_e x a_f|
-            const double* ae = g.a + 3 * ((d + 1) % 3);
-            const double* af = g.a + 3 * ((d + 2) % 3);
-            const double cx = ae[1] * af[2] - ae[2] * af[1], cy = ae[2] * af[0] - ae[0] * af[2],
-                         cz = ae[0] * af[1] - ae[1] * af[0];
-            const double hd = std::fabs(det) / std::sqrt(cx * cx + cy * cy + cz * cz);
-            g.nb[d] = static_cast<int>(std::max(1.0, std::min<double>(NB_MAX_BINS, std::floor(hd / rlist))));
-            const double span = std::ceil(rlist * g.nb[d] / hd * (1.0 + 1e-12));
-            if (span > NB_MAX_SPAN) return POD_ENOTSUP;
-            g.ns[d] = static_cast<int>(span);
-        }
-    } else {
-        const int rc = open_geometry(h, N, pos, rlist, &g);
+    {
+        const int rc = cell ? periodic_geometry(cell, rlist, &g) : open_geometry_dev(h, N, pos, rlist, &g);
         if (rc != POD_OK) return rc;
     }
     const long nbins = static_cast<long>(g.nb[0]) * g.nb[1] * g.nb[2];
     int key_bits = 1;
     while ((1L << key_bits) < nbins) ++key_bits;
 
-    size_t cub_sort = 0, cub_scan = 0;
-    if (hipcub::DeviceRadixSort::SortPairs(nullptr, cub_sort, static_cast<int*>(nullptr), static_cast<int*>(nullptr),
-                                           static_cast<int*>(nullptr), static_cast<int*>(nullptr), N, 0, key_bits,
-                                           h->stream) != hipSuccess ||
-        hipcub::DeviceScan::ExclusiveSum(nullptr, cub_scan, static_cast<long*>(nullptr), static_cast<long*>(nullptr),
-                                         N + 1, h->stream) != hipSuccess)
+    size_t sort_bytes = 0, scan_bytes = 0;
+    if (rocprim::radix_sort_pairs(nullptr, sort_bytes, static_cast<int*>(nullptr), static_cast<int*>(nullptr),
+                                  static_cast<int*>(nullptr), static_cast<int*>(nullptr), N, 0u,
+                                  static_cast<unsigned>(key_bits), h->stream) != hipSuccess ||
+        rocprim::exclusive_scan(nullptr, scan_bytes, static_cast<long*>(nullptr), static_cast<long*>(nullptr), 0L,
+                                static_cast<size_t>(N) + 1, rocprim::plus<long>(), h->stream) != hipSuccess)
         return POD_EHIP;
     const size_t n1 = static_cast<size_t>(N) + 1;
     const size_t sI = align256(sizeof(int) * n1), sL = align256(sizeof(long) * n1);
     const size_t sP = align256(sizeof(double) * 3 * n1), sW = align256(sizeof(int) * 3 * n1);
-    const size_t sB = align256(sizeof(int) * static_cast<size_t>(nbins)), sT = align256(std::max(cub_sort, cub_scan));
+    const size_t sB = align256(sizeof(int) * static_cast<size_t>(nbins)), sT = align256(std::max(sort_bytes, scan_bytes));
     const int rc = ensure_scratch(h, 4 * sI + 2 * sL + 2 * sP + sW + 2 * sB + sT);
     if (rc != POD_OK) return rc;
     char* base = static_cast<char*>(h->d_scratch);
@@ -327,8 +260,8 @@ int pod_build_neighbors(pod_handle* h, int N, const void* pos, const double* cel
         hipLaunchKernelGGL((bin_kernel<float>), gb, tb, 0, h->stream, N, static_cast<const float*>(pos), g, key, idx,
                            wpos, wrap, h->d_err);
     size_t tbytes = sT;
-    if (hipcub::DeviceRadixSort::SortPairs(tmp, tbytes, key, key_s, idx, idx_s, N, 0, key_bits, h->stream) !=
-        hipSuccess)
+    if (rocprim::radix_sort_pairs(tmp, tbytes, key, key_s, idx, idx_s, N, 0u, static_cast<unsigned>(key_bits),
+                                  h->stream) != hipSuccess)
         return POD_EHIP;
     const dim3 gbins(static_cast<unsigned>((nbins + NB_THREADS - 1) / NB_THREADS));
     hipLaunchKernelGGL(fill_int_kernel, gbins, tb, 0, h->stream, start, nbins, 0);
@@ -338,7 +271,9 @@ int pod_build_neighbors(pod_handle* h, int N, const void* pos, const double* cel
                        cnt, nullptr, nullptr, nullptr, h->d_err);
     hipLaunchKernelGGL(fill_int_kernel, dim3(1), tb, 0, h->stream, reinterpret_cast<int*>(cnt + N), 2L, 0);
     tbytes = sT;
-    if (hipcub::DeviceScan::ExclusiveSum(tmp, tbytes, cnt, off64, N + 1, h->stream) != hipSuccess) return POD_EHIP;
+    if (rocprim::exclusive_scan(tmp, tbytes, cnt, off64, 0L, static_cast<size_t>(N) + 1, rocprim::plus<long>(),
+                                h->stream) != hipSuccess)
+        return POD_EHIP;
     hipLaunchKernelGGL(offsets_kernel, gb, tb, 0, h->stream, N, off64, offsets, cnt);
     long P = 0;
     if (hipMemcpyAsync(&P, cnt, sizeof(long), hipMemcpyDeviceToHost, h->stream) != hipSuccess ||

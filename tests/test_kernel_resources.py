@@ -1,0 +1,44 @@
+"""Register and scratch use of the energy path's benchmark kernel instances
+(FP64 and FP32, K = 6, angular degree 4, standard snapshot family), read
+from the compiler's resource-usage remarks of a device-only gfx950 compile
+of csrc/pod_kernels.hip with the library's flags.  The test fails when an
+instance spills (scratch above the recorded bound) or loses occupancy, so a
+change that pushes a hot kernel into scratch memory is caught on the CPU."""
+import shutil
+
+import pytest
+
+from paper_2212_14446_amd import build_lib
+
+# instance: (max scratch bytes per lane, min waves per SIMD, VGPRs when recorded)
+RECORDED = {
+    "void atom_kernel_occ2<double, 4, 1, true>(KArgs<double>)": (0, 2, 223),
+    "void atom_kernel<float, 4, 1, true>(KArgs<float>)": (0, 4, 110),
+    "void pair_kernel<double, 4, 6, true>(PArgs<double>)": (0, 4, 128),
+    "void pair_kernel<float, 4, 6, true>(PArgs<float>)": (0, 7, 72),
+    "void finalize_kernel<double>(FinArgs<double>)": (0, 8, 28),
+    "void finalize_kernel<float>(FinArgs<float>)": (0, 8, 28),
+}
+
+
+@pytest.fixture(scope="module")
+def resources():
+    if not shutil.which(build_lib.hipcc()) and not shutil.which("hipcc"):
+        pytest.skip("hipcc not available")
+    return build_lib.kernel_resources("pod_kernels.hip")
+
+
+@pytest.mark.parametrize("name", sorted(RECORDED))
+def test_benchmark_instance_within_recorded_registers(resources, name):
+    assert name in resources, f"instance {name} not compiled"
+    max_scratch, min_occ, _ = RECORDED[name]
+    r = resources[name]
+    assert r["scratch"] <= max_scratch, (name, r)
+    assert r["occupancy"] >= min_occ, (name, r)
+
+
+def test_no_energy_path_instance_spills_much(resources):
+    # every instance of the energy path: at most the 20 bytes per lane of the
+    # degree-6 FP64 descriptor instance (one wavefront per SIMD, 256 + 256 registers)
+    worst = max((r["scratch"], n) for n, r in resources.items())
+    assert worst[0] <= 20, worst
