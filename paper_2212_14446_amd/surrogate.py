@@ -106,21 +106,31 @@ def fit(h: pod.Handle, net: Network, X, target, epochs: int = 20, batch: int = 8
     return history
 
 
-def four_body_dataset(model, boxes, c, n_in: int):
-    """Training rows from full 2/3/4-body systems: inputs are the 2/3-body
-    descriptors (columns 1..n_in of D) and labels the exact per-atom 4-body
-    energies sum_{k in 4-body} c_k D_ik, both computed by the library
+def four_body_dataset(model, boxes, c, n_in: int, input_model=None):
+    """Training rows from full 2/3/4-body systems: inputs are 2/3-body
+    descriptors (columns 1..n_in of the per-atom descriptors of input_model,
+    by default of model itself) and labels the exact per-atom 4-body energies
+    sum_{k in 4-body} c_k D_ik of model, both computed by the library
     (pod_descriptors, and pod_energy_forces with the 4-body coefficients
-    only).  model: FP64 PodModel with 4-body terms; boxes: iterable of
+    only).  model: FP64 PodModel with 4-body terms; input_model: FP64
+    2/3-body PodModel, e.g. with a higher 3-body degree; boxes: iterable of
     (pos, cell, neighbour list).  Returns (X FP32 [n, n_in], E4 FP32 [n])."""
     import torch
+    m_by = model.M_by_order
+    n23 = 1 + m_by[1] + m_by[2]
+    if input_model is None and n_in != n23 - 1:
+        raise ValueError("n_in differs from the model's 2/3-body descriptor count")
+    if input_model is not None and n_in > input_model.M - 1:
+        raise ValueError("n_in exceeds the input model's descriptors")
     c4 = np.array(c, dtype=np.float64)
-    c4[: n_in + 1] = 0.0
+    c4[:n23] = 0.0
+    src = model if input_model is None else input_model
     Xs, Ts = [], []
     for pos, cell, nl in boxes:
         nb = pod.DeviceNeighbors.from_list(nl)
-        D = model.descriptors(pos, cell, nb)
+        D = src.descriptors(pos, cell, nb)
         o = model.energy_forces(pos, cell, nb, c4, forces=False, virial=False, global_desc=False)
         Xs.append(D[:, 1:n_in + 1].float())
         Ts.append(o["E_atom"].float())
+        del D, o
     return torch.cat(Xs).contiguous(), torch.cat(Ts).contiguous()

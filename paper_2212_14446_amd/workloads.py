@@ -290,6 +290,27 @@ def config4() -> Workload:
 
 SETUP_CFG5 = PodSetup(rin=0.5, rcut=5.0, L=8, K2=6, K3=6, K4=6, P3=4, P4=4)
 SETUP_CFG5_23 = PodSetup(rin=0.5, rcut=5.0, L=8, K2=6, K3=6, K4=0, P3=4, P4=0)
+# the same 2/3-body part with 4-body terms up to angular degree 6 (P4 > P3):
+# the exact model's atomic basis grows from 35 to 84 monomials, while the
+# surrogate keeps the degree-4 basis of SETUP_CFG5_23
+SETUP_CFG5_P6 = PodSetup(rin=0.5, rcut=5.0, L=8, K2=6, K3=6, K4=6, P3=4, P4=6)
+
+
+def embed_23_coefficients(c, setup: PodSetup, setup23: PodSetup):
+    """The constant, 2-body and 3-body coefficients of a model (setup) in the
+    descriptor layout of a 2/3-body setup with the same K2, K3 and a 3-body
+    degree P3 at least as high: columns of degrees above setup.P3 get zero,
+    so that c23 . D23 is the model's 2/3-body energy."""
+    if setup23.K2 != setup.K2 or setup23.K3 != setup.K3 or setup23.P3 < setup.P3:
+        raise ValueError("2/3-body layout does not contain the model's")
+    c = np.asarray(c, dtype=np.float64)
+    out = np.zeros(setup23.M)
+    out[: 1 + setup.K2] = c[: 1 + setup.K2]
+    o, o23 = 1 + setup.K2, 1 + setup23.K2
+    for m in range(setup.K3):
+        out[o23 + m * (setup23.P3 + 1): o23 + m * (setup23.P3 + 1) + setup.P3 + 1] = \
+            c[o + m * (setup.P3 + 1): o + (m + 1) * (setup.P3 + 1)]
+    return out
 
 
 def config5_train_boxes(n_boxes: int = 19, seed: int = 9):

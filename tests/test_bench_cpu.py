@@ -41,3 +41,32 @@ def test_flop_split_between_kernels():
     assert sp["per_atom"] == c["per_atom"]
     assert sp["pair_per_pair"] == 2 * 8 * 6 + c["backward_per_pair"]
 
+
+
+def test_embedded_two_three_body_coefficients_reproduce_the_model_energy():
+    """The surrogate's exact part: a model's constant, 2- and 3-body
+    coefficients placed in the layout of a 2/3-body setup with a higher
+    3-body degree give, through the oracle, the model's energy with its
+    4-body coefficients set to zero."""
+    import numpy as np
+
+    from oracle import pod_oracle as po
+    from paper_2212_14446_amd import workloads as wl
+    S = wl.PodSetup(rin=0.5, rcut=5.0, L=6, K2=3, K3=2, K4=2, P3=2, P4=3)
+    S23 = wl.PodSetup(rin=0.5, rcut=5.0, L=6, K2=3, K3=2, K4=0, P3=4, P4=0)
+    mk = lambda s: po.PodParams(s.rin, s.rcut, *s.snapshot_family(), s.K2, s.K3, s.K4, s.P3, s.P4)
+    p, p23 = mk(S), mk(S23)
+    Q, _ = po.pod_basis(p, n_quad=400)
+    pos, cell = wl.bcc(1)
+    pos = wl.displace(pos, 0.2, 7)
+    off, nj, sh = po.neighbors_bruteforce(pos, cell, p.rcut)
+    c = np.random.default_rng(3).normal(size=S.M)
+    c23 = wl.embed_23_coefficients(c, S, S23)
+    assert c23.shape == (S23.M,)
+    c_no4 = c.copy()
+    c_no4[1 + S.K2 + S.K3 * (S.P3 + 1):] = 0.0
+    e_ref = po.total_energy(pos, cell, off, nj, sh, p, Q, c_no4)
+    e_23 = po.total_energy(pos, cell, off, nj, sh, p23, Q, c23)
+    assert abs(e_23 - e_ref) <= 1e-12 * max(1.0, abs(e_ref))
+    with __import__("pytest").raises(ValueError):
+        wl.embed_23_coefficients(c, S, wl.PodSetup(rin=0.5, rcut=5.0, L=6, K2=3, K3=2, K4=0, P3=1, P4=0))

@@ -90,6 +90,7 @@ SWEEP = [
     (10, 8, 8, 8, 2, 2),
     (8, 3, 2, 2, 5, 6),
     (8, 2, 0, 4, 0, 3),
+    (8, 6, 6, 6, 4, 6),     # 4-body degree above the 3-body one (the surrogate comparison's exact model)
 ]
 
 
@@ -111,7 +112,7 @@ def test_sweep_f64(box49, L, K2, K3, K4, P3, P4):
     _assert64(_compare(case, "f64"))
 
 
-@pytest.mark.parametrize("L,K2,K3,K4,P3,P4", [SWEEP[1], SWEEP[5], SWEEP[8]])
+@pytest.mark.parametrize("L,K2,K3,K4,P3,P4", [SWEEP[1], SWEEP[5], SWEEP[8], SWEEP[10]])
 def test_sweep_f32(box49, L, K2, K3, K4, P3, P4):
     pos, cell = box49
     s = wl.PodSetup(0.5, 5.0, L, K2, K3, K4, P3, P4)
