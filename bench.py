@@ -386,7 +386,10 @@ def run_neighbors(reps, warmup=2):
 
 # Table 6: (K2, K3, P3) of the OPOD/FPOD3 models and (K4, P4) of FPOD4, rows
 # with M = 6, 15, 31, 56 (the kernels' radial/angular limits exclude 92, 141)
-TABLE6 = [(2, 1, 2, 1, 1), (5, 3, 2, 3, 2), (5, 5, 4, 5, 3), (6, 7, 6, 7, 4)]
+# (L, K2, K3, P3, K4, P4) of the six rows of Table 6; rows 5 and 6 need
+# K up to 12, so their snapshot family has L = 14 (12 Bessel + 2 inverse powers)
+TABLE6 = [(8, 2, 1, 2, 1, 1), (8, 5, 3, 2, 3, 2), (8, 5, 5, 4, 5, 3), (8, 6, 7, 6, 7, 4),
+          (14, 10, 9, 8, 9, 5), (14, 8, 12, 10, 12, 6)]
 
 
 @on_stream
@@ -415,8 +418,8 @@ def run_opod(steps, warmup=3):
         return e0.elapsed_time(e1) / steps
 
     rows = []
-    for (K2, K3, P3, K4, P4) in TABLE6:
-        s3 = wl.PodSetup(0.5, 5.0, 8, K2, K3, 0, P3, 0)
+    for (L, K2, K3, P3, K4, P4) in TABLE6:
+        s3 = wl.PodSetup(0.5, 5.0, L, K2, K3, 0, P3, 0)
         m3 = pod.PodModel(pod.setup_from_workload(s3), "f64")
         nb.build_reverse(m3)
         c = torch.tensor(wl.coefficients(s3.M, 3), device="cuda")
@@ -426,7 +429,7 @@ def run_opod(steps, warmup=3):
         t_fast = timed(lambda: m3.energy_forces(x3, w.cell, nb, c, check=False, out=out))
         t_excl = timed(lambda: m3.opod_energy_forces(x3, w.cell, nb, c, check=False, out=oout))
         m3.check()
-        s4 = wl.PodSetup(0.5, 5.0, 8, K2, K3, K4, P3, P4)
+        s4 = wl.PodSetup(0.5, 5.0, L, K2, K3, K4, P3, P4)
         m4 = pod.PodModel(pod.setup_from_workload(s4), "f64")
         D = torch.empty((w.N, s4.M), dtype=torch.float64, device="cuda")
         x = m4._pos(w.pos)
@@ -434,7 +437,7 @@ def run_opod(steps, warmup=3):
         t_d_excl = timed(lambda: pod.pod_opod_descriptors(m4.h, w.N, nb.P, x, w.cell, nb.offsets, nb.nbr_j,
                                                           nb.shift, D))
         m4.check()
-        rows.append({"K2": K2, "K3": K3, "P3": P3, "M3": s3.M, "fpod3_ef_ms": t_fast, "opod_ef_ms": t_excl,
+        rows.append({"L": L, "K2": K2, "K3": K3, "P3": P3, "M3": s3.M, "fpod3_ef_ms": t_fast, "opod_ef_ms": t_excl,
                      "opod_over_fpod3": t_excl / t_fast, "K4": K4, "P4": P4, "M4": s4.M,
                      "fast_desc4_ms": t_d_fast, "excl_desc4_ms": t_d_excl, "excl_over_fast": t_d_excl / t_d_fast})
         print(f"[bench] opod row {rows[-1]}", file=sys.stderr, flush=True)

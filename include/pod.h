@@ -66,10 +66,13 @@ extern "C" {
 #define POD_F64 0
 #define POD_F32 1
 
-/* Compile-time limits of the kernels. */
+/* Compile-time limits of the kernels.  Models up to angular degree 6 run on
+ * the register-resident per-atom kernel; degrees 7 to 10 (the largest
+ * models of Table 6) on a kernel that keeps each atom's basis in LDS. */
 #define POD_MAX_L 16   /* snapshots */
-#define POD_MAX_K 8    /* radial functions, max(K2, K3, K4) */
-#define POD_MAX_P 6    /* angular degree, max(P3, P4) */
+#define POD_MAX_K 12   /* radial functions, max(K2, K3, K4) */
+#define POD_MAX_P 10   /* angular degree of the 3-body terms, P3 */
+#define POD_MAX_P4 6   /* angular degree of the 4-body terms, P4 (K_a <= 23) */
 
 /*
  * Parameters (Sec. II.B-II.D).  One snapshot tuple mu_l = (rin, rcut, alpha_l,
@@ -77,7 +80,7 @@ extern "C" {
  * varphi with phi = sin(alpha pi x)/(r - rin), varphi = r^-gamma (eq. (3)).
  * Requirements: 0 <= rin < rcut; 1 <= L <= POD_MAX_L; 0 <= kappa_l <= 1;
  * beta_l >= 0; 0 <= K2, K3, K4 <= min(L, POD_MAX_K) with at least one > 0;
- * 0 <= P3, P4 <= POD_MAX_P.  Q: NULL to compute the POD basis (method of
+ * 0 <= P3 <= POD_MAX_P; 0 <= P4 <= POD_MAX_P4.  Q: NULL to compute the POD basis (method of
  * snapshots on n_quad midpoint nodes of (rin, rcut), unit eigenvectors of the
  * snapshot correlation matrix, decreasing eigenvalue, entry of largest
  * magnitude positive), or an L x K row-major matrix (K = max(K2, K3, K4)) to

@@ -21,7 +21,7 @@ LIB = os.path.join(HERE, "libpod.so")
 OBJDIR = os.path.join(ROOT, "_build")
 
 SOURCES = ["pod_host.cpp", "pod_plan.cpp", "pod_kernels.hip", "pod_batch.hip", "pod_mlp.hip", "pod_neighbors.hip",
-           "pod_fit.hip", "pod_opod.hip", "pod_md.hip", "pod_acsf.hip", "pod_five.hip"]
+           "pod_fit.hip", "pod_opod.hip", "pod_md.hip", "pod_acsf.hip", "pod_five.hip", "pod_wide.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

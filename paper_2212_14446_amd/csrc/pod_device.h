@@ -117,11 +117,72 @@ __device__ __forceinline__ int unpack_shift(int sh, int d) {
     return static_cast<int>(static_cast<int8_t>((sh >> (8 * d)) & 0xFF));
 }
 
+// One neighbour slot of an atom: index and packed image shift.
+struct SlotIdx {
+    int j;    // neighbour index, -1 for an empty slot
+    int sh;   // packed image shift
+};
+
+// The loads of a slot are issued on every lane (an empty slot reads entry 0,
+// which exists whenever the list is not empty): with a fixed number of
+// loads per round the compiler can wait for exactly the ones a round needs
+// and leave the prefetched ones in flight.
+template <typename A>
+__device__ __forceinline__ SlotIdx slot_index(const A& g, bool valid, int p) {
+    const int pc = valid ? p : 0;
+    SlotIdx s;
+    s.j = g.nbr_j[pc];
+    s.sh = g.shift[pc];
+    if (!valid) { s.j = -1; s.sh = 0; }
+    return s;
+}
+
+template <typename T, typename A>
+__device__ __forceinline__ void slot_pos(const A& g, const SlotIdx& s, T (&pj)[3]) {
+    const int jc = (s.j >= 0 && s.j < g.N) ? s.j : 0;
+    pj[0] = g.pos[3 * jc + 0];
+    pj[1] = g.pos[3 * jc + 1];
+    pj[2] = g.pos[3 * jc + 2];
+}
+
+// r_ij = r_j + n.cell - r_i, |r_ij| and validity of one fetched slot.  Data
+// errors are collected in `eb` (error-word bits).
+template <typename T, typename A>
+__device__ __forceinline__ bool slot_geometry(const A& g, bool valid, const SlotIdx& s, const T (&pj)[3],
+                                              const T (&pi)[3], int& eb, T (&d)[3], T& r) {
+    d[0] = d[1] = d[2] = T(0);
+    r = T(0.5) * (g.prm.rin + g.prm.rcut);
+    if (!valid) return false;
+    if (s.j < 0 || s.j >= g.N || (!g.cell.periodic && (s.sh & 0xFFFFFF) != 0)) {
+        eb |= ERR_NEIGH;
+        return false;
+    }
+    const T sx = T(unpack_shift(s.sh, 0)), sy = T(unpack_shift(s.sh, 1)), sz = T(unpack_shift(s.sh, 2));
+    const T* a = g.cell.a;
+    const T d0 = pj[0] - pi[0] + sx * a[0] + sy * a[3] + sz * a[6];
+    const T d1 = pj[1] - pi[1] + sx * a[1] + sy * a[4] + sz * a[7];
+    const T d2 = pj[2] - pi[2] + sx * a[2] + sy * a[5] + sz * a[8];
+    const T r2 = d0 * d0 + d1 * d1 + d2 * d2;
+    if (!d_finite(r2)) {
+        eb |= ERR_NONFINITE;
+        return false;
+    }
+    const T rr = d_sqrt(r2);
+    if (rr <= g.prm.rin) {
+        eb |= ERR_RANGE;
+        return false;
+    }
+    if (rr >= g.prm.rcut) return false;   // not a neighbour (Sec. II.A): no contribution
+    d[0] = d0; d[1] = d1; d[2] = d2;
+    r = rr;
+    return true;
+}
+
 // Radial functions R_k(r) = sum_l Q_lk Phi_l(r) and (DERIV) R'_k(r) for k <
-// POD_MAX_K (Sec. II.B, eqs. (3)-(8), (11), (12)).  Q is zero beyond K.
-template <typename T, bool DERIV>
-__device__ __forceinline__ void radial(const ParamsT<T>* __restrict__ P, T r, T rinv,
-                                       T (&R)[POD_MAX_K], T (&dR)[POD_MAX_K]) {
+// NR (Sec. II.B, eqs. (3)-(8), (11), (12)).  Q is zero beyond K.
+template <typename T, bool DERIV, int NR>
+__device__ __forceinline__ void radial(const ParamsT<T>* __restrict__ P, T r, T rinv, T (&R)[NR], T (&dR)[NR]) {
+    static_assert(NR <= POD_MAX_K, "radial functions beyond the parameter block");
     const T inv_h = P->inv_h;
     const T dist = r - P->rin;
     const T t = dist * inv_h;
@@ -135,7 +196,7 @@ __device__ __forceinline__ void radial(const ParamsT<T>* __restrict__ P, T r, T 
     constexpr T kPi = T(3.14159265358979323846);
     T x = 0, dx = 0, s1 = 0, c1 = 1, sk = 0, ck = 1;
 #pragma unroll
-    for (int k = 0; k < POD_MAX_K; ++k) { R[k] = 0; dR[k] = 0; }
+    for (int k = 0; k < NR; ++k) { R[k] = 0; dR[k] = 0; }
     const int L = P->L;
     for (int l = 0; l < L; ++l) {
         const SnapT<T>& sn = P->s[l];
@@ -182,7 +243,7 @@ __device__ __forceinline__ void radial(const ParamsT<T>* __restrict__ P, T r, T 
         const T ph = fc * psi;
         const T dph = DERIV ? dfc * psi + fc * dpsi : T(0);
 #pragma unroll
-        for (int k = 0; k < POD_MAX_K; ++k) {
+        for (int k = 0; k < NR; ++k) {
             const T qlk = P->Q[l][k];
             R[k] += qlk * ph;
             if (DERIV) dR[k] += qlk * dph;
@@ -249,10 +310,13 @@ __device__ __forceinline__ void sincospi_unit(T x, T* sp, T* cp) {
 // Radial functions for the standard snapshot family (Bessel alpha = 1..nb at
 // one beta, inverse powers gamma = 1..ni): one expm1, one sincos and one exp
 // per pair; sin/cos(alpha pi x) by angle addition; Q read from LDS.
-// KR: number of radial functions to form (the others are left zero).
-template <typename T, bool DERIV, int KR = POD_MAX_K>
+// KR: number of radial functions to form (the others are left zero; -1 =
+// all NR).  sQ holds Q with row stride POD_MAX_K.
+template <typename T, bool DERIV, int KR = -1, int NR>
 __device__ __forceinline__ void radial_std(const ParamsT<T>* __restrict__ P, const T* __restrict__ sQ, T r,
-                                           T rinv, T (&R)[POD_MAX_K], T (&dR)[POD_MAX_K]) {
+                                           T rinv, T (&R)[NR], T (&dR)[NR]) {
+    constexpr int KF = KR < 0 ? NR : KR;
+    static_assert(KF <= NR && NR <= POD_MAX_K, "radial functions beyond the array or the parameter block");
     const T inv_h = P->inv_h;
     const T dist = r - P->rin;
     const T t = dist * inv_h;
@@ -265,7 +329,7 @@ __device__ __forceinline__ void radial_std(const ParamsT<T>* __restrict__ P, con
     const T idist = T(1) / dist;
     constexpr T kPi = T(3.14159265358979323846);
 #pragma unroll
-    for (int k = 0; k < POD_MAX_K; ++k) { R[k] = 0; dR[k] = 0; }
+    for (int k = 0; k < NR; ++k) { R[k] = 0; dR[k] = 0; }
     const int nb = P->std_nb, ni = P->std_ni;
     if (nb > 0) {
         T x, dx;
@@ -292,7 +356,7 @@ __device__ __forceinline__ void radial_std(const ParamsT<T>* __restrict__ P, con
             const T dph = DERIV ? dfci * sk + fci * (T(l + 1) * pdx * ck - sk * idist) : T(0);
             const T* q = sQ + l * POD_MAX_K;
 #pragma unroll
-            for (int k = 0; k < KR; ++k) {
+            for (int k = 0; k < KF; ++k) {
                 R[k] += q[k] * ph;
                 if (DERIV) dR[k] += q[k] * dph;
             }
@@ -305,7 +369,7 @@ __device__ __forceinline__ void radial_std(const ParamsT<T>* __restrict__ P, con
         const T dph = DERIV ? (dfc - T(g) * fc * rinv) * pw : T(0);
         const T* q = sQ + (nb + g - 1) * POD_MAX_K;
 #pragma unroll
-        for (int k = 0; k < KR; ++k) {
+        for (int k = 0; k < KF; ++k) {
             R[k] += q[k] * ph;
             if (DERIV) dR[k] += q[k] * dph;
         }

@@ -242,7 +242,7 @@ __global__ __launch_bounds__(FIVE_THREADS) void five_pair_kernel(FArgs<T> g) {
                 }
             }
         }
-        T R[POD_MAX_K], dR[POD_MAX_K];
+        T R[FAST_MAX_K], dR[FAST_MAX_K];
         if constexpr (FAST) dev::radial_std<T, DERIV>(&g.prm, sQ, r, T(1) / r, R, dR);
         else dev::radial<T, DERIV>(&g.prm, r, T(1) / r, R, dR);
         row[0] = u[0];
@@ -250,7 +250,7 @@ __global__ __launch_bounds__(FIVE_THREADS) void five_pair_kernel(FArgs<T> g) {
         row[2] = u[2];
         row[3] = r;
 #pragma unroll
-        for (int k = 0; k < POD_MAX_K; ++k)
+        for (int k = 0; k < FAST_MAX_K; ++k)
             if (k < g.K5) {
                 row[4 + k] = ok ? R[k] : T(0);
                 if (DERIV) row[4 + g.K5 + k] = ok ? dR[k] : T(0);
@@ -537,7 +537,7 @@ int pod_five_body_descriptors(pod_handle* h, int N, int P, const void* pos, cons
                               const int* nbr_j, const int* shift, int K5, int P5, void* D5) {
     using namespace pod;
     if (!h || N < 0 || P < 0 || K5 < 1 || K5 > h->K || P5 < 0) return POD_EINVAL;
-    if (P5 > POD_FIVE_MAX_P) return POD_ENOTSUP;
+    if (P5 > POD_FIVE_MAX_P || K5 > FAST_MAX_K) return POD_ENOTSUP;
     if (N > 0 && (!pos || !offsets || !D5 || (P > 0 && (!nbr_j || !shift)))) return POD_EINVAL;
     if (N == 0) return POD_OK;
     if (h->dtype == POD_F64)
@@ -552,7 +552,7 @@ int pod_five_body_energy_forces(pod_handle* h, int N, int P, const void* pos, co
                                 void* E_atom, void* F) {
     using namespace pod;
     if (!h || N < 0 || P < 0 || K5 < 1 || K5 > h->K || P5 < 0) return POD_EINVAL;
-    if (P5 > POD_FIVE_MAX_P) return POD_ENOTSUP;
+    if (P5 > POD_FIVE_MAX_P || K5 > FAST_MAX_K) return POD_ENOTSUP;
     if (N > 0 && (!pos || !offsets || !c5 || (!E_atom && !F) || (P > 0 && (!nbr_j || !shift))))
         return POD_EINVAL;
     if (N > 0 && F && P > 0 && !rev) return POD_EINVAL;

@@ -11,6 +11,13 @@ namespace pod {
 
 constexpr int WAVE = 64;
 
+// Largest angular degree and radial-function count of the kernels that keep
+// an atom's basis rows in registers (energy path, batch assembly, surrogate,
+// five-body terms); beyond either the energy path runs on the kernel with
+// the basis in LDS.
+constexpr int FAST_MAX_PA = 6;
+constexpr int FAST_MAX_K = 8;
+
 // Device error word bits (latched with atomicOr, read and cleared by pod_check).
 constexpr int ERR_RANGE = 1;
 constexpr int ERR_NONFINITE = 2;

@@ -7,21 +7,27 @@
 //   ("rounds"): in a round, lane (a, s) evaluates slot s of atom a -- pair
 //   geometry and the radial basis (Sec. II.B, eqs. (3)-(8), (11), (12)) --
 //   and stages {rhat, R_k} in LDS for the atom's K lanes, with the next
-//   slot's indices and positions prefetched.  Every contraction of Sec. II.E
-//   is diagonal in m (the same radial function in all factors, eqs. (14),
-//   (17a)), so D3, D4, the energy and the adjoint dE_i/dB_{i m .} come from
-//   the lane's own row with compile-time tables.  The backward sweep walks
-//   the slots again, forms dE_i/dr_ij (eq. (24c)) from the K adjoint rows of
-//   the atom, and either stores it at the reverse slot of the pair (gather
-//   path, with a reverse-pair index) or adds it to an FP64 accumulator with
-//   device atomics.  E, the virial and G leave as per-workgroup partials.
+//   slots' indices and positions prefetched; it also records the pair's
+//   centre atom and vector for the pair kernel.  Every contraction of
+//   Sec. II.E is diagonal in m (the same radial function in all factors,
+//   eqs. (14), (17a)), so D3, D4, the energy and the adjoint row
+//   dE_i/dB_{i m .} come from the lane's own row with compile-time tables.
+//   The adjoint rows go to memory, [atom][k][mu]; E and G leave as
+//   per-workgroup partials.
+// pair_kernel  (one pair per lane, 64 consecutive list slots per block):
+//   loads the adjoint rows of the block's centre atoms into LDS, re-evaluates
+//   R_k and R'_k and forms dE_i/dr_ij (eq. (24c)); stores it at the pair's
+//   own and reverse slots (gather path, with a reverse-pair index) or adds it
+//   to an FP64 accumulator with device atomics; the virial leaves as
+//   per-block partials.
 // finalize_kernel  sums the partials in a fixed order (E, W, G) and forms the
-//   forces: on the gather path each atom adds its own sum_j g_ij to the
-//   values stored in its list range (32 lanes per atom); otherwise it copies
-//   and clears the accumulator.
+//   forces: on the gather path each atom adds what its own list range holds
+//   (32 lanes per atom); otherwise it copies and clears the accumulator.
 // reverse_kernel  builds the reverse-pair index of a list once.
-// The per-atom basis B and its adjoint never leave the chip; only the
-// pair gradients of the gather path go through memory.
+// Models beyond these kernels' register budget (angular degree above
+// FAST_MAX_PA or more than FAST_MAX_K radial functions) run the whole
+// energy path in the wide-degree kernel of pod_wide.hip, whose partials and
+// pair gradients have the same layout, so finalize_kernel serves both.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -32,6 +38,7 @@
 #include "pod_device.h"
 #include "pod_internal.h"
 #include "pod_tables.h"
+#include "pod_wide.h"
 
 namespace pod {
 
@@ -75,72 +82,13 @@ struct KArgs {
 
 // Neighbour slots are fetched two rounds ahead: the index and image shift of
 // round r + 2 and the neighbour position of round r + 1 are requested before
-// the arithmetic of round r.
-struct SlotIdx {
-    int j;    // neighbour index, -1 for an empty slot
-    int sh;   // packed image shift
-};
-
-// The loads of a slot are issued on every lane (an empty slot reads entry 0,
-// which exists whenever the list is not empty): with a fixed number of
-// loads per round the compiler can wait for exactly the ones a round needs
-// and leave the prefetched ones in flight.
-template <typename A>
-__device__ __forceinline__ SlotIdx slot_index(const A& g, bool valid, int p) {
-    const int pc = valid ? p : 0;
-    SlotIdx s;
-    s.j = g.nbr_j[pc];
-    s.sh = g.shift[pc];
-    if (!valid) { s.j = -1; s.sh = 0; }
-    return s;
-}
-
-template <typename T, typename A>
-__device__ __forceinline__ void slot_pos(const A& g, const SlotIdx& s, T (&pj)[3]) {
-    const int jc = (s.j >= 0 && s.j < g.N) ? s.j : 0;
-    pj[0] = g.pos[3 * jc + 0];
-    pj[1] = g.pos[3 * jc + 1];
-    pj[2] = g.pos[3 * jc + 2];
-}
-
-// r_ij = r_j + n.cell - r_i, |r_ij| and validity of one fetched slot.  Data
-// errors are collected in `eb` (error-word bits).
-template <typename T, typename A>
-__device__ __forceinline__ bool slot_geometry(const A& g, bool valid, const SlotIdx& s, const T (&pj)[3],
-                                              const T (&pi)[3], int& eb, T (&d)[3], T& r) {
-    d[0] = d[1] = d[2] = T(0);
-    r = T(0.5) * (g.prm.rin + g.prm.rcut);
-    if (!valid) return false;
-    if (s.j < 0 || s.j >= g.N || (!g.cell.periodic && (s.sh & 0xFFFFFF) != 0)) {
-        eb |= ERR_NEIGH;
-        return false;
-    }
-    const T sx = T(unpack_shift(s.sh, 0)), sy = T(unpack_shift(s.sh, 1)), sz = T(unpack_shift(s.sh, 2));
-    const T* a = g.cell.a;
-    const T d0 = pj[0] - pi[0] + sx * a[0] + sy * a[3] + sz * a[6];
-    const T d1 = pj[1] - pi[1] + sx * a[1] + sy * a[4] + sz * a[7];
-    const T d2 = pj[2] - pi[2] + sx * a[2] + sy * a[5] + sz * a[8];
-    const T r2 = d0 * d0 + d1 * d1 + d2 * d2;
-    if (!d_finite(r2)) {
-        eb |= ERR_NONFINITE;
-        return false;
-    }
-    const T rr = d_sqrt(r2);
-    if (rr <= g.prm.rin) {
-        eb |= ERR_RANGE;
-        return false;
-    }
-    if (rr >= g.prm.rcut) return false;   // not a neighbour (Sec. II.A): no contribution
-    d[0] = d0; d[1] = d1; d[2] = d2;
-    r = rr;
-    return true;
-}
+// the arithmetic of round r (slot helpers in pod_device.h).
 
 // KR: radial functions formed on the standard-family path (K when it is
-// fixed at compile time, else all POD_MAX_K, zero beyond K).
-template <typename T, bool DERIV, bool FAST, int KR = POD_MAX_K>
+// fixed at compile time, else all FAST_MAX_K, zero beyond K).
+template <typename T, bool DERIV, bool FAST, int KR = FAST_MAX_K>
 __device__ __forceinline__ void radial_any(const ParamsT<T>* __restrict__ P, const T* sQ, T r, T rinv,
-                                           T (&R)[POD_MAX_K], T (&dR)[POD_MAX_K]) {
+                                           T (&R)[FAST_MAX_K], T (&dR)[FAST_MAX_K]) {
     if constexpr (FAST) radial_std<T, DERIV, KR>(P, sQ, r, rinv, R, dR);
     else radial<T, DERIV>(P, r, rinv, R, dR);
 }
@@ -187,14 +135,14 @@ __host__ __device__ inline AtomLds atom_lds_layout(int K, int NA, int M, size_t 
 // The same for any K: one pass over the monomials per radial function.
 template <typename T, int PA>
 __device__ __forceinline__ void pair_gradient_any(const T* __restrict__ abr, int K, const T (&A)[n_mono(PA)],
-                                                  const T (&R)[POD_MAX_K], const T (&dR)[POD_MAX_K], T ri, T ux,
+                                                  const T (&R)[FAST_MAX_K], const T (&dR)[FAST_MAX_K], T ri, T ux,
                                                   T uy, T uz, T& gx, T& gy, T& gz) {
     constexpr MonoTable<PA> mt{};
     constexpr int NA = n_mono(PA);
     constexpr int NAP = NA;    // rows of one atom are contiguous
     gx = 0; gy = 0; gz = 0;
 #pragma unroll
-    for (int k = 0; k < POD_MAX_K; ++k) {
+    for (int k = 0; k < FAST_MAX_K; ++k) {
         if (k < K) {
             const T* abk = abr + k * NAP;
             T hd[PA + 1];
@@ -294,13 +242,13 @@ __device__ __forceinline__ void atom_body(const KArgs<T>& g) {
                     pv[0] = d[0]; pv[1] = d[1]; pv[2] = d[2];
                 }
                 const T rinv = T(1) / r;
-                T R[POD_MAX_K], dR[POD_MAX_K];
+                T R[FAST_MAX_K], dR[FAST_MAX_K];
                 radial_any<T, false, FAST>(P, &P->Q[0][0], r, rinv, R, dR);
                 const T z = ok ? T(1) : T(0);
                 T* row = sT + lane * SS;
                 row[0] = d[0] * rinv; row[1] = d[1] * rinv; row[2] = d[2] * rinv;
 #pragma unroll
-                for (int k = 0; k < POD_MAX_K; ++k)
+                for (int k = 0; k < FAST_MAX_K; ++k)
                     if (k < K) row[3 + k] = R[k] * z;
             }
             wave_sync();
@@ -607,8 +555,8 @@ __host__ __device__ inline size_t pair_lds_bytes(int K, int NA, size_t tsize) {
 // reads of the adjoint rows ahead of the arithmetic and runs out of
 // registers (FP64: 256 VGPRs + 256 AGPRs and scratch, against 180 VGPRs).
 template <typename T, int PA, int KK>
-__device__ __forceinline__ void pair_gradient_blocks(const T* __restrict__ abr, const T (&R)[POD_MAX_K],
-                                                     const T (&dR)[POD_MAX_K], T ri, T ux, T uy, T uz, int gate,
+__device__ __forceinline__ void pair_gradient_blocks(const T* __restrict__ abr, const T (&R)[FAST_MAX_K],
+                                                     const T (&dR)[FAST_MAX_K], T ri, T ux, T uy, T uz, int gate,
                                                      T& gx, T& gy, T& gz) {
     constexpr MonoTable<PA> mt{};
     constexpr int NA = n_mono(PA);
@@ -683,7 +631,7 @@ __device__ __forceinline__ void lds_copy_wait() {
 template <typename T>
 struct PairGeom {
     T d[3], r, ri, ux, uy, uz;
-    T R[POD_MAX_K], dR[POD_MAX_K];
+    T R[FAST_MAX_K], dR[FAST_MAX_K];
     bool ok;
 };
 
@@ -697,7 +645,7 @@ __device__ __forceinline__ void pair_setup(const PArgs<T>& g, bool valid, const 
     q.r = q.ok ? d_sqrt(r2) : T(0.5) * (P->rin + P->rcut);
     q.ri = T(1) / q.r;
     // Q from the parameter block (uniform addresses: scalar loads)
-    radial_any<T, true, FAST, (KK > 0 ? KK : POD_MAX_K)>(P, &P->Q[0][0], q.r, q.ri, q.R, q.dR);
+    radial_any<T, true, FAST, (KK > 0 ? KK : FAST_MAX_K)>(P, &P->Q[0][0], q.r, q.ri, q.R, q.dR);
     q.ux = q.d[0] * q.ri; q.uy = q.d[1] * q.ri; q.uz = q.d[2] * q.ri;
 }
 
@@ -1062,6 +1010,22 @@ int fill_args(pod_handle* h, KArgs<T>& a, int N, int P, const void* pos, const d
     return POD_OK;
 }
 
+// Arguments of the wide-degree kernel from those of the per-atom kernel.
+template <typename T>
+WideArgs<T> wide_args(const KArgs<T>& a) {
+    WideArgs<T> w;
+    w.prm = a.prm; w.cell = a.cell;
+    w.N = a.N; w.P = a.P;
+    w.pos = a.pos; w.offsets = a.offsets; w.nbr_j = a.nbr_j; w.shift = a.shift;
+    w.coef = a.coef; w.D = a.D; w.E_atom = a.E_atom;
+    w.part = a.part; w.wpart = nullptr;
+    w.gown = nullptr; w.gbuf = nullptr; w.rev = nullptr; w.Facc = nullptr;
+    w.rec = nullptr; w.rs = 0;
+    w.want_G = a.want_G; w.want_back = a.want_back; w.want_W = 0;
+    w.err = a.err;
+    return w;
+}
+
 template <typename T>
 int descriptors_impl(pod_handle* h, int N, int P, const void* pos, const double* cell, const int* offsets,
                      const int* nbr_j, const int* shift, void* D) {
@@ -1070,6 +1034,17 @@ int descriptors_impl(pod_handle* h, int N, int P, const void* pos, const double*
     const int rc = fill_args<T>(h, a, N, P, pos, cell, offsets, nbr_j, shift);
     if (rc != POD_OK) return rc;
     a.D = static_cast<T*>(D);
+    if (wide_path(h->K, h->PA)) {
+        WideArgs<T> w = wide_args(a);
+        w.rs = wide_rec_stride(h->K, false);
+        const int rc2 = ensure_scratch(h, static_cast<size_t>(P > 0 ? P : 1) * w.rs * sizeof(T));
+        if (rc2 != POD_OK) return rc2;
+        w.rec = static_cast<T*>(h->d_scratch);
+        timing_begin(h, 1);
+        const hipError_t e = launch_wide<T>(w, 0, h->std_ok != 0, wide_blocks(N), h->stream);
+        timing_end(h, 1);
+        return e == hipSuccess ? POD_OK : POD_EHIP;
+    }
     const int apw = WAVE / h->K;
     const int nblk = (N + apw - 1) / apw;
     timing_begin(h, 1);
@@ -1082,26 +1057,31 @@ int descriptors_impl(pod_handle* h, int N, int P, const void* pos, const double*
 // Scratch of one energy call, carved from one device buffer (256-byte
 // aligned pieces): atom-kernel partials [10 + M][nblk], pair-kernel virial
 // partials [9][nblk_p], adjoint rows [N][K][NA] (per-atom stride padded to
-// 16 bytes), centre atom and pair vector of each pair, and on the gather path the pair gradients [P][3] at reverse and at own
-// slots.
+// 16 bytes), centre atom and pair vector of each pair, on the gather path
+// the pair gradients [P][3] at reverse and at own slots, and for the
+// wide-degree kernel (no adjoint rows, centres or pair vectors) the pair
+// records [P][4 + 2K].
 struct EfScratch {
-    size_t part, wpart, abar, centre, pdv, gbuf, gown, total;
+    size_t part, wpart, abar, centre, pdv, gbuf, gown, rec, total;
 };
 
 EfScratch ef_scratch_layout(int N, int P, int K, int PA, int M, size_t tsize, bool back, bool gather) {
     auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+    const bool wide = wide_path(K, PA);   // one kernel, partials per persistent workgroup
     const int apw = WAVE / K;
-    const size_t nblk = N > 0 ? (static_cast<size_t>(N) + apw - 1) / apw : 0;
-    const size_t nblk_p = back ? (static_cast<size_t>(P) + PAIR_BLOCK - 1) / PAIR_BLOCK : 0;
+    const size_t nblk = N <= 0 ? 0 : wide ? static_cast<size_t>(wide_blocks(N)) : (static_cast<size_t>(N) + apw - 1) / apw;
+    const size_t nblk_p = !back ? 0 : wide ? nblk : (static_cast<size_t>(P) + PAIR_BLOCK - 1) / PAIR_BLOCK;
     EfScratch L;
     size_t o = 0;
     L.part = o; o += al(static_cast<size_t>(10 + M) * (nblk > 0 ? nblk : 1) * sizeof(double));
     L.wpart = o; o += al(9 * (nblk_p > 0 ? nblk_p : 1) * sizeof(double));
-    L.abar = o; o += back ? al(static_cast<size_t>(N) * abar_stride(K, n_mono(PA), static_cast<int>(tsize)) * tsize) : 0;
-    L.centre = o; o += al((static_cast<size_t>(P) + 1) * sizeof(int));      // entry P: spare for empty slots
-    L.pdv = o; o += al((static_cast<size_t>(P) + 1) * 3 * tsize);
+    L.abar = o;
+    o += (back && !wide) ? al(static_cast<size_t>(N) * abar_stride(K, n_mono(PA), static_cast<int>(tsize)) * tsize) : 0;
+    L.centre = o; o += wide ? 0 : al((static_cast<size_t>(P) + 1) * sizeof(int));   // entry P: spare for empty slots
+    L.pdv = o; o += wide ? 0 : al((static_cast<size_t>(P) + 1) * 3 * tsize);
     L.gbuf = o; o += gather ? al(static_cast<size_t>(P > 0 ? P : 1) * 3 * tsize) : 0;
     L.gown = o; o += gather ? al(static_cast<size_t>(P > 0 ? P : 1) * 3 * tsize) : 0;
+    L.rec = o; o += wide ? al(static_cast<size_t>(P > 0 ? P : 1) * wide_rec_stride(K, true) * tsize) : 0;
     L.total = o;
     return L;
 }
@@ -1132,6 +1112,41 @@ int energy_forces_run(pod_handle* h, char* scratch, double* facc, int N, int P, 
     a.want_G = G != nullptr;
     a.want_back = back;
     a.y_net = y_net; a.g_net = g_net; a.n_net = n_net;
+    if (wide_path(h->K, h->PA)) {
+        if constexpr (MODE != 1) return POD_ENOTSUP;
+        // wide-degree kernel: energy, G and pair gradients in one launch
+        WideArgs<T> w = wide_args(a);
+        const int nblk_w = wide_blocks(N);
+        w.wpart = reinterpret_cast<double*>(scratch + L.wpart);
+        w.gbuf = gather ? reinterpret_cast<T*>(scratch + L.gbuf) : nullptr;
+        w.gown = gather ? reinterpret_cast<T*>(scratch + L.gown) : nullptr;
+        w.rev = gather ? rev : nullptr;
+        w.Facc = (back && !gather) ? facc : nullptr;
+        w.rec = reinterpret_cast<T*>(scratch + L.rec);
+        w.rs = wide_rec_stride(h->K, true);
+        w.want_W = W != nullptr;
+        timing_begin(h, 1);
+        const hipError_t e = launch_wide<T>(w, 1, h->std_ok != 0, nblk_w, h->stream);
+        timing_end(h, 1);
+        if (e != hipSuccess) return POD_EHIP;
+        FinArgs<T> fa;
+        fa.part = a.part;
+        fa.nblk = nblk_w; fa.ncol = ncol;
+        fa.wpart = w.wpart; fa.nblk_p = back ? nblk_w : 0;
+        fa.E = E; fa.W = back ? W : nullptr; fa.G = G;
+        fa.Facc = facc; fa.F = static_cast<T*>(F);
+        fa.n3 = (back && !gather) ? 3L * N : 0L;
+        fa.gbuf = w.gbuf; fa.gown = w.gown; fa.rev = gather ? rev : nullptr; fa.offsets = offsets;
+        fa.N = N; fa.P = P; fa.err = h->d_err;
+        const int nfb = gather ? (N + 7) / 8 : static_cast<int>((fa.n3 + 255) / 256);
+        if (E || W || G || nfb > 0) {
+            timing_begin(h, 0);
+            hipLaunchKernelGGL((finalize_kernel<T>), dim3(ncol + nfb), dim3(256), 0, h->stream, fa);
+            timing_end(h, 0);
+            if (hipGetLastError() != hipSuccess) return POD_EHIP;
+        }
+        return POD_OK;
+    }
     if (nblk > 0) {
         timing_begin(h, 1);
         const hipError_t e = dispatch_pa<T, MODE>(h->PA, a, h->std_ok != 0, nblk,
@@ -1327,7 +1342,7 @@ int pod_energy_forces_surrogate(pod_handle* h, int N, int P, const void* pos, co
     if (pod::bad_common(h, N, P, pos, offsets, nbr_j, shift)) return POD_EINVAL;
     if (!c || !theta || !mu || !inv_sigma) return POD_EINVAL;
     if (h->K4 != 0) return POD_EINVAL;
-    if (h->M - 1 < 1 || h->M - 1 > POD_MLP_MAX_IN) return POD_ENOTSUP;
+    if (h->M - 1 < 1 || h->M - 1 > POD_MLP_MAX_IN || pod::wide_path(h->K, h->PA)) return POD_ENOTSUP;
     if (h->dtype == POD_F64)
         return pod::surrogate_impl<double>(h, N, P, pos, cell, offsets, nbr_j, shift, rev, c, theta, mu, inv_sigma,
                                            E_atom, E, F, W);

@@ -4,7 +4,8 @@
 //   4-body  eq. (20a): sum over neighbour triples j < k < l  O(N_i^3), with
 //           the cyclic angular functions g_p of eq. (19a) / Table 2
 // and the linear 2/3-body model built on them (OPOD of Table 6) with its
-// forces.  One wavefront per atom; the atom's neighbours (unit vectors,
+// forces, up to the largest sizes of Table 6 (K = 12, 3-body degree 10,
+// 4-body degree 6).  One wavefront per atom; the atom's neighbours (unit vectors,
 // distances, R_m and R'_m) are staged in LDS once, then the pair and triple
 // loops read them from there.  FP64.
 #include <hip/hip_runtime.h>
@@ -14,6 +15,7 @@
 #include "pod.h"
 #include "pod_device.h"
 #include "pod_internal.h"
+#include "pod_tables.h"
 
 namespace pod {
 namespace {
@@ -21,19 +23,27 @@ namespace {
 using namespace dev;
 
 constexpr int OPOD_NMAX = 128;   // neighbours within rcut per atom (else POD_ENEIGH)
-constexpr int OPOD_P4MAX = 4;    // Table 2 range of the 4-body angular functions
-constexpr int OPOD_KA = 11;      // g_p with n <= 4
-constexpr int OPOD_MC = 4;       // radial indices per 4-body accumulator chunk
 
-// g_p terms (Table 2): for each p in Table-1 order the distinct members of
-// the cyclic orbit {(a,b,c), (c,a,b), (b,c,a)} of the exponents of
-// (w_ijk, w_ijl, w_ikl).
+// 4-body descriptor instances: angular degree up to 4 (Table 2, 11 functions
+// g_p, four radial indices per accumulator pass) and up to 6 (eq. (19a) for
+// n = 5, 6 as well: 23 functions, two radial indices per pass).
+template <int P4MAX>
+struct OpodD4 {
+    static constexpr int KA = n_partitions(P4MAX);
+    static constexpr int MC = P4MAX <= 4 ? 4 : 2;
+};
+
+// g_p terms (eq. (19a), Table 2 for n <= 4): for each p in Table-1 order the
+// distinct members of the cyclic orbit {(a,b,c), (c,a,b), (b,c,a)} of the
+// exponents of (w_ijk, w_ijl, w_ikl).
+template <int P4MAX>
 struct GTable {
-    int nterm[OPOD_KA];
-    int e[OPOD_KA][3][3];
+    static constexpr int KA = n_partitions(P4MAX);
+    int nterm[KA];
+    int e[KA][3][3];
     constexpr GTable() : nterm{}, e{} {
         int p = 0;
-        for (int n = 0; n <= OPOD_P4MAX; ++n)
+        for (int n = 0; n <= P4MAX; ++n)
             for (int a = n; a >= 0; --a)
                 for (int b = (a < n - a ? a : n - a); b >= 0; --b) {
                     const int c = n - a - b;
@@ -74,23 +84,27 @@ struct OArgs {
 };
 
 // Neighbour staging: unit vector, distance, R_m, R'_m of every neighbour of
-// atom i (absent pairs -- r >= rcut -- get R = R' = 0 and u = 0).
+// atom i (absent pairs -- r >= rcut -- get R = R' = 0 and u = 0).  KS radial
+// slots: FAST_MAX_K for models with K up to 8 (less LDS, more workgroups per
+// CU), POD_MAX_K otherwise.
+template <int KS>
 struct Stage {
     double u[OPOD_NMAX][3];
     double r[OPOD_NMAX];
-    double R[OPOD_NMAX][POD_MAX_K];
-    double dR[OPOD_NMAX][POD_MAX_K];
+    double R[OPOD_NMAX][KS];
+    double dR[OPOD_NMAX][KS];
     int ok[OPOD_NMAX];   // a neighbour within rcut with a valid index
 };
 
-__device__ __forceinline__ void stage_neighbours(const OArgs& a, int i, int p0, int n, int lane, Stage& s) {
+template <int KS>
+__device__ __forceinline__ void stage_neighbours(const OArgs& a, int i, int p0, int n, int lane, Stage<KS>& s) {
     const double pi0 = a.pos[3 * i], pi1 = a.pos[3 * i + 1], pi2 = a.pos[3 * i + 2];
     for (int t = lane; t < n; t += WAVE) {
         const int p = p0 + t;
         const int j = a.nbr_j[p];
         const int sh = a.shift[p];
         double u[3] = {0.0, 0.0, 0.0}, r = 0.5 * (a.prm.rin + a.prm.rcut);
-        double R[POD_MAX_K], dR[POD_MAX_K];
+        double R[KS], dR[KS];
         bool ok = false;
         if (j < 0 || j >= a.N || (!a.cell.periodic && (sh & 0xFFFFFF) != 0)) {
             atomicOr(a.err, ERR_NEIGH);
@@ -123,7 +137,7 @@ __device__ __forceinline__ void stage_neighbours(const OArgs& a, int i, int p0, 
         s.r[t] = r;
         s.ok[t] = ok ? 1 : 0;
 #pragma unroll
-        for (int m = 0; m < POD_MAX_K; ++m) {
+        for (int m = 0; m < KS; ++m) {
             s.R[t][m] = ok ? R[m] : 0.0;
             s.dR[t][m] = ok ? dR[m] : 0.0;
         }
@@ -131,9 +145,13 @@ __device__ __forceinline__ void stage_neighbours(const OArgs& a, int i, int p0, 
 }
 
 // Exclusive descriptors [1 | D2 | D3 (eq. (15b)) | D4 (eq. (20a))].
+template <int P4MAX, int KS, int P3MAX>
 __global__ __launch_bounds__(WAVE) void opod_desc_kernel(OArgs a) {
-    constexpr GTable gt{};
-    __shared__ Stage s;
+    constexpr GTable<P4MAX> gt{};
+    constexpr int OPOD_KA = OpodD4<P4MAX>::KA;
+    constexpr int OPOD_MC = OpodD4<P4MAX>::MC;
+    constexpr int OPOD_P4MAX = P4MAX;
+    __shared__ Stage<KS> s;
     const int i = blockIdx.x;
     const int lane = threadIdx.x;
     const int p0 = a.offsets[i], n = a.offsets[i + 1] - p0;
@@ -156,23 +174,23 @@ __global__ __launch_bounds__(WAVE) void opod_desc_kernel(OArgs a) {
     }
     // 3-body: lane j sums over k > j (eq. (15b))
     for (int m = 0; m < K3; ++m) {
-        double acc[POD_MAX_P + 1];
+        double acc[P3MAX + 1];
 #pragma unroll
-        for (int q = 0; q <= POD_MAX_P; ++q) acc[q] = 0.0;
+        for (int q = 0; q <= P3MAX; ++q) acc[q] = 0.0;
         for (int j = lane; j < n; j += WAVE) {
             const double Rj = s.R[j][m];
             for (int k = j + 1; k < n; ++k) {
                 const double w = s.u[j][0] * s.u[k][0] + s.u[j][1] * s.u[k][1] + s.u[j][2] * s.u[k][2];
                 double x = Rj * s.R[k][m];
 #pragma unroll
-                for (int q = 0; q <= POD_MAX_P; ++q) {
+                for (int q = 0; q <= P3MAX; ++q) {
                     if (q <= P3) acc[q] += x;
                     x *= w;
                 }
             }
         }
 #pragma unroll
-        for (int q = 0; q <= POD_MAX_P; ++q) {
+        for (int q = 0; q <= P3MAX; ++q) {
             const double v = wave_sum(acc[q]);
             if (lane == 0 && q <= P3) Drow[a.prm.off3 + m * (P3 + 1) + q] = v;
         }
@@ -245,8 +263,9 @@ __global__ __launch_bounds__(WAVE) void opod_desc_kernel(OArgs a) {
 //   X_jk = R_m(r_ij) R_m(r_ik) P_m(w),  P_m(w) = sum_n c3_mn w^n
 //   dE_i/dr_ij = sum_k sum_m [R'_m(r_ij) R_m(r_ik) P_m u_j
 //                             + R_m R_m P'_m (u_k - w u_j) / r_ij]
+template <int KS>
 __global__ __launch_bounds__(WAVE) void opod_energy_kernel(OArgs a) {
-    __shared__ Stage s;
+    __shared__ Stage<KS> s;
     __shared__ double cf[1 + POD_MAX_K + POD_MAX_K * (POD_MAX_P + 1)];
     const int i = blockIdx.x;
     const int lane = threadIdx.x;
@@ -405,14 +424,25 @@ int pod_opod_descriptors(pod_handle* h, int N, int P, const void* pos, const dou
     if (!h || N < 0 || P < 0) return POD_EINVAL;
     if (N > 0 && (!pos || !offsets || !D || (P > 0 && (!nbr_j || !shift)))) return POD_EINVAL;
     if (h->dtype != POD_F64) return POD_ENOTSUP;
-    if (h->K4 > 0 && h->P4 > OPOD_P4MAX) return POD_ENOTSUP;
+    if (h->K4 > 0 && h->P4 > POD_MAX_P4) return POD_ENOTSUP;
     if (N == 0) return POD_OK;
     OArgs a;
     const int rc = fill(h, a, N, pos, cell, offsets, nbr_j, shift);
     if (rc != POD_OK) return rc;
     a.D = static_cast<double*>(D);
     timing_begin(h, 1);
-    hipLaunchKernelGGL(opod_desc_kernel, dim3(N), dim3(WAVE), 0, h->stream, a);
+    // instances: 4-body degree up to 4 or 6; K up to 8 with 3-body degree up
+    // to 6, or the largest sizes
+    const bool p6 = h->K4 > 0 && h->P4 > 4;
+    const bool big = h->K > FAST_MAX_K || (h->K3 > 0 && h->P3 > FAST_MAX_PA);
+    if (p6 && big)
+        hipLaunchKernelGGL((opod_desc_kernel<POD_MAX_P4, POD_MAX_K, POD_MAX_P>), dim3(N), dim3(WAVE), 0, h->stream, a);
+    else if (p6)
+        hipLaunchKernelGGL((opod_desc_kernel<POD_MAX_P4, FAST_MAX_K, FAST_MAX_PA>), dim3(N), dim3(WAVE), 0, h->stream, a);
+    else if (big)
+        hipLaunchKernelGGL((opod_desc_kernel<4, POD_MAX_K, POD_MAX_P>), dim3(N), dim3(WAVE), 0, h->stream, a);
+    else
+        hipLaunchKernelGGL((opod_desc_kernel<4, FAST_MAX_K, FAST_MAX_PA>), dim3(N), dim3(WAVE), 0, h->stream, a);
     timing_end(h, 1);
     return hipGetLastError() == hipSuccess ? POD_OK : POD_EHIP;
 }
@@ -438,7 +468,8 @@ int pod_opod_energy_forces(pod_handle* h, int N, int P, const void* pos, const d
     a.part = static_cast<double*>(h->d_scratch);
     if (N > 0) {
         timing_begin(h, 1);
-        hipLaunchKernelGGL(opod_energy_kernel, dim3(N), dim3(WAVE), 0, h->stream, a);
+        if (h->K > FAST_MAX_K) hipLaunchKernelGGL(opod_energy_kernel<POD_MAX_K>, dim3(N), dim3(WAVE), 0, h->stream, a);
+        else hipLaunchKernelGGL(opod_energy_kernel<FAST_MAX_K>, dim3(N), dim3(WAVE), 0, h->stream, a);
         timing_end(h, 1);
     }
     const long n3 = F ? 3L * N : 0L;

@@ -92,7 +92,7 @@ int validate_params(const pod_params* p) {
     const int K = std::max(p->K2, std::max(p->K3, p->K4));
     if (K < 1 || K > p->L) return POD_EINVAL;
     if (K > POD_MAX_K) return POD_ENOTSUP;
-    if (p->P3 > POD_MAX_P || p->P4 > POD_MAX_P) return POD_ENOTSUP;
+    if (p->P3 > POD_MAX_P || p->P4 > POD_MAX_P4) return POD_ENOTSUP;
     if (p->dtype != POD_F64 && p->dtype != POD_F32) return POD_EINVAL;
     if (p->n_quad != 0 && p->n_quad < 2 * p->L) return POD_EINVAL;
     if (p->Q) {

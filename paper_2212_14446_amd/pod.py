@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libpod.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "pod.h")
 
 POD_F64, POD_F32 = 0, 1
-POD_MAX_L, POD_MAX_K, POD_MAX_P = 16, 8, 6
+POD_MAX_L, POD_MAX_K, POD_MAX_P, POD_MAX_P4 = 16, 12, 10, 6
 POD_MLP_HIDDEN, POD_MLP_MAX_IN = 64, 64
 ERRORS = {0: "POD_OK", -1: "POD_EINVAL", -2: "POD_ERANGE", -3: "POD_ENONFINITE", -4: "POD_ENOMEM",
           -5: "POD_EHIP", -6: "POD_ENOTSUP", -7: "POD_ENEIGH", -8: "POD_ESINGULAR", -9: "POD_ETOOBIG"}

@@ -105,6 +105,14 @@ void test_validation() {
         {"all K zero", POD_EINVAL, [](Family& f) { f.p.K2 = f.p.K3 = f.p.K4 = 0; }},
         {"K > L", POD_EINVAL, [](Family& f) { f.p.K3 = f.p.L + 1; }},
         {"P3 > max", POD_ENOTSUP, [](Family& f) { f.p.P3 = POD_MAX_P + 1; }},
+        {"P4 > max", POD_ENOTSUP, [](Family& f) { f.p.P4 = POD_MAX_P4 + 1; }},
+        {"K > max", POD_ENOTSUP, [](Family& f) {
+             f.p.L = POD_MAX_L;
+             f.alpha.resize(POD_MAX_L, 1.0); f.beta.resize(POD_MAX_L, 0.0);
+             f.gamma.resize(POD_MAX_L, 1.0); f.kappa.resize(POD_MAX_L, 0.0);
+             f.p.alpha = f.alpha.data(); f.p.beta = f.beta.data(); f.p.gamma = f.gamma.data();
+             f.p.kappa = f.kappa.data();
+             f.p.K4 = POD_MAX_K + 1; }},
         {"P4 < 0", POD_EINVAL, [](Family& f) { f.p.P4 = -2; }},
         {"dtype", POD_EINVAL, [](Family& f) { f.p.dtype = 7; }},
         {"n_quad < 2L", POD_EINVAL, [](Family& f) { f.p.n_quad = 3; }},

@@ -97,7 +97,34 @@ def test_errors():
     with pytest.raises(pod.PodError) as e:
         m32.opod_descriptors(w.pos, w.cell, nb)
     assert pod.ERRORS[e.value.code] == "POD_ENOTSUP"
-    m6 = pod.PodModel(pod.setup_from_workload(wl.PodSetup(0.5, 5.0, 8, 2, 2, 2, 2, 5)), "f64")
-    with pytest.raises(pod.PodError) as e:   # g_p beyond Table 2
-        m6.opod_descriptors(w.pos, w.cell, nb)
-    assert pod.ERRORS[e.value.code] == "POD_ENOTSUP"
+
+
+
+# The largest sizes of Table 6 (rows 5 and 6: K up to 12, 3-body degree 8
+# and 10, 4-body degree 5 and 6, whose g_p of eq. (19a) go beyond Table 2),
+# on a 16-atom box, against the exclusive-sum oracle.
+@pytest.mark.parametrize("setup", [wl.PodSetup(0.5, 5.0, 14, 10, 9, 9, 8, 5),
+                                   wl.PodSetup(0.5, 5.0, 14, 8, 12, 12, 10, 6),
+                                   wl.PodSetup(0.5, 5.0, 8, 2, 2, 2, 2, 5)])
+def test_descriptors_table6_large_rows(setup):
+    w = wl.small_bcc(2, sigma=0.15, seed=33, setup=setup)
+    say(f"[gpu] opod descriptors K={setup.K2},{setup.K3},{setup.K4} P={setup.P3},{setup.P4} N={w.N}")
+    m, p, Q = _model(setup)
+    D = m.opod_descriptors(w.pos, w.cell, pod.DeviceNeighbors.from_list(w.nl)).cpu().numpy()
+    ref = oo.descriptors(*_args(w, p, Q), atoms=np.arange(w.N))
+    assert colerr(D, ref) <= 1e-10
+
+
+@pytest.mark.parametrize("setup", [wl.PodSetup(0.5, 5.0, 14, 10, 9, 0, 8, 0),
+                                   wl.PodSetup(0.5, 5.0, 14, 8, 12, 0, 10, 0)])
+def test_energy_forces_table6_large_rows(setup):
+    w = wl.small_bcc(2, sigma=0.15, seed=34, setup=setup)
+    say(f"[gpu] opod energy K2={setup.K2} K3={setup.K3} P3={setup.P3} N={w.N}")
+    m, p, Q = _model(setup)
+    c = wl.coefficients(setup.M, 8)
+    o = m.opod_energy_forces(w.pos, w.cell, pod.DeviceNeighbors.from_list(w.nl), c)
+    ref = oo.energy_forces(*_args(w, p, Q), c)
+    assert relerr(o["E"].item(), ref["E"]) <= 1e-10
+    assert relerr(o["E_atom"].cpu().numpy(), ref["E_atom"]) <= 1e-10
+    assert relerr(o["F"].cpu().numpy(), ref["F"]) <= 1e-10
+    assert relerr(o["W"].cpu().numpy(), ref["W"]) <= 1e-10

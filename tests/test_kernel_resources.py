@@ -1,7 +1,8 @@
 """Register and scratch use of the energy path's benchmark kernel instances
-(FP64 and FP32, K = 6, angular degree 4, standard snapshot family), read
-from the compiler's resource-usage remarks of a device-only gfx950 compile
-of csrc/pod_kernels.hip with the library's flags.  The test fails when an
+(FP64 and FP32, K = 6, angular degree 4, standard snapshot family) and of the
+wide-degree kernels, read from the compiler's resource-usage remarks of a
+device-only gfx950 compile of csrc/pod_kernels.hip and csrc/pod_wide.hip with
+the library's flags.  The test fails when an
 instance spills (scratch above the recorded bound) or loses occupancy, so a
 change that pushes a hot kernel into scratch memory is caught on the CPU."""
 import shutil
@@ -21,11 +22,26 @@ RECORDED = {
 }
 
 
+# wide-degree path (degree 7 to 10, K up to 12): no spill in any instance
+WIDE_RECORDED = {
+    "void wide_kernel<double, 0>(pod::WideArgs<double>)": (0, 4),
+    "void wide_kernel<double, 1>(pod::WideArgs<double>)": (0, 2),
+    "void wide_kernel<float, 1>(pod::WideArgs<float>)": (0, 2),
+}
+
+
 @pytest.fixture(scope="module")
 def resources():
     if not shutil.which(build_lib.hipcc()) and not shutil.which("hipcc"):
         pytest.skip("hipcc not available")
     return build_lib.kernel_resources("pod_kernels.hip")
+
+
+@pytest.fixture(scope="module")
+def wide_resources():
+    if not shutil.which(build_lib.hipcc()) and not shutil.which("hipcc"):
+        pytest.skip("hipcc not available")
+    return build_lib.kernel_resources("pod_wide.hip")
 
 
 @pytest.mark.parametrize("name", sorted(RECORDED))
@@ -42,3 +58,12 @@ def test_no_energy_path_instance_spills_much(resources):
     # degree-6 FP64 descriptor instance (one wavefront per SIMD, 256 + 256 registers)
     worst = max((r["scratch"], n) for n, r in resources.items())
     assert worst[0] <= 20, worst
+
+
+@pytest.mark.parametrize("name", sorted(WIDE_RECORDED))
+def test_wide_instances_within_recorded_registers(wide_resources, name):
+    assert name in wide_resources, f"instance {name} not compiled"
+    max_scratch, min_occ = WIDE_RECORDED[name]
+    r = wide_resources[name]
+    assert r["scratch"] <= max_scratch and r["occupancy"] >= min_occ, (name, r)
+    assert max(v["scratch"] for v in wide_resources.values()) == 0
