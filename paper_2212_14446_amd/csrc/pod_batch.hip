@@ -185,14 +185,14 @@ __global__ __launch_bounds__(MAX_THREADS) void batch_kernel(BArgs g) {
                 }
             }
             const double ri = 1.0 / r;
-            double R[POD_MAX_K], dR[POD_MAX_K];
+            double R[FAST_MAX_K], dR[FAST_MAX_K];
             if constexpr (FAST) radial_std<double, true>(P, sQ, r, ri, R, dR);
             else radial<double, true>(P, r, ri, R, dR);
             const double z = ok ? 1.0 : 0.0;
             double* row = rec + static_cast<size_t>(pp) * SR;
             row[0] = d0 * ri * z; row[1] = d1 * ri * z; row[2] = d2 * ri * z; row[3] = ri;
 #pragma unroll
-            for (int k = 0; k < POD_MAX_K; ++k)
+            for (int k = 0; k < FAST_MAX_K; ++k)
                 if (k < K) { row[4 + k] = R[k] * z; row[4 + K + k] = dR[k] * z; }
         }
         for (int k = tid; k < M; k += nth) sG[k] = 0.0;
@@ -276,12 +276,27 @@ __global__ __launch_bounds__(MAX_THREADS) void batch_kernel(BArgs g) {
                             jacobian_row<PA>(kind, idx, b, J);
                         }
                         double s0 = 0.0, s1 = 0.0, s2 = 0.0;   // -sum_j v_ij, the centre's own row
-                        const int pe = sOff[a + 1] - p0;
-                        for (int pp = sOff[a] - p0; pp < pe; ++pp) {
-                            const int jl = g.nbr_j[p0 + pp] - a0;
-                            const double* row = rec + static_cast<size_t>(pp) * SR;
-                            const double ux = row[0], uy = row[1], uz = row[2], ri = row[3];
-                            const double Rm = row[4 + m], dRm = row[4 + K + m];
+                        const int pb = sOff[a] - p0, pe = sOff[a + 1] - p0;
+                        // the next pair's record is requested before this pair's
+                        // arithmetic (the loop is bound by these loads' latency otherwise)
+                        int nj = 0;
+                        double nux = 0, nuy = 0, nuz = 0, nri = 0, nRm = 0, ndRm = 0;
+                        if (pb < pe) {
+                            const double* row = rec + static_cast<size_t>(pb) * SR;
+                            nj = g.nbr_j[p0 + pb];
+                            nux = row[0]; nuy = row[1]; nuz = row[2]; nri = row[3];
+                            nRm = row[4 + m]; ndRm = row[4 + K + m];
+                        }
+                        for (int pp = pb; pp < pe; ++pp) {
+                            const int jl = nj - a0;
+                            const double ux = nux, uy = nuy, uz = nuz, ri = nri;
+                            const double Rm = nRm, dRm = ndRm;
+                            if (pp + 1 < pe) {
+                                const double* row = rec + static_cast<size_t>(pp + 1) * SR;
+                                nj = g.nbr_j[p0 + pp + 1];
+                                nux = row[0]; nuy = row[1]; nuz = row[2]; nri = row[3];
+                                nRm = row[4 + m]; ndRm = row[4 + K + m];
+                            }
                             double A[NA];
                             A[0] = 1.0;
 #pragma unroll
@@ -382,7 +397,7 @@ int pod_batch_assemble(pod_handle* h, int n_cfg, int N, int P, const int* cfg_at
                        double* G, double* dGdR, const pod_tune* tune) {
     using namespace pod;
     if (!h || n_cfg < 0 || N < 0 || P < 0) return POD_EINVAL;
-    if (h->dtype != POD_F64) return POD_ENOTSUP;
+    if (h->dtype != POD_F64 || h->PA > FAST_MAX_PA || h->K > FAST_MAX_K) return POD_ENOTSUP;
     if (n_cfg == 0 || N == 0) return POD_OK;
     if (!cfg_atom_off || !pos || !cells || !offsets || (P > 0 && (!nbr_j || !shift))) return POD_EINVAL;
     // plan on the host: cell sizes and pair counts

@@ -55,10 +55,10 @@ struct WideLds {
 __host__ __device__ constexpr size_t wide_align(size_t b) { return (b + 15) & ~size_t(15); }
 
 // ints of the packed 4-body tables: per index p its triple and term range
-// (3 KA4), the terms (NT4), the occurrence ranges (NA4 + 1) and the
-// occurrences (3 NT4)
+// (3 KA4), the terms (NT4), the occurrence ranges (NA4 + 1), the
+// occurrences (3 NT4) and the index of (a, 0, 0) per degree a
 __host__ __device__ constexpr int wide_tab_ints() {
-    return 3 * n_partitions(POD_MAX_P4) + 4 * D4Table<POD_MAX_P4>::NT + n_mono(POD_MAX_P4) + 1;
+    return 3 * n_partitions(POD_MAX_P4) + 4 * D4Table<POD_MAX_P4>::NT + n_mono(POD_MAX_P4) + 1 + POD_MAX_P4 + 1;
 }
 
 __host__ __device__ constexpr WideLds wide_lds(int K, int PA, int M, bool four, int tsize) {

@@ -66,13 +66,14 @@ static_assert(GSUB == 8, "the gradient reduction assumes eight lanes per pair");
 // every monomial n < NA4 its occurrences in the terms, p | u << 5 | v << 12 |
 // coefficient << 19 (u, v the other two monomials).  The packed layout is
 // the one copied to LDS: [ptri KA4][tbeg KA4][tend KA4][term NT4][obeg NA4+1]
-// [occ 3 NT4].
+// [occ 3 NT4][index of (a, 0, 0) for a <= POD_MAX_P4].  The occurrences of a
+// monomial are in term order, hence sorted by p.
 struct WideTables {
     int code[NA_MAX];
     int tab[wide_tab_ints()];
 };
 constexpr int T_PTRI = 0, T_TBEG = KA4, T_TEND = 2 * KA4, T_TERM = 3 * KA4, T_OBEG = 3 * KA4 + NT4,
-              T_OCC = 3 * KA4 + NT4 + NA4 + 1;
+              T_OCC = 3 * KA4 + NT4 + NA4 + 1, T_PA00 = 3 * KA4 + 4 * NT4 + NA4 + 1;
 
 constexpr WideTables make_wide_tables() {
     WideTables w{};
@@ -87,6 +88,7 @@ constexpr WideTables make_wide_tables() {
     }
     for (int k = 0; k < NT4; ++k)
         w.tab[T_TERM + k] = d4.tx[k] | (d4.ty[k] << 7) | (d4.tz[k] << 14) | (d4.tc[k] << 21);
+    for (int a = 0; a <= POD_MAX_P4; ++a) w.tab[T_PA00 + a] = n_partitions(a - 1);
     int cnt[NA4] = {};
     for (int k = 0; k < NT4; ++k) { ++cnt[d4.tx[k]]; ++cnt[d4.ty[k]]; ++cnt[d4.tz[k]]; }
     w.tab[T_OBEG] = 0;
@@ -114,7 +116,7 @@ static_assert(NA4 <= 128 && KA4 <= 32 && POD_MAX_P <= 15 && wide_max_term_coef()
 __device__ const WideTables kWide = make_wide_tables();
 
 // 4-body index of the triple (a, 0, 0): the first triple of degree a.
-__device__ __forceinline__ int p_a00(int a) { return n_partitions(a - 1); }
+__device__ __forceinline__ int p_a00(const int* tab, int a) { return tab[T_PA00 + a]; }
 
 // Sum over the workgroup in a fixed order (shuffles within each wavefront,
 // then the four wavefront sums in order); every thread gets the result.
@@ -312,12 +314,19 @@ __global__ __launch_bounds__(WT) void wide_kernel(WideArgs<T> g) {
                 if ((tri >> 4) == 0) {
                     v = Bk[0] * sS[k * PA1 + (tri & 15)];                           // eq. (27a)
                 } else {
-                    v = T(0);
+                    T v0 = T(0), v1 = T(0);
                     const int t1 = sTab[T_TEND + p];
-                    for (int t = sTab[T_TBEG + p]; t < t1; ++t) {                   // eq. (30a)
-                        const int tm = sTab[T_TERM + t];
-                        v += T(tm >> 21) * Bk[tm & 127] * Bk[(tm >> 7) & 127] * Bk[(tm >> 14) & 127];
+                    int t = sTab[T_TBEG + p];
+                    for (; t + 1 < t1; t += 2) {                                    // eq. (30a)
+                        const int ta = sTab[T_TERM + t], tb = sTab[T_TERM + t + 1];
+                        v0 += T(ta >> 21) * Bk[ta & 127] * Bk[(ta >> 7) & 127] * Bk[(ta >> 14) & 127];
+                        v1 += T(tb >> 21) * Bk[tb & 127] * Bk[(tb >> 7) & 127] * Bk[(tb >> 14) & 127];
                     }
+                    if (t < t1) {
+                        const int ta = sTab[T_TERM + t];
+                        v0 += T(ta >> 21) * Bk[ta & 127] * Bk[(ta >> 7) & 127] * Bk[(ta >> 14) & 127];
+                    }
+                    v = v0 + v1;
                 }
             }
             if constexpr (MODE == 0) {
@@ -365,15 +374,29 @@ __global__ __launch_bounds__(WT) void wide_kernel(WideArgs<T> g) {
                     if (k < K4) {
                         const T* c4 = cf + off4 + k * KA;
                         if (nn == 0)
-                            for (int a = 0; a <= P4; ++a) v += c4[p_a00(a)] * sS[k * PA1 + a];   // eq. (27a)
-                        if (dg <= P4) v += c4[p_a00(dg)] * B0 * T(2) * mult * Bn;
+                            for (int a = 0; a <= P4; ++a) v += c4[p_a00(sTab, a)] * sS[k * PA1 + a];   // eq. (27a)
+                        if (dg <= P4) v += c4[p_a00(sTab, dg)] * B0 * T(2) * mult * Bn;
                         if (nn < NA4) {
-                            const int o1 = sTab[T_OBEG + nn + 1];
-                            for (int o = sTab[T_OBEG + nn]; o < o1; ++o) {                  // eq. (30a)
-                                const int oc = sTab[T_OCC + o];
-                                const int p = oc & 31;
-                                if (p < KA) v += c4[p] * T(oc >> 19) * Bk[(oc >> 5) & 127] * Bk[(oc >> 12) & 127];
+                            // occurrences are sorted by p: stop at the first p of a
+                            // higher degree than the model's; four at a time
+                            const int o0 = sTab[T_OBEG + nn], o1 = sTab[T_OBEG + nn + 1];
+                            T v4 = T(0);
+                            int o = o0;
+                            for (; o + 3 < o1; o += 4) {                                      // eq. (30a)
+                                const int oa = sTab[T_OCC + o], ob = sTab[T_OCC + o + 1];
+                                const int oc = sTab[T_OCC + o + 2], od = sTab[T_OCC + o + 3];
+                                if ((od & 31) >= KA) break;
+                                v4 += c4[oa & 31] * T(oa >> 19) * Bk[(oa >> 5) & 127] * Bk[(oa >> 12) & 127];
+                                v4 += c4[ob & 31] * T(ob >> 19) * Bk[(ob >> 5) & 127] * Bk[(ob >> 12) & 127];
+                                v4 += c4[oc & 31] * T(oc >> 19) * Bk[(oc >> 5) & 127] * Bk[(oc >> 12) & 127];
+                                v4 += c4[od & 31] * T(od >> 19) * Bk[(od >> 5) & 127] * Bk[(od >> 12) & 127];
                             }
+                            for (; o < o1; ++o) {
+                                const int oa = sTab[T_OCC + o];
+                                if ((oa & 31) >= KA) break;
+                                v4 += c4[oa & 31] * T(oa >> 19) * Bk[(oa >> 5) & 127] * Bk[(oa >> 12) & 127];
+                            }
+                            v += v4;
                         }
                     }
                     ab[j] = v;
