@@ -40,8 +40,8 @@ METRIC = "atoms/s for POD energy+forces (FP64/FP32) and MLP-surrogate speedup at
 PEAK_F64 = 78.6e12    # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz, FP64 vector
 PEAK_F32 = 157.3e12   # published FP32 vector peak (packed); unpacked issue gives 78.6e12
 KERNEL_SOURCES = ["paper_2212_14446_amd/csrc/pod_kernels.hip", "paper_2212_14446_amd/csrc/pod_tables.h",
-                  "paper_2212_14446_amd/csrc/pod_device.h",
-                  "paper_2212_14446_amd/csrc/pod_internal.h"]
+                  "paper_2212_14446_amd/csrc/pod_device.h", "paper_2212_14446_amd/csrc/pod_internal.h",
+                  "paper_2212_14446_amd/csrc/pod_wide.h"]
 
 
 def kernel_hash():
