@@ -284,10 +284,12 @@ int pod_mlp_train_step(pod_handle* h, int n, int n_in, const float* X, long ldx,
  * for a handle without 4-body descriptors (K4 = 0; n_in = M - 1 inputs,
  * else POD_EINVAL / POD_ENOTSUP).  Forces follow eq. (673a): the adjoint of
  * atom i takes the weights c + (0, dy/dX_i) on its descriptors, then the
- * pair sweep of eq. (24c) as in pod_energy_forces.  Three kernels on the
- * handle's stream: descriptors, network forward + input gradient, energy and
- * adjoint.  Arguments as for pod_energy_forces (no G); theta, mu, inv_sigma
- * as for pod_mlp_forward. */
+ * pair sweep of eq. (24c) as in pod_energy_forces.  The per-atom kernel
+ * runs the network on its own descriptors (the same products and rounding
+ * as pod_mlp_forward, so the results equal those of pod_descriptors followed
+ * by pod_mlp_forward); before it a small kernel packs the weights into the
+ * handle's network scratch.  Arguments as for pod_energy_forces (no G);
+ * theta, mu, inv_sigma as for pod_mlp_forward. */
 int pod_energy_forces_surrogate(pod_handle* h, int N, int P, const void* pos, const double* cell,
                                 const int* offsets, const int* nbr_j, const int* shift,
                                 const int* rev, const void* c, const float* theta, const float* mu,
@@ -485,9 +487,11 @@ void pod_acsf_free(pod_acsf* a);
  * batched-assembly kernel; kind 4: the pair-gradient kernel of the energy
  * calls (per-pair gradients, own-atom sums, virial); kind 0: the finalize
  * kernel (totals E, W, G and the force gather or copy-out); kind 2: the
- * network kernels; kind 3: the Gram kernels of pod_fit_gram; for the
- * symmetry functions, kind 1 times the basis kernels and kind 0 the
- * pair-gradient and gather kernels -- then resets that count. */
+ * network kernels (for the surrogate: its weight packing; its network runs
+ * inside the per-atom kernel, kind 1); kind 3: the Gram kernels of
+ * pod_fit_gram; for the symmetry functions, kind 1 times the basis kernels
+ * and kind 0 the pair-gradient and gather kernels -- then resets that
+ * count. */
 int pod_set_kernel_timing(pod_handle* h, int n);
 int pod_get_kernel_time(pod_handle* h, int kind, double* total_ms, int* launches);
 

@@ -118,4 +118,11 @@ void timing_end(pod_handle* h, int kind);
 // Network forward + input gradient on the handle's stream (x_dtype: POD_F64 / POD_F32).
 int mlp_forward_launch(pod_handle* h, int n, int n_in, const void* X, long ldx, int x_dtype, const float* theta,
                        const float* mu, const float* isg, float* y, float* dydx);
+namespace net {
+struct Packed;
+}
+// The network weights packed for the per-atom energy kernel (one small
+// kernel on the handle's stream); out: device memory of sizeof(net::Packed).
+int mlp_pack_launch(pod_handle* h, int n_in, const float* theta, const float* mu, const float* isg,
+                    net::Packed* out);
 }  // namespace pod

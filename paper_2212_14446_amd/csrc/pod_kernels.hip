@@ -36,6 +36,7 @@
 
 #include "pod.h"
 #include "pod_device.h"
+#include "pod_net.h"
 #include "pod_internal.h"
 #include "pod_tables.h"
 #include "pod_wide.h"
@@ -74,9 +75,8 @@ struct KArgs {
     double* part;      // block partials, column-major [10 + M][nblk] (mode 1)
     int want_G;        // block partials of G requested
     int want_back;     // adjoint rows requested (forces or virial)
-    const float* y_net;  // mode 2: per-atom network energy (N)
-    const float* g_net;  // mode 2: per-atom dy/dD for descriptor columns 1.. (N x n_net)
-    int n_net;
+    const net::Packed* netw;  // mode 2: network weights (pod_net.h)
+    int n_net;                // mode 2: network inputs, descriptor columns 1 .. n_net
     int* err;
 };
 
@@ -111,7 +111,16 @@ struct AtomLds {
     size_t off_e, off_t, total;
 };
 
-__host__ __device__ inline AtomLds atom_lds_layout(int K, int NA, int M, size_t tsize, int KA, int PA) {
+// With the network (mode 2) the T area holds, while the network runs, the
+// basis rows in the adjoint-row slots and after them one tile: the
+// standardised inputs [16][MAX_IN] (bfloat16), later overwritten by the
+// input gradients [16][MAX_IN] (FP32), and the outputs [16] (FP32).
+constexpr size_t NET_LDS = 16 * net::MAX_IN * 4 + 16 * 4;
+__host__ __device__ constexpr size_t net_tile_offset(int apw, int AST, size_t tsize) {
+    return (static_cast<size_t>(apw) * AST * tsize + 15) / 16 * 16;
+}
+
+__host__ __device__ inline AtomLds atom_lds_layout(int K, int NA, int M, size_t tsize, int KA, int PA, bool netw) {
     const int apw = WAVE / K;
     AtomLds L;
     L.off_e = 0;
@@ -123,6 +132,10 @@ __host__ __device__ inline AtomLds atom_lds_layout(int K, int NA, int M, size_t 
     const size_t gst = static_cast<size_t>(2 + PA + KA) * WAVE * sizeof(double);
     size_t t = stage > adj ? stage : adj;
     t = t > gst ? t : gst;
+    if (netw) {
+        const size_t tn = net_tile_offset(apw, abar_stride(K, NA, static_cast<int>(tsize)), tsize) + NET_LDS;
+        t = t > tn ? t : tn;
+    }
     L.total = L.off_t + t;
     return L;
 }
@@ -197,7 +210,7 @@ __device__ __forceinline__ void atom_body(const KArgs<T>& g) {
     const bool act = (al < apw) && (atom < g.N);
 
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const AtomLds LY = atom_lds_layout(K, NA, M, sizeof(T), KA, PA);
+    const AtomLds LY = atom_lds_layout(K, NA, M, sizeof(T), KA, PA, MODE == 2);
     double* sE = reinterpret_cast<double*>(smem_raw + LY.off_e);
     T* sT = reinterpret_cast<T*>(smem_raw + LY.off_t);
 
@@ -379,16 +392,82 @@ __device__ __forceinline__ void atom_body(const KArgs<T>& g) {
 #pragma unroll
     for (int n = 0; n <= PA; ++n) eff3[n] = w3[n];
     if constexpr (MODE == 2) {
-        // network surrogate (eq. (673a)): energy y_i, adjoint weights c + dy/dD_i
+        // network surrogate (eq. (673a)) on the wavefront's atoms, 16 at a
+        // time (pod_net.h): the 2/3-body descriptors standardised and rounded
+        // as the network kernels do, then the energy y_i and the adjoint
+        // weights c + dy/dD_i.  The basis row waits in its adjoint-row slot
+        // in LDS meanwhile (the adjoint is formed there in place below), so
+        // the network's registers do not add to the row's; the network's
+        // tiles follow the adjoint rows.
+        using namespace net;
         if (act) {
-            const float* gn = g.g_net + static_cast<size_t>(atom) * g.n_net;
-            if (has2) eff2 += static_cast<T>(gn[m]);
-            if (has3) {
+            T* brow = sT + al * AST + m * NA;
 #pragma unroll
-                for (int n = 0; n <= PA; ++n)
-                    if (n <= P3) eff3[n] += static_cast<T>(gn[P->off3 - 1 + m * (P3 + 1) + n]);
+            for (int mu = 0; mu < NA; ++mu) brow[mu] = acc[mu];
+        }
+        const int n_in = g.n_net;
+        unsigned char* nbase = reinterpret_cast<unsigned char*>(sT) + net_tile_offset(apw, AST, sizeof(T));
+        unsigned short* sX = reinterpret_cast<unsigned short*>(nbase);   // [16][MAX_IN] (inputs)
+        float* sD = reinterpret_cast<float*>(nbase);                      // [16][MAX_IN] (gradients; same place)
+        float* sY = sD + 16 * MAX_IN;                                     // [16]
+        const int r = lane & 15, gq = lane >> 4;
+        const int off3 = P->off3;
+#pragma unroll 1
+        for (int tb = 0; tb < apw; tb += 16) {
+            const bool mine = act && al >= tb && al < tb + 16;
+            const int ra = al - tb;
+            // the weights' address depends on tb (by a term that is zero), so
+            // their loads stay inside the loop instead of being hoisted in
+            // front of it and held in registers across it
+            const PackedW nw{reinterpret_cast<const Packed*>(reinterpret_cast<const char*>(g.netw) + (tb >> 30))};
+            // zero the input tile (2 KB: 32 bytes per lane)
+            uint4* z4 = reinterpret_cast<uint4*>(sX);
+            z4[2 * lane] = uint4{0u, 0u, 0u, 0u};
+            z4[2 * lane + 1] = uint4{0u, 0u, 0u, 0u};
+            wave_sync();
+            if (mine) {
+                if (has2)
+                    sX[ra * MAX_IN + m] = to_bf16(static_cast<float>((acc[0] - static_cast<T>(nw.p->mu[m])) *
+                                                                     static_cast<T>(nw.p->isg[m])));
+                if (has3) {
+#pragma unroll
+                    for (int n = 0; n <= PA; ++n)
+                        if (n <= P3) {
+                            const int k = off3 - 1 + m * (P3 + 1) + n;
+                            sX[ra * MAX_IN + k] = to_bf16(static_cast<float>(
+                                (d3[n] - static_cast<T>(nw.p->mu[k])) * static_cast<T>(nw.p->isg[k])));
+                        }
+                }
             }
-            if (q == 0) e += static_cast<double>(g.y_net[atom]);
+            wave_sync();
+            bf4 xb[4];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) xb[s] = *reinterpret_cast<const bf4*>(&sX[r * MAX_IN + 16 * s + 4 * gq]);
+            wave_sync();   // the input tile is read before the gradients overwrite it
+            f4 z1[4], z2[4], dx[4];
+            bf4 h1b[4];
+            layers(nw, xb, r, gq, z1, h1b, z2);
+            const float y = output(nw, z2, gq);
+            input_grad(nw, xb, z2, r, gq, tb >> 30, dx);
+            if (gq == 0) sY[r] = y;
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int k = 16 * s + 4 * gq + i;
+                    if (k < n_in) sD[r * MAX_IN + k] = dx[s][i] * nw.p->isg[k];
+                }
+            wave_sync();
+            if (mine) {
+                if (has2) eff2 += static_cast<T>(sD[ra * MAX_IN + m]);
+                if (has3) {
+#pragma unroll
+                    for (int n = 0; n <= PA; ++n)
+                        if (n <= P3) eff3[n] += static_cast<T>(sD[ra * MAX_IN + off3 - 1 + m * (P3 + 1) + n]);
+                }
+                if (q == 0) e += static_cast<double>(sY[ra]);
+            }
+            wave_sync();
         }
     }
 #pragma unroll
@@ -400,9 +479,18 @@ __device__ __forceinline__ void atom_body(const KArgs<T>& g) {
     // the adjoint row dE_i/dB_{i m .}: in registers up to P_a = 5; beyond,
     // the row and the basis row do not both fit, so the adjoint row is
     // accumulated in its LDS slot (the staging area is free after the rounds)
-    constexpr bool AB_LDS = NA > 60;
+    constexpr bool AB_LDS = NA > 60 || MODE == 2;
     T ab[AB_LDS ? 1 : NA];
-    if constexpr (AB_LDS) {
+    if constexpr (MODE == 2) {
+        // the row waits in its LDS slot; the surrogate's model has no 4-body
+        // descriptors (the entry point requires K4 = 0), so eq. (26c) is all
+        if (act && g.want_back) {
+            T* abrow = sT + al * AST + m * NA;
+#pragma unroll
+            for (int mu = 0; mu < NA; ++mu)
+                abrow[mu] = T(2 * mt.mult[mu]) * eff3[mt.deg[mu]] * abrow[mu] + (mu == 0 ? eff2 : T(0));
+        }
+    } else if constexpr (AB_LDS) {
         if (act) {
             T* abrow = sT + al * AST + m * NA;
 #pragma unroll
@@ -485,6 +573,14 @@ __global__ __launch_bounds__(64) void atom_kernel(KArgs<T> g) {
 
 template <typename T, int PA, int MODE, bool FAST>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void atom_kernel_occ2(KArgs<T> g) {
+    atom_body<T, PA, MODE, FAST>(g);
+}
+
+// The FP32 surrogate instances (mode 2) are held to three wavefronts per
+// SIMD, which their LDS (basis rows parked while the network runs) allows
+// anyway.
+template <typename T, int PA, int MODE, bool FAST>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void atom_kernel_occ3(KArgs<T> g) {
     atom_body<T, PA, MODE, FAST>(g);
 }
 
@@ -926,9 +1022,13 @@ __global__ __launch_bounds__(256) void reverse_kernel(const int* __restrict__ of
 template <typename T, int PA, int MODE>
 hipError_t launch_atom(const KArgs<T>& a, bool fast, int nblk, size_t lds, hipStream_t st) {
     constexpr bool occ2 = sizeof(T) == 8 && PA <= 4;
+    constexpr bool occ3 = sizeof(T) == 4 && MODE == 2;
     if constexpr (occ2) {
         if (fast) hipLaunchKernelGGL((atom_kernel_occ2<T, PA, MODE, true>), dim3(nblk), dim3(WAVE), lds, st, a);
         else hipLaunchKernelGGL((atom_kernel_occ2<T, PA, MODE, false>), dim3(nblk), dim3(WAVE), lds, st, a);
+    } else if constexpr (occ3) {
+        if (fast) hipLaunchKernelGGL((atom_kernel_occ3<T, PA, MODE, true>), dim3(nblk), dim3(WAVE), lds, st, a);
+        else hipLaunchKernelGGL((atom_kernel_occ3<T, PA, MODE, false>), dim3(nblk), dim3(WAVE), lds, st, a);
     } else {
         if (fast) hipLaunchKernelGGL((atom_kernel<T, PA, MODE, true>), dim3(nblk), dim3(WAVE), lds, st, a);
         else hipLaunchKernelGGL((atom_kernel<T, PA, MODE, false>), dim3(nblk), dim3(WAVE), lds, st, a);
@@ -979,8 +1079,8 @@ hipError_t dispatch_pair(int PA, const PArgs<T>& a, bool fast, int nblk, size_t 
     }
 }
 
-size_t lds_bytes(int K, int PA, size_t tsize, int M) {
-    return atom_lds_layout(K, n_mono(PA), M, tsize, n_partitions(PA), PA).total;
+size_t lds_bytes(int K, int PA, size_t tsize, int M, bool netw = false) {
+    return atom_lds_layout(K, n_mono(PA), M, tsize, n_partitions(PA), PA, netw).total;
 }
 
 template <typename T>
@@ -1005,7 +1105,7 @@ int fill_args(pod_handle* h, KArgs<T>& a, int N, int P, const void* pos, const d
     a.offsets = offsets; a.nbr_j = nbr_j; a.shift = shift;
     a.coef = nullptr; a.D = nullptr; a.E_atom = nullptr; a.abar = nullptr; a.centre = nullptr; a.pdv = nullptr; a.part = nullptr;
     a.want_G = 0; a.want_back = 0;
-    a.y_net = nullptr; a.g_net = nullptr; a.n_net = 0;
+    a.netw = nullptr; a.n_net = 0;
     a.err = h->d_err;
     return POD_OK;
 }
@@ -1091,8 +1191,8 @@ EfScratch ef_scratch_layout(int N, int P, int K, int PA, int M, size_t tsize, bo
 template <typename T, int MODE = 1>
 int energy_forces_run(pod_handle* h, char* scratch, double* facc, int N, int P, const void* pos, const double* cell,
                       const int* offsets, const int* nbr_j, const int* shift, const int* rev, const void* c,
-                      void* E_atom, double* E, void* F, double* W, double* G, const float* y_net = nullptr,
-                      const float* g_net = nullptr, int n_net = 0) {
+                      void* E_atom, double* E, void* F, double* W, double* G,
+                      const net::Packed* netw = nullptr, int n_net = 0) {
     KArgs<T> a;
     int rc = fill_args<T>(h, a, N, P, pos, cell, offsets, nbr_j, shift);
     if (rc != POD_OK) return rc;
@@ -1111,7 +1211,7 @@ int energy_forces_run(pod_handle* h, char* scratch, double* facc, int N, int P, 
     a.pdv = reinterpret_cast<T*>(scratch + L.pdv);
     a.want_G = G != nullptr;
     a.want_back = back;
-    a.y_net = y_net; a.g_net = g_net; a.n_net = n_net;
+    a.netw = netw; a.n_net = n_net;
     if (wide_path(h->K, h->PA)) {
         if constexpr (MODE != 1) return POD_ENOTSUP;
         // wide-degree kernel: energy, G and pair gradients in one launch
@@ -1150,7 +1250,7 @@ int energy_forces_run(pod_handle* h, char* scratch, double* facc, int N, int P, 
     if (nblk > 0) {
         timing_begin(h, 1);
         const hipError_t e = dispatch_pa<T, MODE>(h->PA, a, h->std_ok != 0, nblk,
-                                               lds_bytes(h->K, h->PA, sizeof(T), h->M), h->stream);
+                                               lds_bytes(h->K, h->PA, sizeof(T), h->M, MODE == 2), h->stream);
         timing_end(h, 1);
         if (e != hipSuccess) return POD_EHIP;
     }
@@ -1197,7 +1297,7 @@ int energy_forces_run(pod_handle* h, char* scratch, double* facc, int N, int P, 
 template <typename T, int MODE = 1>
 int energy_forces_impl(pod_handle* h, int N, int P, const void* pos, const double* cell, const int* offsets,
                        const int* nbr_j, const int* shift, const int* rev, const void* c, void* E_atom, double* E,
-                       void* F, double* W, double* G, const float* y_net = nullptr, const float* g_net = nullptr,
+                       void* F, double* W, double* G, const net::Packed* netw = nullptr,
                        int n_net = 0) {
     const bool back = (F != nullptr) || (W != nullptr);
     const bool gather = rev != nullptr && F != nullptr;
@@ -1207,38 +1307,30 @@ int energy_forces_impl(pod_handle* h, int N, int P, const void* pos, const doubl
     rc = ensure_force_acc(h, N);
     if (rc != POD_OK) return rc;
     rc = energy_forces_run<T, MODE>(h, static_cast<char*>(h->d_scratch), h->d_facc, N, P, pos, cell, offsets, nbr_j,
-                                    shift, rev, c, E_atom, E, F, W, G, y_net, g_net, n_net);
+                                    shift, rev, c, E_atom, E, F, W, G, netw, n_net);
     if (rc == POD_EHIP && back && !gather) h->facc_dirty = 1;
     return rc;
 }
 
-// Network surrogate of the 4-body term: descriptors, network forward and
-// input gradient, then energy and adjoint with per-atom weights (mode 2).
+// Network surrogate of the 4-body term: the weights packed once (one small
+// kernel), then the per-atom kernel in mode 2 runs the network on its own
+// 2/3-body descriptors and takes the energy and the adjoint weights
+// c + dy/dD_i from it; pair and finalize kernels as for the linear model.
 template <typename T>
 int surrogate_impl(pod_handle* h, int N, int P, const void* pos, const double* cell, const int* offsets,
                    const int* nbr_j, const int* shift, const int* rev, const void* c, const float* theta,
                    const float* mu, const float* isg, void* E_atom, double* E, void* F, double* W) {
     const int n_in = h->M - 1;
-    const size_t align = 256;
-    const size_t d_bytes = (static_cast<size_t>(N) * h->M * sizeof(T) + align - 1) / align * align;
-    const size_t y_bytes = (static_cast<size_t>(N) * sizeof(float) + align - 1) / align * align;
-    const size_t g_bytes = static_cast<size_t>(N) * n_in * sizeof(float);
-    float* y = nullptr;
-    float* gr = nullptr;
+    net::Packed* pk = nullptr;
     if (N > 0) {
-        int rc = ensure_mscratch(h, d_bytes + y_bytes + g_bytes);
+        const int rc = ensure_mscratch(h, sizeof(net::Packed));
         if (rc != POD_OK) return rc;
-        char* base = static_cast<char*>(h->d_mscratch);
-        T* D = reinterpret_cast<T*>(base);
-        y = reinterpret_cast<float*>(base + d_bytes);
-        gr = reinterpret_cast<float*>(base + d_bytes + y_bytes);
-        rc = descriptors_impl<T>(h, N, P, pos, cell, offsets, nbr_j, shift, D);
-        if (rc != POD_OK) return rc;
-        rc = mlp_forward_launch(h, N, n_in, D + 1, h->M, h->dtype, theta, mu, isg, y, gr);
-        if (rc != POD_OK) return rc;
+        pk = static_cast<net::Packed*>(h->d_mscratch);
+        const int rc2 = mlp_pack_launch(h, n_in, theta, mu, isg, pk);
+        if (rc2 != POD_OK) return rc2;
     }
     return energy_forces_impl<T, 2>(h, N, P, pos, cell, offsets, nbr_j, shift, rev, c, E_atom, E, F, W, nullptr,
-                                    y, gr, n_in);
+                                    pk, n_in);
 }
 
 __global__ __launch_bounds__(256) void zero_kernel(double* p, long n) {

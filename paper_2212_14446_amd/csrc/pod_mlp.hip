@@ -5,62 +5,37 @@
 // Layout of the parameter vector theta (FP32): W1 [64][n_in], b1 [64],
 // W2 [64][64], b2 [64], w3 [64], b3, row-major and concatenated.
 //
-// All matrix products use v_mfma_f32_16x16x16_bf16 on tiles of 16 atoms.
-// Activations are kept transposed (feature x atom): the product
-// Z^T = W X^T leaves lane l holding atom l % 16 and features 4 (l / 16) + i,
-// which is exactly the B-operand layout of the next product, so the layers
-// chain in registers.  Rounding to bfloat16 (nearest even) happens where a
-// value enters a product: standardised inputs, W1, W2, the first hidden
-// activation, and the back-propagated pre-activation gradients.
+// All matrix products use v_mfma_f32_16x16x16_bf16 on tiles of 16 atoms;
+// the arithmetic of a tile (forward, output, input gradient) is shared with
+// the per-atom energy kernel through pod_net.h.  Here the weights sit in
+// LDS; training adds the weight gradients of every tile.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
 
 #include "pod.h"
 #include "pod_internal.h"
+#include "pod_net.h"
 
 namespace pod {
 namespace {
+
+using net::bf4;
+using net::f4;
+using net::from_bf16;
+using net::Layout;
+using net::layout;
+using net::mfma;
+using net::silu;
+using net::silu_d;
+using net::to_bf16;
 
 constexpr int H = POD_MLP_HIDDEN;     // 64
 constexpr int MAX_IN = POD_MLP_MAX_IN;  // 64
 constexpr int WS = H + 4;             // padded LDS row stride of the weight tiles (bf16 elements)
 constexpr int TS = 20;                // padded row stride of the per-wave transpose tiles
 
-typedef short bf4 __attribute__((ext_vector_type(4)));
-typedef float f4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ unsigned short to_bf16(float f) {
-    unsigned u = __float_as_uint(f);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return static_cast<unsigned short>(u >> 16);
-}
-__device__ __forceinline__ float from_bf16(unsigned short b) { return __uint_as_float(static_cast<unsigned>(b) << 16); }
-
-__device__ __forceinline__ float sigm(float z) { return 1.0f / (1.0f + expf(-z)); }
-__device__ __forceinline__ float silu(float z) { return z * sigm(z); }
-__device__ __forceinline__ float silu_d(float z) {
-    const float s = sigm(z);
-    return s * (1.0f + z * (1.0f - s));
-}
-
-__device__ __forceinline__ f4 mfma(bf4 a, bf4 b, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0); }
-
 __device__ __forceinline__ bf4 lds4(const unsigned short* p) { return *reinterpret_cast<const bf4*>(p); }
-
-struct Layout {
-    int o_b1, o_W2, o_b2, o_w3, o_b3, n;
-};
-__host__ __device__ inline Layout layout(int n_in) {
-    Layout L;
-    L.o_b1 = H * n_in;
-    L.o_W2 = L.o_b1 + H;
-    L.o_b2 = L.o_W2 + H * H;
-    L.o_w3 = L.o_b2 + H;
-    L.o_b3 = L.o_w3 + H;
-    L.n = L.o_b3 + 1;
-    return L;
-}
 
 // Weights as the products read them, in LDS.
 struct alignas(16) Weights {
@@ -100,6 +75,19 @@ __device__ void load_weights(Weights& L, const float* __restrict__ theta, const 
     if (tid == 0) L.b3 = theta[o.o_b3];
 }
 
+// Accessor of the LDS weights for the shared tile arithmetic (pod_net.h).
+struct LdsW {
+    const Weights& L;
+    __device__ __forceinline__ bf4 w1(int h, int k) const { return lds4(&L.W1[h * WS + k]); }
+    __device__ __forceinline__ bf4 w1t(int k, int h) const { return lds4(&L.W1T[k * WS + h]); }
+    __device__ __forceinline__ bf4 w2(int a, int b) const { return lds4(&L.W2[a * WS + b]); }
+    __device__ __forceinline__ bf4 w2t(int a, int b) const { return lds4(&L.W2T[a * WS + b]); }
+    __device__ __forceinline__ float b1(int i) const { return L.b1[i]; }
+    __device__ __forceinline__ float b2(int i) const { return L.b2[i]; }
+    __device__ __forceinline__ float w3(int i) const { return L.w3[i]; }
+    __device__ __forceinline__ float b3() const { return L.b3; }
+};
+
 // Forward pass of one tile of 16 atoms.  Lane l: atom r = l % 16 of the tile,
 // feature group g = l / 16.  xb[s]: standardised inputs 16 s + 4 g + i;
 // z1[t], z2[u]: pre-activations of hidden units 16 t + 4 g + i.
@@ -120,38 +108,12 @@ __device__ __forceinline__ void forward_tile(const Weights& L, const TX* __restr
             xb[s][i] = static_cast<short>(to_bf16(v));
         }
     }
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-        for (int s = 0; s < 4; ++s)
-            if (s < ns) acc = mfma(lds4(&L.W1[(16 * t + r) * WS + 16 * s + 4 * g]), xb[s], acc);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            z1[t][i] = acc[i] + L.b1[16 * t + 4 * g + i];
-            h1b[t][i] = static_cast<short>(to_bf16(silu(z1[t][i])));
-        }
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-        for (int t = 0; t < 4; ++t) acc = mfma(lds4(&L.W2[(16 * u + r) * WS + 16 * t + 4 * g]), h1b[t], acc);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) z2[u][i] = acc[i] + L.b2[16 * u + 4 * g + i];
-    }
+    net::layers(LdsW{L}, xb, r, g, z1, h1b, z2);
 }
 
 // y of the tile's atoms: every lane of column r ends with the same value.
 __device__ __forceinline__ float output_tile(const Weights& L, const f4 (&z2)[4], int g) {
-    float p = 0.0f;
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) p += L.w3[16 * u + 4 * g + i] * silu(z2[u][i]);
-    p += __shfl_xor(p, 16);
-    p += __shfl_xor(p, 32);
-    return p + L.b3;
+    return net::output(LdsW{L}, z2, g);
 }
 
 template <typename TX>
@@ -186,35 +148,17 @@ __global__ __launch_bounds__(256) void infer_kernel(InferArgs<TX> a) {
         const float y = output_tile(L, z2, g);
         if (ok && g == 0 && a.y) a.y[atom] = y;
         if (!a.dydx) continue;
-        // back-propagation to the inputs (eq. (673a)): dz2 = w3 * silu'(z2)
-        bf4 dz2b[4];
+        // back-propagation to the inputs (eq. (673a))
+        f4 dx[4];
+        net::input_grad(LdsW{L}, xb, z2, r, g, 0, dx);
+        if (ok) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-                dz2b[u][i] = static_cast<short>(to_bf16(L.w3[16 * u + 4 * g + i] * silu_d(z2[u][i])));
-        bf4 dz1b[4];
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-            for (int u = 0; u < 4; ++u) acc = mfma(lds4(&L.W2T[(16 * t + r) * WS + 16 * u + 4 * g]), dz2b[u], acc);
-#pragma unroll
-            for (int i = 0; i < 4; ++i) dz1b[t][i] = static_cast<short>(to_bf16(acc[i] * silu_d(z1[t][i])));
-        }
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            if (s >= ns) break;
-            f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-            for (int t = 0; t < 4; ++t) acc = mfma(lds4(&L.W1T[(16 * s + r) * WS + 16 * t + 4 * g]), dz1b[t], acc);
-            if (ok) {
+            for (int s = 0; s < 4; ++s)
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const int k = 16 * s + 4 * g + i;
-                    if (k < a.n_in) a.dydx[static_cast<long>(atom) * a.n_in + k] = acc[i] * L.isg[k];
+                    if (s < ns && k < a.n_in) a.dydx[static_cast<long>(atom) * a.n_in + k] = dx[s][i] * L.isg[k];
                 }
-            }
         }
     }
 }
@@ -423,7 +367,60 @@ int grid_for(int tiles, int per_block, int cap) {
     return b < 1 ? 1 : (b > cap ? cap : b);
 }
 
+// The weights packed for the per-atom kernel (net::Packed): one element of
+// W1 / W2 (and its transposed copy) per thread, the vectors by the first
+// workgroup.
+constexpr int PACK_THREADS = 256;
+constexpr int PACK_BLOCKS = (H * MAX_IN + H * H) / PACK_THREADS;
+
+__global__ __launch_bounds__(PACK_THREADS) void pack_kernel(const float* __restrict__ theta,
+                                                            const float* __restrict__ mu,
+                                                            const float* __restrict__ isg, int n_in,
+                                                            net::Packed* out) {
+    const Layout o = layout(n_in);
+    const int i = blockIdx.x * PACK_THREADS + threadIdx.x;
+    if (i < H * MAX_IN) {
+        const int h = i / MAX_IN, k = i - h * MAX_IN;
+        const unsigned short b = to_bf16(k < n_in ? theta[h * n_in + k] : 0.0f);
+        out->W1[h * MAX_IN + k] = b;
+        out->W1T[k * H + h] = b;
+    } else if (i < H * MAX_IN + H * H) {
+        const int j = i - H * MAX_IN;
+        const int h2 = j / H, h1 = j - h2 * H;
+        const unsigned short b = to_bf16(theta[o.o_W2 + j]);
+        out->W2[h2 * H + h1] = b;
+        out->W2T[h1 * H + h2] = b;
+    }
+    if (blockIdx.x == 0) {
+        const int t = threadIdx.x;
+        if (t < H) {
+            out->b1[t] = theta[o.o_b1 + t];
+            out->b2[t] = theta[o.o_b2 + t];
+            out->w3[t] = theta[o.o_w3 + t];
+        }
+        if (t < MAX_IN) {
+            out->mu[t] = t < n_in ? mu[t] : 0.0f;
+            out->isg[t] = t < n_in ? isg[t] : 0.0f;
+        }
+        if (t == 0) {
+            out->b3 = theta[o.o_b3];
+            out->pad[0] = out->pad[1] = out->pad[2] = 0.0f;
+        }
+    }
+}
+
+static_assert((H * MAX_IN + H * H) % PACK_THREADS == 0, "pack grid");
+static_assert(H <= PACK_THREADS && MAX_IN <= PACK_THREADS, "pack vectors");
+
 }  // namespace
+
+int mlp_pack_launch(pod_handle* h, int n_in, const float* theta, const float* mu, const float* isg,
+                    net::Packed* out) {
+    timing_begin(h, 2);
+    hipLaunchKernelGGL(pack_kernel, dim3(PACK_BLOCKS), dim3(PACK_THREADS), 0, h->stream, theta, mu, isg, n_in, out);
+    timing_end(h, 2);
+    return hipGetLastError() == hipSuccess ? POD_OK : POD_EHIP;
+}
 
 int mlp_forward_launch(pod_handle* h, int n, int n_in, const void* X, long ldx, int x_dtype, const float* theta,
                        const float* mu, const float* isg, float* y, float* dydx) {

@@ -287,6 +287,48 @@ def test_surrogate_energy_forces_vs_oracle(sur_case, dtype, gather):
     assert abs(got["E"][0] - ref["E"]) < WORST * np.abs(ref["E_atom"]).max()
 
 
+@pytest.mark.parametrize("K", [3, 1])
+def test_surrogate_several_network_tiles_per_wave(K):
+    """With K = 3 (21 atoms per wavefront) and K = 1 (64) the per-atom kernel
+    runs the network on two and four tiles of 16 atoms in turn.  The
+    network's outputs must equal those of the network kernel on the
+    device's own descriptors (same products, same rounding: the energies to
+    FP64 rounding of the linear part), and the forces those of the oracle's
+    adjoint with these per-atom weights to 1e-10."""
+    import torch
+    S = wl.PodSetup(rin=0.5, rcut=5.0, L=8, K2=K, K3=K, K4=0, P3=4, P4=0)
+    w = wl.small_bcc(3, sigma=0.15, seed=31 + K, setup=S)
+    op = oracle_params(S)
+    Q, _ = po.pod_basis(op)
+    args = (w.pos, w.cell, w.nl.offsets.astype(np.int64), w.nl.nbr_j, w.nl.shift3, op, Q)
+    D = po.descriptors_fast(*args)
+    rng = np.random.default_rng(32 + K)
+    c = rng.normal(size=D.shape[1]) / (D.std(0) + 1e-3) * 0.1
+    n_in = D.shape[1] - 1
+    theta, _, _, _ = rand_case(1, n_in, 33 + K)
+    f32 = lambda a: np.asarray(a, dtype=np.float32).astype(np.float64)
+    mu = f32(D[:, 1:].mean(0))
+    isg = f32(1.0 / (D[:, 1:].std(0) + 1e-6))
+    m = pod.PodModel(pod.setup_from_workload(S), "f64", Q=Q[:, :K])
+    net = surrogate.Network(n_in, seed=0)
+    f = lambda a: torch.tensor(a, dtype=torch.float32, device="cuda")
+    net.theta, net.mu, net.inv_sigma = f(theta), f(mu), f(isg)
+    nb = pod.DeviceNeighbors.from_list(w.nl)
+    nb.build_reverse(m)
+    say(f"[gpu] surrogate K={K}: {64 // K} atoms per wavefront, N={w.N}, n_in={n_in}")
+    o = m.energy_forces_surrogate(w.pos, w.cell, nb, c, net)
+    Dd = m.descriptors(w.pos, w.cell, nb)
+    y_dev, g_dev = net.forward(m.h, Dd, x_col=1, ldx=m.M)
+    torch.cuda.synchronize()
+    got = {k: v.double().cpu().numpy() for k, v in o.items()}
+    Dd = Dd.double().cpu().numpy()
+    y_dev, g_dev = y_dev.double().cpu().numpy(), g_dev.double().cpu().numpy()
+    assert relerr(got["E_atom"], Dd @ c + y_dev) < 1e-12
+    C = c[None, :] + np.concatenate([np.zeros((w.N, 1)), g_dev], axis=1)
+    F_C, W_C = mo.forces_from_atom_weights(w.pos, *args[1:], C)
+    assert relerr(got["F"], F_C) < 1e-10 and relerr(got["W"], W_C) < 1e-10
+
+
 def test_surrogate_silent_network_equals_linear_path(sur_case):
     """w3 = 0, b3 = 0: the surrogate path must reproduce pod_energy_forces
     with the 2/3-body coefficients to FP64 rounding (the network adds exact
