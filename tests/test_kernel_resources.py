@@ -1,6 +1,7 @@
 """Register and scratch use of the energy path's benchmark kernel instances
-(FP64 and FP32, K = 6, angular degree 4, standard snapshot family) and of the
-wide-degree kernels, read from the compiler's resource-usage remarks of a
+(FP64 and FP32, K = 6, angular degree 4, standard snapshot family), of the
+surrogate's per-atom kernel with the network inside, and of the wide-degree
+kernels, read from the compiler's resource-usage remarks of a
 device-only gfx950 compile of csrc/pod_kernels.hip and csrc/pod_wide.hip with
 the library's flags.  The test fails when an
 instance spills (scratch above the recorded bound) or loses occupancy, so a
@@ -19,6 +20,9 @@ RECORDED = {
     "void pair_kernel<float, 4, 6, true>(PArgs<float>)": (0, 7, 72),
     "void finalize_kernel<double>(FinArgs<double>)": (0, 8, 28),
     "void finalize_kernel<float>(FinArgs<float>)": (0, 8, 28),
+    # the surrogate's per-atom kernel with the network inside (FP32 benchmark model)
+    "void atom_kernel_occ3<float, 4, 2, true>(KArgs<float>)": (0, 3, 155),
+    "void atom_kernel_occ2<double, 4, 2, true>(KArgs<double>)": (0, 2, 224),
 }
 
 
