@@ -1,12 +1,13 @@
 """Differentiable POD energy (torch.autograd.Function over the adjoint kernel):
-gradcheck in FP64, the 54,000-atom FP32 box against central differences of
-the FP64 GPU energy on 250 random atoms, dE/dc = G and the virial against a
-strain difference."""
+gradcheck in FP64, the 54,000-atom box against the compiled FP64 oracle on
+every atom and its FP32 forces against central differences of the FP64 GPU
+energy on 250 random atoms, dE/dc = G and the virial against a strain
+difference."""
 import numpy as np
 import pytest
 import torch
 
-from gpu_common import Case, relerr, say
+from gpu_common import Case, oracle_params, relerr, say
 from oracle import pod_oracle as po
 from paper_2212_14446_amd import pod, workloads as wl
 from paper_2212_14446_amd.autograd import pod_energy
@@ -104,6 +105,49 @@ def test_cfg4_fp32_forces_vs_fp64_central_differences(box54k):
     efd32 = np.abs(fd - F32[atoms]).max() / np.abs(F64[atoms]).max()
     say(f"[gpu]   central differences (250 atoms): FP64 forces {efd64:.2e}, FP32 forces {efd32:.2e}")
     assert efd64 < 1e-6 and efd32 < 1e-4
+
+
+def test_cfg4_full_box_vs_compiled_oracle(box54k):
+    """The 54,000-atom box against the compiled FP64 oracle (oracle.cpp, pinned
+    to the NumPy oracle at 1e-12), every atom: the differentiable energy's
+    FP64 forces, dE/dc and virial at 1e-10, its FP32 forces at 1e-4 and
+    energy at 2e-5 (both sides on the FP32-rounded inputs).  The models take
+    the oracle's basis Q, so the comparison does not depend on the sign
+    convention of the eigenvectors."""
+    from oracle import oracle_c
+    w = box54k
+    s = w.setup
+    op = oracle_params(s)
+    Q, _ = po.pod_basis(op)
+    K = op.K
+    m64 = pod.PodModel(pod.setup_from_workload(s), "f64", Q=Q[:, :K])
+    nb = pod.DeviceNeighbors.from_list(w.nl)
+    nb.build_reverse(m64)
+    D = m64.descriptors(w.pos, w.cell, nb).cpu().numpy()
+    c = wl.standardised_coefficients(D, s, seed=9)
+    args = (w.nl.offsets.astype(np.int64), w.nl.nbr_j, w.nl.shift3, op, Q)
+    say(f"[gpu] cfg4 against the compiled oracle, N={w.N}, {oracle_c.host_threads()} host threads")
+    ref = oracle_c.energy_forces(w.pos, w.cell, *args, c, threads=oracle_c.host_threads())
+    x = torch.tensor(w.pos, dtype=torch.float64, device="cuda", requires_grad=True)
+    cc = torch.tensor(c, dtype=torch.float64, device="cuda", requires_grad=True)
+    E, W = pod_energy(x, cc, m64, nb, w.cell)
+    E.backward()
+    assert abs(E.item() - ref["E"]) < 1e-10 * abs(ref["E"])
+    assert relerr(-x.grad.cpu().numpy(), ref["F"]) < 1e-10
+    assert relerr(cc.grad.cpu().numpy(), ref["G"]) < 1e-10
+    assert relerr(W.cpu().numpy(), ref["W"]) < 1e-10
+    # FP32 on the FP32-rounded inputs, against the oracle on the same inputs
+    m32 = pod.PodModel(pod.setup_from_workload(s), "f32", Q=Q[:, :K])
+    x32 = torch.tensor(w.pos, dtype=torch.float32, device="cuda", requires_grad=True)
+    c32 = torch.tensor(c, dtype=torch.float32, device="cuda")
+    E32, _ = pod_energy(x32, c32, m32, nb, w.cell)
+    E32.backward()
+    ref32 = oracle_c.energy_forces(x32.detach().double().cpu().numpy(), w.cell, *args, c32.double().cpu().numpy(),
+                                   threads=oracle_c.host_threads())
+    eE = abs(E32.item() - ref32["E"]) / abs(ref32["E"])
+    eF = relerr(-x32.grad.double().cpu().numpy(), ref32["F"])
+    say(f"[gpu]   FP32 against the oracle: E {eE:.2e}, F {eF:.2e}")
+    assert eE < 2e-5 and eF < 1e-4
 
 
 def test_dE_dc_is_G_and_virial_is_strain_derivative():
