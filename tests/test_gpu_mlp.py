@@ -287,16 +287,18 @@ def test_surrogate_energy_forces_vs_oracle(sur_case, dtype, gather):
     assert abs(got["E"][0] - ref["E"]) < WORST * np.abs(ref["E_atom"]).max()
 
 
-@pytest.mark.parametrize("K", [3, 1])
-def test_surrogate_several_network_tiles_per_wave(K):
+@pytest.mark.parametrize("K,P3", [(3, 4), (1, 4), (8, 6)])
+def test_surrogate_several_network_tiles_per_wave(K, P3):
     """With K = 3 (21 atoms per wavefront) and K = 1 (64) the per-atom kernel
-    runs the network on two and four tiles of 16 atoms in turn.  The
+    runs the network on two and four tiles of 16 atoms in turn; K = 8 at
+    P3 = 6 gives the largest input, 64 descriptors (all four input groups
+    filled).  The
     network's outputs must equal those of the network kernel on the
     device's own descriptors (same products, same rounding: the energies to
     FP64 rounding of the linear part), and the forces those of the oracle's
     adjoint with these per-atom weights to 1e-10."""
     import torch
-    S = wl.PodSetup(rin=0.5, rcut=5.0, L=8, K2=K, K3=K, K4=0, P3=4, P4=0)
+    S = wl.PodSetup(rin=0.5, rcut=5.0, L=8, K2=K, K3=K, K4=0, P3=P3, P4=0)
     w = wl.small_bcc(3, sigma=0.15, seed=31 + K, setup=S)
     op = oracle_params(S)
     Q, _ = po.pod_basis(op)
@@ -327,6 +329,10 @@ def test_surrogate_several_network_tiles_per_wave(K):
     C = c[None, :] + np.concatenate([np.zeros((w.N, 1)), g_dev], axis=1)
     F_C, W_C = mo.forces_from_atom_weights(w.pos, *args[1:], C)
     assert relerr(got["F"], F_C) < 1e-10 and relerr(got["W"], W_C) < 1e-10
+    # energy only (no adjoint rows, no pair kernel): the same energies
+    e = m.energy_forces_surrogate(w.pos, w.cell, nb, c, net, forces=False, virial=False)
+    torch.cuda.synchronize()
+    assert np.array_equal(e["E_atom"].cpu().numpy(), got["E_atom"]) and e["E"].item() == got["E"][0]
 
 
 def test_surrogate_silent_network_equals_linear_path(sur_case):
