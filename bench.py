@@ -384,10 +384,9 @@ def run_neighbors(reps, warmup=2):
     return out
 
 
-# Table 6: (K2, K3, P3) of the OPOD/FPOD3 models and (K4, P4) of FPOD4, rows
-# with M = 6, 15, 31, 56 (the kernels' radial/angular limits exclude 92, 141)
-# (L, K2, K3, P3, K4, P4) of the six rows of Table 6; rows 5 and 6 need
-# K up to 12, so their snapshot family has L = 14 (12 Bessel + 2 inverse powers)
+# (L, K2, K3, P3, K4, P4) of the six rows of Table 6 (M3 = 6, 15, 31, 56, 92,
+# 141); rows 5 and 6 need K up to 12, so their snapshot family has L = 14
+# (12 Bessel + 2 inverse powers)
 TABLE6 = [(8, 2, 1, 2, 1, 1), (8, 5, 3, 2, 3, 2), (8, 5, 5, 4, 5, 3), (8, 6, 7, 6, 7, 4),
           (14, 10, 9, 8, 9, 5), (14, 8, 12, 10, 12, 6)]
 

@@ -93,17 +93,24 @@ __global__ __launch_bounds__(NB_THREADS) void order_kernel(int N, const int* __r
 
 // FILL = false: number of neighbours of every atom into cnt[i];
 // FILL = true: the neighbours themselves from offsets[i] on (same order).
+// The rows of a workgroup's atoms are one contiguous range of the list:
+// when it fits the workgroup's LDS (FILL_CAP entries) the rows are built
+// there and copied out with consecutive threads on consecutive entries
+// (each thread's own row would otherwise be written with one scattered
+// 4-byte store per entry and lane).
+constexpr int FILL_CAP = 4096;
+constexpr int FILL_THREADS = 128;   // workgroup of the fill pass
+
+// The search of one atom; with `stage`, its row goes to stage[out ..] and
+// stage[FILL_CAP + out ..] (LDS) instead of nbr_j / shift.
 template <bool FILL>
-__global__ __launch_bounds__(NB_THREADS) void search_kernel(int N, NbGeom g, const int* __restrict__ key,
-                                                            const int* __restrict__ sidx,
-                                                            const int* __restrict__ start, const int* __restrict__ end,
-                                                            const double* __restrict__ wpos,
-                                                            const double* __restrict__ spos,
-                                                            const int* __restrict__ wrap, long* __restrict__ cnt,
-                                                            const int* __restrict__ offsets, int* __restrict__ nbr_j,
-                                                            int* __restrict__ shift, int* err) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
+__device__ __forceinline__ void search_atom(int i, const NbGeom& g, const int* __restrict__ key,
+                                            const int* __restrict__ sidx, const int* __restrict__ start,
+                                            const int* __restrict__ end, const double* __restrict__ wpos,
+                                            const double* __restrict__ spos, const int* __restrict__ wrap,
+                                            long* __restrict__ cnt, const int* __restrict__ offsets,
+                                            int* __restrict__ nbr_j, int* __restrict__ shift, int* err,
+                                            int* stage) {
     const int b = key[i];
     const int ci[3] = {b % g.nb[0], (b / g.nb[0]) % g.nb[1], b / (g.nb[0] * g.nb[1])};
     const double ri[3] = {wpos[3 * i], wpos[3 * i + 1], wpos[3 * i + 2]};
@@ -156,14 +163,53 @@ __global__ __launch_bounds__(NB_THREADS) void search_kernel(int N, NbGeom g, con
                         const int n2 = S[2] - wrap[3 * j + 2] + wrap[3 * i + 2];
                         if (n0 < -127 || n0 > 127 || n1 < -127 || n1 > 127 || n2 < -127 || n2 > 127)
                             atomicOr(err, ERR_NEIGH);   // beyond the signed-byte shift
-                        nbr_j[out + n] = j;
-                        shift[out + n] = (n0 & 0xFF) | ((n1 & 0xFF) << 8) | ((n2 & 0xFF) << 16);
+                        const int sh = (n0 & 0xFF) | ((n1 & 0xFF) << 8) | ((n2 & 0xFF) << 16);
+                        if (stage) {
+                            stage[out + n] = j;
+                            stage[FILL_CAP + out + n] = sh;
+                        } else {
+                            nbr_j[out + n] = j;
+                            shift[out + n] = sh;
+                        }
                     }
                     ++n;
                 }
             }
     if (!FILL) cnt[i] = n;
 }
+
+template <bool FILL>
+__global__ __launch_bounds__(NB_THREADS) void search_kernel(int N, NbGeom g, const int* __restrict__ key,
+                                                            const int* __restrict__ sidx,
+                                                            const int* __restrict__ start, const int* __restrict__ end,
+                                                            const double* __restrict__ wpos,
+                                                            const double* __restrict__ spos,
+                                                            const int* __restrict__ wrap, long* __restrict__ cnt,
+                                                            const int* __restrict__ offsets, int* __restrict__ nbr_j,
+                                                            int* __restrict__ shift, int* err) {
+    extern __shared__ int sfill[];   // FILL: [FILL_CAP] neighbour indices, [FILL_CAP] shifts
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int base = 0, total = 0;
+    bool staged = false;
+    if (FILL) {
+        const int i0 = min(static_cast<int>(blockIdx.x * blockDim.x), N);
+        const int i1 = min(i0 + static_cast<int>(blockDim.x), N);
+        base = offsets[i0];
+        total = offsets[i1] - base;
+        staged = total >= 0 && total <= FILL_CAP;
+    }
+    if (i < N) search_atom<FILL>(i, g, key, sidx, start, end, wpos, spos, wrap, cnt, offsets, nbr_j, shift, err,
+                                 staged ? sfill - base : nullptr);
+    if (FILL && staged) {
+        __syncthreads();
+        for (int t = threadIdx.x; t < total; t += blockDim.x) {
+            nbr_j[base + t] = sfill[t];
+            shift[base + t] = sfill[FILL_CAP + t];
+        }
+    }
+}
+
+
 
 // int32 offsets from the 64-bit prefix sum; total[0] = number of pairs.
 __global__ __launch_bounds__(NB_THREADS) void offsets_kernel(int N, const long* __restrict__ off64,
@@ -282,8 +328,9 @@ int pod_build_neighbors(pod_handle* h, int N, const void* pos, const double* cel
     *n_pairs = P;
     if (P > 0x7fffffffL) return POD_ENOTSUP;   // int32 offsets
     if (P > 0 && capacity >= P) {
-        hipLaunchKernelGGL((search_kernel<true>), gb, tb, 0, h->stream, N, g, key, idx_s, start, end, wpos, spos, wrap,
-                           nullptr, offsets, nbr_j, shift, h->d_err);
+        const dim3 gf(static_cast<unsigned>((static_cast<long>(N) + FILL_THREADS - 1) / FILL_THREADS));
+        hipLaunchKernelGGL((search_kernel<true>), gf, dim3(FILL_THREADS), 2 * FILL_CAP * sizeof(int), h->stream, N, g,
+                           key, idx_s, start, end, wpos, spos, wrap, nullptr, offsets, nbr_j, shift, h->d_err);
         if (hipStreamSynchronize(h->stream) != hipSuccess) return POD_EHIP;
     }
     return hipGetLastError() == hipSuccess ? POD_OK : POD_EHIP;

@@ -203,6 +203,8 @@ def test_argument_and_data_errors():
 
 
 def test_config2_box_vs_host_builder():
+    # rcut 5 (~25 pairs per atom): each fill workgroup's rows fit its LDS
+    # stage; rcut 6 (~56): they do not, and the rows are written directly
     for rcut in (5.0, 6.0):
         w = wl.config2(rcut)
         say(f"[gpu] neighbors: {w.name} N={w.N}")
