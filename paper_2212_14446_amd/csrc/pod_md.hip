@@ -65,19 +65,47 @@ __global__ __launch_bounds__(MD_THREADS) void kick_drift_kernel(int N, T* __rest
     }
 }
 
-// v += dt/2 a F; per-block partial sums of m v^2 / 2 (eV)
-template <typename T>
-__global__ __launch_bounds__(MD_THREADS) void kick_kernel(long n3, T* __restrict__ v, const T* __restrict__ F,
-                                                          double hka, double half_m_over_acc,
-                                                          double* __restrict__ part) {
+// One atom per thread: the second half-kick of a step with its forces (the
+// block's partial sum of m v^2 / 2 in ke_part) and, with DRIFT, the first
+// half-kick and drift of the next step with the same forces (the running
+// displacement maximum as in kick_drift_kernel).  Per component the
+// arithmetic is a half kick rounded to the stored type followed by
+// kick_drift_kernel's, as with two launches; one launch per step is saved.
+template <typename T, bool DRIFT>
+__global__ __launch_bounds__(MD_THREADS) void kick_atoms_kernel(int N, T* __restrict__ x, T* __restrict__ v,
+                                                                const T* __restrict__ F, const T* __restrict__ xr,
+                                                                double hka, double dt, double half_m_over_acc,
+                                                                double* __restrict__ ke_part,
+                                                                double* __restrict__ disp_part) {
     __shared__ double red[MD_THREADS];
-    double ke = 0.0;
-    for (long k = static_cast<long>(blockIdx.x) * MD_THREADS + threadIdx.x; k < n3;
-         k += static_cast<long>(gridDim.x) * MD_THREADS) {
-        const double vn = static_cast<double>(v[k]) + hka * static_cast<double>(F[k]);
-        v[k] = static_cast<T>(vn);
-        const double vs = static_cast<double>(static_cast<T>(vn));
-        ke += vs * vs;
+    double ke = 0.0, mx = 0.0;
+    for (long i = static_cast<long>(blockIdx.x) * MD_THREADS + threadIdx.x; i < N;
+         i += static_cast<long>(gridDim.x) * MD_THREADS) {
+        double d2 = 0.0;
+#pragma unroll
+        for (int e = 0; e < 3; ++e) {
+            const long k = 3 * i + e;
+            const double f = static_cast<double>(F[k]);
+            const double vn = static_cast<double>(v[k]) + hka * f;
+            const double vs = static_cast<double>(static_cast<T>(vn));
+            ke += vs * vs;
+            if constexpr (DRIFT) {
+                const double vh = vs + hka * f;
+                v[k] = static_cast<T>(vh);
+                const T xn = static_cast<T>(static_cast<double>(x[k]) + dt * vh);
+                x[k] = xn;
+                if (xr) {
+                    const double dd = static_cast<double>(xn) - static_cast<double>(xr[k]);
+                    d2 += dd * dd;
+                }
+            } else {
+                v[k] = static_cast<T>(vn);
+            }
+        }
+        if constexpr (DRIFT) {
+            const double d = sqrt(d2);
+            mx = (d > mx || d != d) ? d : mx;
+        }
     }
     red[threadIdx.x] = ke * half_m_over_acc;
     __syncthreads();
@@ -85,7 +113,22 @@ __global__ __launch_bounds__(MD_THREADS) void kick_kernel(long n3, T* __restrict
         if (static_cast<int>(threadIdx.x) < o) red[threadIdx.x] += red[threadIdx.x + o];
         __syncthreads();
     }
-    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+    if (threadIdx.x == 0) ke_part[blockIdx.x] = red[0];
+    if (!DRIFT || !disp_part) return;
+    __syncthreads();
+    red[threadIdx.x] = mx;
+    __syncthreads();
+    for (int o = MD_THREADS / 2; o > 0; o >>= 1) {
+        if (static_cast<int>(threadIdx.x) < o) {
+            const double b = red[threadIdx.x + o];
+            if (b > red[threadIdx.x] || b != b) red[threadIdx.x] = b;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double r = red[0], o = disp_part[blockIdx.x];
+        disp_part[blockIdx.x] = (r > o || r != r) ? r : o;
+    }
 }
 
 // max_n |x_n - x_ref_n| per block
@@ -162,8 +205,7 @@ template <typename T>
 int verlet_impl(pod_handle* h, int N, int P, void* pos, void* vel, void* F, const double* cell, const int* offsets,
                 const int* nbr_j, const int* shift, const int* rev, const void* c, double mass, double dt, int nsteps,
                 double* E_pot, double* E_kin, const void* pos_ref, double* max_disp) {
-    const long n3 = 3L * N;
-    const int nb3 = md_blocks(n3), nb1 = md_blocks(N);
+    const int nb1 = md_blocks(N);
     int rc = ensure_mscratch(h, sizeof(double) * (KE_RING + 1) * MD_BLOCKS);
     if (rc != POD_OK) return rc;
     double* partd = static_cast<double*>(h->d_mscratch);   // running displacement maxima
@@ -178,21 +220,29 @@ int verlet_impl(pod_handle* h, int N, int P, void* pos, void* vel, void* F, cons
         hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(MD_THREADS), 0, h->stream, max_disp, 1);
         hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(MD_THREADS), 0, h->stream, partd, MD_BLOCKS);
     }
+    // step s: half kick + drift, forces, half kick; the closing half kick of
+    // step s and the opening half kick and drift of step s + 1 share one
+    // launch (same forces)
+    if (N > 0 && nsteps > 0)
+        hipLaunchKernelGGL((kick_drift_kernel<T>), dim3(nb1), dim3(MD_THREADS), 0, h->stream, N, x, v, f, xr, hka, dt,
+                           xr ? partd : nullptr);
     for (int s = 0; s < nsteps; ++s) {
-        if (N > 0)
-            hipLaunchKernelGGL((kick_drift_kernel<T>), dim3(nb1), dim3(MD_THREADS), 0, h->stream, N, x, v, f, xr, hka,
-                               dt, xr ? partd : nullptr);
         rc = pod_energy_forces(h, N, P, pos, cell, offsets, nbr_j, shift, rev, c, nullptr, E_pot ? E_pot + s : nullptr,
                                F, nullptr, nullptr);
         if (rc != POD_OK) return rc;
         double* ke = ring + static_cast<long>(s % KE_RING) * MD_BLOCKS;
-        if (N > 0)
-            hipLaunchKernelGGL((kick_kernel<T>), dim3(nb3), dim3(MD_THREADS), 0, h->stream, n3, v, f, hka,
-                               half_m_over_acc, ke);
+        if (N > 0) {
+            if (s + 1 < nsteps)
+                hipLaunchKernelGGL((kick_atoms_kernel<T, true>), dim3(nb1), dim3(MD_THREADS), 0, h->stream, N, x, v, f,
+                                   xr, hka, dt, half_m_over_acc, ke, xr ? partd : nullptr);
+            else
+                hipLaunchKernelGGL((kick_atoms_kernel<T, false>), dim3(nb1), dim3(MD_THREADS), 0, h->stream, N, x, v,
+                                   f, xr, hka, dt, half_m_over_acc, ke, nullptr);
+        }
         // kinetic energies of up to KE_RING steps in one launch, one block per step
         if (E_kin && (s % KE_RING == KE_RING - 1 || s == nsteps - 1)) {
             const int cnt = s % KE_RING + 1;
-            hipLaunchKernelGGL(fold_kernel, dim3(cnt), dim3(MD_THREADS), 0, h->stream, ring, N > 0 ? nb3 : 0, 0,
+            hipLaunchKernelGGL(fold_kernel, dim3(cnt), dim3(MD_THREADS), 0, h->stream, ring, N > 0 ? nb1 : 0, 0,
                                E_kin + (s + 1 - cnt), static_cast<long>(MD_BLOCKS));
         }
     }
