@@ -111,16 +111,16 @@ struct AtomLds {
     size_t off_e, off_t, total;
 };
 
-// With the network (mode 2) the T area holds, while the network runs, the
-// basis rows in the adjoint-row slots and after them one tile: the
-// standardised inputs [16][MAX_IN] (bfloat16), later overwritten by the
-// input gradients [16][MAX_IN] (FP32), and the outputs [16] (FP32).
+// With the network (mode 2) a workgroup is nw wavefronts, each with the
+// layout above (its T area holds the basis rows in the adjoint-row slots
+// while the network runs), followed by the network tiles of the workgroup's
+// nw * APW atoms, 16 atoms per tile.  A tile slot holds the standardised
+// inputs [16][MAX_IN] (bfloat16), later overwritten by the input gradients
+// [16][MAX_IN] (FP32), and the outputs [16] (FP32).
 constexpr size_t NET_LDS = 16 * net::MAX_IN * 4 + 16 * 4;
-__host__ __device__ constexpr size_t net_tile_offset(int apw, int AST, size_t tsize) {
-    return (static_cast<size_t>(apw) * AST * tsize + 15) / 16 * 16;
-}
+__host__ __device__ constexpr int net_tiles(int nw, int apw) { return (nw * apw + 15) / 16; }
 
-__host__ __device__ inline AtomLds atom_lds_layout(int K, int NA, int M, size_t tsize, int KA, int PA, bool netw) {
+__host__ __device__ inline AtomLds atom_lds_layout(int K, int NA, int M, size_t tsize, int KA, int PA) {
     const int apw = WAVE / K;
     AtomLds L;
     L.off_e = 0;
@@ -132,10 +132,6 @@ __host__ __device__ inline AtomLds atom_lds_layout(int K, int NA, int M, size_t 
     const size_t gst = static_cast<size_t>(2 + PA + KA) * WAVE * sizeof(double);
     size_t t = stage > adj ? stage : adj;
     t = t > gst ? t : gst;
-    if (netw) {
-        const size_t tn = net_tile_offset(apw, abar_stride(K, NA, static_cast<int>(tsize)), tsize) + NET_LDS;
-        t = t > tn ? t : tn;
-    }
     L.total = L.off_t + t;
     return L;
 }
@@ -201,18 +197,28 @@ __device__ __forceinline__ void atom_body(const KArgs<T>& g) {
     const int M = P->M;
     const int SS = stage_stride(K);
     const int AST = abar_stride(K, NA, sizeof(T));   // per-atom stride of the adjoint rows
-    const int lane = threadIdx.x;
     const int apw = WAVE / K;
+    // Mode 2: nw wavefronts per workgroup, wavefront wid taking atom group
+    // grp = blockIdx.x * nw + wid of the ngrp groups of APW atoms (the last
+    // workgroup may hold groups past the end, which only take part in the
+    // workgroup's barriers).  Otherwise one wavefront per workgroup.
+    const int nw = MODE == 2 ? static_cast<int>(blockDim.x) / WAVE : 1;
+    const int wid = MODE == 2 ? __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / WAVE) : 0;
+    const int lane = MODE == 2 ? static_cast<int>(threadIdx.x) % WAVE : static_cast<int>(threadIdx.x);
+    const int grp = MODE == 2 ? static_cast<int>(blockIdx.x) * nw + wid : static_cast<int>(blockIdx.x);
+    const int ngrp = MODE == 2 ? (g.N + apw - 1) / apw : static_cast<int>(gridDim.x);
+    const bool grp_live = MODE != 2 || grp < ngrp;
     const int al = lane / K;
     const int q = lane - al * K;       // radial index m, or neighbour slot within a round
     const int m = q;
-    const int atom = blockIdx.x * apw + al;
+    const int atom = grp * apw + al;
     const bool act = (al < apw) && (atom < g.N);
 
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const AtomLds LY = atom_lds_layout(K, NA, M, sizeof(T), KA, PA, MODE == 2);
-    double* sE = reinterpret_cast<double*>(smem_raw + LY.off_e);
-    T* sT = reinterpret_cast<T*>(smem_raw + LY.off_t);
+    const AtomLds LY = atom_lds_layout(K, NA, M, sizeof(T), KA, PA);
+    unsigned char* wbase = smem_raw + (MODE == 2 ? static_cast<size_t>(wid) * LY.total : 0);
+    double* sE = reinterpret_cast<double*>(wbase + LY.off_e);
+    T* sT = reinterpret_cast<T*>(wbase + LY.off_t);
 
     int beg = 0, cnt = 0;
     int eb = 0;                         // error-word bits found by this lane
@@ -350,7 +356,7 @@ __device__ __forceinline__ void atom_body(const KArgs<T>& g) {
                 if (p < Ka4) sG[(2 + P3e + p) * WAVE + lane] = static_cast<double>(d4[p]);
         }
         wave_sync();
-        const int na = (g.N - blockIdx.x * apw < apw) ? g.N - blockIdx.x * apw : apw;
+        const int na = (g.N - grp * apw < apw) ? g.N - grp * apw : apw;
         const int nj3 = 2 + P3e + Ka4;     // columns per radial index
         for (int t = lane; t < K * nj3; t += WAVE) {
             const int mm = t / nj3, j = t - mm * nj3;
@@ -361,9 +367,9 @@ __device__ __forceinline__ void atom_body(const KArgs<T>& g) {
             if (col < 0) continue;
             double sum = 0.0;
             for (int a2 = 0; a2 < na; ++a2) sum += sG[j * WAVE + a2 * K + mm];
-            g.part[static_cast<size_t>(10 + col) * gridDim.x + blockIdx.x] = sum;
+            if (grp_live) g.part[static_cast<size_t>(10 + col) * ngrp + grp] = sum;
         }
-        if (lane == 0) g.part[static_cast<size_t>(10) * gridDim.x + blockIdx.x] = static_cast<double>(na);
+        if (lane == 0 && grp_live) g.part[static_cast<size_t>(10) * ngrp + grp] = static_cast<double>(na);
         wave_sync();
     }
 
@@ -392,13 +398,16 @@ __device__ __forceinline__ void atom_body(const KArgs<T>& g) {
 #pragma unroll
     for (int n = 0; n <= PA; ++n) eff3[n] = w3[n];
     if constexpr (MODE == 2) {
-        // network surrogate (eq. (673a)) on the wavefront's atoms, 16 at a
+        // network surrogate (eq. (673a)) on the workgroup's atoms, 16 at a
         // time (pod_net.h): the 2/3-body descriptors standardised and rounded
         // as the network kernels do, then the energy y_i and the adjoint
         // weights c + dy/dD_i.  The basis row waits in its adjoint-row slot
         // in LDS meanwhile (the adjoint is formed there in place below), so
-        // the network's registers do not add to the row's; the network's
-        // tiles follow the adjoint rows.
+        // the network's registers do not add to the row's.  Every wavefront
+        // writes the input rows of its atoms (row wid * APW + a of the
+        // workgroup's tiles); the tiles are then shared out over the
+        // wavefronts, so a workgroup of nw wavefronts evaluates
+        // ceil(nw * APW / 16) tiles rather than nw partly empty ones.
         using namespace net;
         if (act) {
             T* brow = sT + al * AST + m * NA;
@@ -406,68 +415,83 @@ __device__ __forceinline__ void atom_body(const KArgs<T>& g) {
             for (int mu = 0; mu < NA; ++mu) brow[mu] = acc[mu];
         }
         const int n_in = g.n_net;
-        unsigned char* nbase = reinterpret_cast<unsigned char*>(sT) + net_tile_offset(apw, AST, sizeof(T));
-        unsigned short* sX = reinterpret_cast<unsigned short*>(nbase);   // [16][MAX_IN] (inputs)
-        float* sD = reinterpret_cast<float*>(nbase);                      // [16][MAX_IN] (gradients; same place)
-        float* sY = sD + 16 * MAX_IN;                                     // [16]
-        const int r = lane & 15, gq = lane >> 4;
+        const int ntile = net_tiles(nw, apw);
+        unsigned char* nreg = smem_raw + static_cast<size_t>(nw) * LY.total;
+        const int row = wid * apw + al;   // the atom's row in the workgroup's tiles
+        unsigned char* rslot = nreg + static_cast<size_t>(row >> 4) * NET_LDS;
+        unsigned short* xrow = reinterpret_cast<unsigned short*>(rslot) + (row & 15) * MAX_IN;
+        const float* drow = reinterpret_cast<const float*>(rslot) + (row & 15) * MAX_IN;
+        const float* yrow = reinterpret_cast<const float*>(rslot) + 16 * MAX_IN + (row & 15);
         const int off3 = P->off3;
-#pragma unroll 1
-        for (int tb = 0; tb < apw; tb += 16) {
-            const bool mine = act && al >= tb && al < tb + 16;
-            const int ra = al - tb;
-            // the weights' address depends on tb (by a term that is zero), so
-            // their loads stay inside the loop instead of being hoisted in
-            // front of it and held in registers across it
-            const PackedW nw{reinterpret_cast<const Packed*>(reinterpret_cast<const char*>(g.netw) + (tb >> 30))};
-            // zero the input tile (2 KB: 32 bytes per lane)
-            uint4* z4 = reinterpret_cast<uint4*>(sX);
-            z4[2 * lane] = uint4{0u, 0u, 0u, 0u};
-            z4[2 * lane + 1] = uint4{0u, 0u, 0u, 0u};
+        {
+            // zero the wavefront's rows (128 bytes each), and with the last
+            // wavefront the rows of the last tile past the workgroup's atoms
+            const Packed* pk = g.netw;
+            const int r0 = wid * apw;
+            const int r1 = wid == nw - 1 ? 16 * ntile : r0 + apw;
+            for (int idx = lane; idx < (r1 - r0) * 8; idx += WAVE) {
+                const int rr = r0 + (idx >> 3);
+                uint4* z4 = reinterpret_cast<uint4*>(nreg + static_cast<size_t>(rr >> 4) * NET_LDS) + (rr & 15) * 8;
+                z4[idx & 7] = uint4{0u, 0u, 0u, 0u};
+            }
             wave_sync();
-            if (mine) {
+            if (act) {
                 if (has2)
-                    sX[ra * MAX_IN + m] = to_bf16(static_cast<float>((acc[0] - static_cast<T>(nw.p->mu[m])) *
-                                                                     static_cast<T>(nw.p->isg[m])));
+                    xrow[m] = to_bf16(static_cast<float>((acc[0] - static_cast<T>(pk->mu[m])) *
+                                                         static_cast<T>(pk->isg[m])));
                 if (has3) {
 #pragma unroll
                     for (int n = 0; n <= PA; ++n)
                         if (n <= P3) {
                             const int k = off3 - 1 + m * (P3 + 1) + n;
-                            sX[ra * MAX_IN + k] = to_bf16(static_cast<float>(
-                                (d3[n] - static_cast<T>(nw.p->mu[k])) * static_cast<T>(nw.p->isg[k])));
+                            xrow[k] = to_bf16(static_cast<float>((d3[n] - static_cast<T>(pk->mu[k])) *
+                                                                 static_cast<T>(pk->isg[k])));
                         }
                 }
             }
-            wave_sync();
+        }
+        __syncthreads();
+        const int r = lane & 15, gq = lane >> 4;
+#pragma unroll 1
+        for (int t = wid; t < ntile; t += nw) {
+            // the weights' address depends on t by a term that is zero at run
+            // time but not provably so (t is bounded by the launch, K is not),
+            // so their loads stay inside the loop instead of being hoisted in
+            // front of it and held in registers across it
+            const int zero = (t * K) >> 30;
+            const PackedW wts{reinterpret_cast<const Packed*>(reinterpret_cast<const char*>(g.netw) + zero)};
+            unsigned char* tslot = nreg + static_cast<size_t>(t) * NET_LDS;
+            const unsigned short* sX = reinterpret_cast<const unsigned short*>(tslot);
+            float* sD = reinterpret_cast<float*>(tslot);
+            float* sY = sD + 16 * MAX_IN;
             bf4 xb[4];
 #pragma unroll
             for (int s = 0; s < 4; ++s) xb[s] = *reinterpret_cast<const bf4*>(&sX[r * MAX_IN + 16 * s + 4 * gq]);
             wave_sync();   // the input tile is read before the gradients overwrite it
             f4 z1[4], z2[4], dx[4];
             bf4 h1b[4];
-            layers(nw, xb, r, gq, z1, h1b, z2);
-            const float y = output(nw, z2, gq);
-            input_grad(nw, xb, z2, r, gq, tb >> 30, dx);
+            layers(wts, xb, r, gq, z1, h1b, z2);
+            const float y = output(wts, z2, gq);
+            input_grad(wts, xb, z2, r, gq, zero, dx);
             if (gq == 0) sY[r] = y;
 #pragma unroll
             for (int s = 0; s < 4; ++s)
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const int k = 16 * s + 4 * gq + i;
-                    if (k < n_in) sD[r * MAX_IN + k] = dx[s][i] * nw.p->isg[k];
+                    if (k < n_in) sD[r * MAX_IN + k] = dx[s][i] * wts.p->isg[k];
                 }
             wave_sync();
-            if (mine) {
-                if (has2) eff2 += static_cast<T>(sD[ra * MAX_IN + m]);
-                if (has3) {
+        }
+        __syncthreads();
+        if (act) {
+            if (has2) eff2 += static_cast<T>(drow[m]);
+            if (has3) {
 #pragma unroll
-                    for (int n = 0; n <= PA; ++n)
-                        if (n <= P3) eff3[n] += static_cast<T>(sD[ra * MAX_IN + off3 - 1 + m * (P3 + 1) + n]);
-                }
-                if (q == 0) e += static_cast<double>(sY[ra]);
+                for (int n = 0; n <= PA; ++n)
+                    if (n <= P3) eff3[n] += static_cast<T>(drow[off3 - 1 + m * (P3 + 1) + n]);
             }
-            wave_sync();
+            if (q == 0) e += static_cast<double>(*yrow);
         }
     }
 #pragma unroll
@@ -538,7 +562,7 @@ __device__ __forceinline__ void atom_body(const KArgs<T>& g) {
         }
         wave_sync();
         const double eb = wave_sum(ei);
-        if (lane == 0) g.part[blockIdx.x] = eb;
+        if (lane == 0 && grp_live) g.part[grp] = eb;
     }
     if (!g.want_back) return;
 
@@ -555,7 +579,7 @@ __device__ __forceinline__ void atom_body(const KArgs<T>& g) {
     }
     wave_sync();
     {
-        const int a0 = blockIdx.x * apw;
+        const int a0 = grp * apw;
         const int na = (g.N - a0 < apw) ? g.N - a0 : apw;
         const int nv = na * AST;
         T* dst = g.abar + static_cast<size_t>(a0) * AST;
@@ -576,12 +600,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void at
     atom_body<T, PA, MODE, FAST>(g);
 }
 
-// The FP32 surrogate instances (mode 2) are held to three wavefronts per
-// SIMD, which their LDS (basis rows parked while the network runs) allows
-// anyway.
-template <typename T, int PA, int MODE, bool FAST>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void atom_kernel_occ3(KArgs<T> g) {
-    atom_body<T, PA, MODE, FAST>(g);
+// The surrogate instances (mode 2) run up to four wavefronts per workgroup,
+// held to WPE wavefronts per SIMD: three in FP32 (which their LDS allows
+// anyway), two in FP64 up to angular degree 4, as the mode-1 instances.
+template <typename T, int PA, bool FAST, int WPE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void atom_net_kernel(KArgs<T> g) {
+    atom_body<T, PA, 2, FAST>(g);
 }
 
 // ---------------------------------------------------------------------------
@@ -1020,15 +1044,15 @@ __global__ __launch_bounds__(256) void reverse_kernel(const int* __restrict__ of
 }
 
 template <typename T, int PA, int MODE>
-hipError_t launch_atom(const KArgs<T>& a, bool fast, int nblk, size_t lds, hipStream_t st) {
+hipError_t launch_atom(const KArgs<T>& a, bool fast, int nblk, int nthr, size_t lds, hipStream_t st) {
     constexpr bool occ2 = sizeof(T) == 8 && PA <= 4;
-    constexpr bool occ3 = sizeof(T) == 4 && MODE == 2;
-    if constexpr (occ2) {
+    if constexpr (MODE == 2) {
+        constexpr int WPE = sizeof(T) == 4 ? 3 : (occ2 ? 2 : 1);
+        if (fast) hipLaunchKernelGGL((atom_net_kernel<T, PA, true, WPE>), dim3(nblk), dim3(nthr), lds, st, a);
+        else hipLaunchKernelGGL((atom_net_kernel<T, PA, false, WPE>), dim3(nblk), dim3(nthr), lds, st, a);
+    } else if constexpr (occ2) {
         if (fast) hipLaunchKernelGGL((atom_kernel_occ2<T, PA, MODE, true>), dim3(nblk), dim3(WAVE), lds, st, a);
         else hipLaunchKernelGGL((atom_kernel_occ2<T, PA, MODE, false>), dim3(nblk), dim3(WAVE), lds, st, a);
-    } else if constexpr (occ3) {
-        if (fast) hipLaunchKernelGGL((atom_kernel_occ3<T, PA, MODE, true>), dim3(nblk), dim3(WAVE), lds, st, a);
-        else hipLaunchKernelGGL((atom_kernel_occ3<T, PA, MODE, false>), dim3(nblk), dim3(WAVE), lds, st, a);
     } else {
         if (fast) hipLaunchKernelGGL((atom_kernel<T, PA, MODE, true>), dim3(nblk), dim3(WAVE), lds, st, a);
         else hipLaunchKernelGGL((atom_kernel<T, PA, MODE, false>), dim3(nblk), dim3(WAVE), lds, st, a);
@@ -1037,15 +1061,15 @@ hipError_t launch_atom(const KArgs<T>& a, bool fast, int nblk, size_t lds, hipSt
 }
 
 template <typename T, int MODE>
-hipError_t dispatch_pa(int PA, const KArgs<T>& a, bool fast, int nblk, size_t lds, hipStream_t st) {
+hipError_t dispatch_pa(int PA, const KArgs<T>& a, bool fast, int nblk, int nthr, size_t lds, hipStream_t st) {
     switch (PA) {
-        case 0: return launch_atom<T, 0, MODE>(a, fast, nblk, lds, st);
-        case 1: return launch_atom<T, 1, MODE>(a, fast, nblk, lds, st);
-        case 2: return launch_atom<T, 2, MODE>(a, fast, nblk, lds, st);
-        case 3: return launch_atom<T, 3, MODE>(a, fast, nblk, lds, st);
-        case 4: return launch_atom<T, 4, MODE>(a, fast, nblk, lds, st);
-        case 5: return launch_atom<T, 5, MODE>(a, fast, nblk, lds, st);
-        case 6: return launch_atom<T, 6, MODE>(a, fast, nblk, lds, st);
+        case 0: return launch_atom<T, 0, MODE>(a, fast, nblk, nthr, lds, st);
+        case 1: return launch_atom<T, 1, MODE>(a, fast, nblk, nthr, lds, st);
+        case 2: return launch_atom<T, 2, MODE>(a, fast, nblk, nthr, lds, st);
+        case 3: return launch_atom<T, 3, MODE>(a, fast, nblk, nthr, lds, st);
+        case 4: return launch_atom<T, 4, MODE>(a, fast, nblk, nthr, lds, st);
+        case 5: return launch_atom<T, 5, MODE>(a, fast, nblk, nthr, lds, st);
+        case 6: return launch_atom<T, 6, MODE>(a, fast, nblk, nthr, lds, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -1079,8 +1103,25 @@ hipError_t dispatch_pair(int PA, const PArgs<T>& a, bool fast, int nblk, size_t 
     }
 }
 
-size_t lds_bytes(int K, int PA, size_t tsize, int M, bool netw = false) {
-    return atom_lds_layout(K, n_mono(PA), M, tsize, n_partitions(PA), PA, netw).total;
+// LDS of one wavefront of the per-atom kernel
+size_t lds_bytes(int K, int PA, size_t tsize, int M) {
+    return atom_lds_layout(K, n_mono(PA), M, tsize, n_partitions(PA), PA).total;
+}
+
+// Wavefronts per workgroup of the mode-2 kernel: of 1 to 4, the count with
+// the fewest network tiles per wavefront whose LDS (per_wave each, plus the
+// tiles) fits 64 KB and allows at least as many wavefronts per compute unit
+// (160 KB of LDS) as one wavefront per workgroup.
+int net_waves(int K, size_t per_wave) {
+    const int apw = WAVE / K;
+    const auto bytes = [&](int w) { return w * per_wave + net_tiles(w, apw) * NET_LDS; };
+    const auto waves_per_cu = [&](int w) { return static_cast<int>(163840 / bytes(w)) * w; };
+    int best = 1;
+    for (int w = 2; w <= 4; ++w) {
+        if (bytes(w) > 65536 || waves_per_cu(w) < waves_per_cu(1)) continue;
+        if (net_tiles(w, apw) * best < net_tiles(best, apw) * w) best = w;
+    }
+    return best;
 }
 
 template <typename T>
@@ -1148,7 +1189,7 @@ int descriptors_impl(pod_handle* h, int N, int P, const void* pos, const double*
     const int apw = WAVE / h->K;
     const int nblk = (N + apw - 1) / apw;
     timing_begin(h, 1);
-    const hipError_t e = dispatch_pa<T, 0>(h->PA, a, h->std_ok != 0, nblk, lds_bytes(h->K, h->PA, sizeof(T), h->M),
+    const hipError_t e = dispatch_pa<T, 0>(h->PA, a, h->std_ok != 0, nblk, WAVE, lds_bytes(h->K, h->PA, sizeof(T), h->M),
                                            h->stream);
     timing_end(h, 1);
     return e == hipSuccess ? POD_OK : POD_EHIP;
@@ -1248,9 +1289,12 @@ int energy_forces_run(pod_handle* h, char* scratch, double* facc, int N, int P, 
         return POD_OK;
     }
     if (nblk > 0) {
+        const size_t pw = lds_bytes(h->K, h->PA, sizeof(T), h->M);
+        const int nw = MODE == 2 ? net_waves(h->K, pw) : 1;
+        const size_t lds = nw * pw + (MODE == 2 ? net_tiles(nw, apw) * NET_LDS : 0);
         timing_begin(h, 1);
-        const hipError_t e = dispatch_pa<T, MODE>(h->PA, a, h->std_ok != 0, nblk,
-                                               lds_bytes(h->K, h->PA, sizeof(T), h->M, MODE == 2), h->stream);
+        const hipError_t e = dispatch_pa<T, MODE>(h->PA, a, h->std_ok != 0, (nblk + nw - 1) / nw, nw * WAVE, lds,
+                                               h->stream);
         timing_end(h, 1);
         if (e != hipSuccess) return POD_EHIP;
     }

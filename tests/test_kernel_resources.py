@@ -21,8 +21,8 @@ RECORDED = {
     "void finalize_kernel<double>(FinArgs<double>)": (0, 8, 28),
     "void finalize_kernel<float>(FinArgs<float>)": (0, 8, 28),
     # the surrogate's per-atom kernel with the network inside (FP32 benchmark model)
-    "void atom_kernel_occ3<float, 4, 2, true>(KArgs<float>)": (0, 3, 155),
-    "void atom_kernel_occ2<double, 4, 2, true>(KArgs<double>)": (0, 2, 224),
+    "void atom_net_kernel<float, 4, true, 3>(KArgs<float>)": (0, 3, 134),
+    "void atom_net_kernel<double, 4, true, 2>(KArgs<double>)": (0, 2, 224),
 }
 
 
