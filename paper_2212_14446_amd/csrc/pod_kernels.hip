@@ -472,7 +472,7 @@ __device__ __forceinline__ void atom_body(const KArgs<T>& g) {
             bf4 h1b[4];
             layers(wts, xb, r, gq, z1, h1b, z2);
             const float y = output(wts, z2, gq);
-            input_grad(wts, xb, z2, r, gq, zero, dx);
+            input_grad(wts, z1, z2, r, gq, dx);
             if (gq == 0) sY[r] = y;
 #pragma unroll
             for (int s = 0; s < 4; ++s)

@@ -150,7 +150,7 @@ __global__ __launch_bounds__(256) void infer_kernel(InferArgs<TX> a) {
         if (!a.dydx) continue;
         // back-propagation to the inputs (eq. (673a))
         f4 dx[4];
-        net::input_grad(LdsW{L}, xb, z2, r, g, 0, dx);
+        net::input_grad(LdsW{L}, z1, z2, r, g, dx);
         if (ok) {
 #pragma unroll
             for (int s = 0; s < 4; ++s)

@@ -137,13 +137,11 @@ __device__ __forceinline__ float output(const W& w, const f4 (&z2)[4], int g) {
 }
 
 // Back-propagation to the standardised inputs (eq. (673a)): dx[s][i] =
-// dy/dx_k for k = 16 s + 4 g + i (the caller applies inv_sigma).  The first
-// layer's pre-activations are formed again from the inputs (the same
-// products, the same bits) rather than kept from the forward pass: `zero`
-// is 0 at run time but unknown to the compiler, so the second evaluation is
-// not merged with the first and z1 need not stay in registers in between.
+// dy/dx_k for k = 16 s + 4 g + i (the caller applies inv_sigma), from the
+// first layer's pre-activations z1 (bias included) and the second's z2 kept
+// from the forward pass.
 template <class W>
-__device__ __forceinline__ void input_grad(const W& w, const bf4 (&xb)[4], const f4 (&z2)[4], int r, int g, int zero,
+__device__ __forceinline__ void input_grad(const W& w, const f4 (&z1)[4], const f4 (&z2)[4], int r, int g,
                                            f4 (&dx)[4]) {
     bf4 dz2b[4];
 #pragma unroll
@@ -155,19 +153,11 @@ __device__ __forceinline__ void input_grad(const W& w, const bf4 (&xb)[4], const
     bf4 dz1b[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-        f4 z1 = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            bf4 x = xb[s];
-            x[0] += static_cast<short>(zero);
-            z1 = mfma(w.w1(16 * t + r, 16 * s + 4 * g), x, z1);
-        }
         f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int u = 0; u < 4; ++u) acc = mfma(w.w2t(16 * t + r, 16 * u + 4 * g), dz2b[u], acc);
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-            dz1b[t][i] = static_cast<short>(to_bf16(acc[i] * silu_d(z1[i] + w.b1(16 * t + 4 * g + i))));
+        for (int i = 0; i < 4; ++i) dz1b[t][i] = static_cast<short>(to_bf16(acc[i] * silu_d(z1[t][i])));
         tile_fence();
     }
 #pragma unroll
