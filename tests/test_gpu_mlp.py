@@ -289,10 +289,12 @@ def test_surrogate_energy_forces_vs_oracle(sur_case, dtype, gather):
 
 @pytest.mark.parametrize("K,P3", [(3, 4), (1, 4), (8, 6)])
 def test_surrogate_several_network_tiles_per_wave(K, P3):
-    """With K = 3 (21 atoms per wavefront) and K = 1 (64) the per-atom kernel
-    runs the network on two and four tiles of 16 atoms in turn; K = 8 at
-    P3 = 6 gives the largest input, 64 descriptors (all four input groups
-    filled).  The
+    """With K = 3 (21 atoms per wavefront, two wavefronts per workgroup in
+    FP64: 42 atoms in three tiles of 16, the first wavefront taking two in
+    turn, and the last workgroup holding a group past the end of the list)
+    and K = 1 (64 atoms, four tiles in turn) the per-atom kernel runs the
+    network on several tiles per wavefront; K = 8 at P3 = 6 gives the
+    largest input, 64 descriptors (all four input groups filled).  The
     network's outputs must equal those of the network kernel on the
     device's own descriptors (same products, same rounding: the energies to
     FP64 rounding of the linear part), and the forces those of the oracle's
@@ -333,6 +335,58 @@ def test_surrogate_several_network_tiles_per_wave(K, P3):
     e = m.energy_forces_surrogate(w.pos, w.cell, nb, c, net, forces=False, virial=False)
     torch.cuda.synchronize()
     assert np.array_equal(e["E_atom"].cpu().numpy(), got["E_atom"]) and e["E"].item() == got["E"][0]
+
+
+@pytest.mark.parametrize("K,P3,cells", [(6, 4, 4), (8, 6, 3)])
+def test_surrogate_f32_workgroup_of_several_wavefronts(K, P3, cells):
+    """FP32, where the per-atom kernel's workgroup is several wavefronts that
+    share the network tiles: K = 6 on 128 atoms (three wavefronts of 10
+    atoms, 13 atom groups: the last workgroup holds two groups past the end
+    of the list) and K = 8 at P3 = 6 on 54 atoms (two wavefronts of 8 atoms,
+    7 groups, one past the end).  Energies against the linear part on the
+    device's own descriptors plus the network kernel's outputs (FP32
+    rounding of the linear part: 1e-5), forces and virial against the
+    oracle's adjoint with the device's per-atom weights (the FP32 force
+    tolerance, 1e-4), and the energy-only launch bit for bit."""
+    import torch
+    S = wl.PodSetup(rin=0.5, rcut=5.0, L=8, K2=K, K3=K, K4=0, P3=P3, P4=0)
+    w = wl.small_bcc(cells, sigma=0.15, seed=41 + K, setup=S)
+    pos = w.pos.astype(np.float32).astype(np.float64)
+    nl = wl.neighbor_list(pos, w.cell, S.rcut)   # listed on the rounded positions
+    op = oracle_params(S)
+    Q, _ = po.pod_basis(op)
+    args = (pos, w.cell, nl.offsets.astype(np.int64), nl.nbr_j, nl.shift3, op, Q)
+    D = po.descriptors_fast(*args)
+    rng = np.random.default_rng(42 + K)
+    f32 = lambda a: np.asarray(a, dtype=np.float32).astype(np.float64)
+    c = f32(rng.normal(size=D.shape[1]) / (D.std(0) + 1e-3) * 0.1)
+    n_in = D.shape[1] - 1
+    theta, _, _, _ = rand_case(1, n_in, 43 + K)
+    mu = f32(D[:, 1:].mean(0))
+    isg = f32(1.0 / (D[:, 1:].std(0) + 1e-6))
+    m = pod.PodModel(pod.setup_from_workload(S), "f32", Q=Q[:, :K])
+    net = surrogate.Network(n_in, seed=0)
+    f = lambda a: torch.tensor(a, dtype=torch.float32, device="cuda")
+    net.theta, net.mu, net.inv_sigma = f(theta), f(mu), f(isg)
+    nb = pod.DeviceNeighbors.from_list(nl)
+    nb.build_reverse(m)
+    say(f"[gpu] surrogate f32 K={K}: N={len(pos)}, {-(-len(pos) // (64 // K))} atom groups, n_in={n_in}")
+    o = m.energy_forces_surrogate(pos, w.cell, nb, c, net)
+    Dd = m.descriptors(pos, w.cell, nb)
+    y_dev, g_dev = net.forward(m.h, Dd, x_col=1, ldx=m.M)
+    torch.cuda.synchronize()
+    got = {k: v.double().cpu().numpy() for k, v in o.items()}
+    Dd = Dd.double().cpu().numpy()
+    y_dev, g_dev = y_dev.double().cpu().numpy(), g_dev.double().cpu().numpy()
+    e1 = relerr(got["E_atom"], Dd @ c + y_dev)
+    C = c[None, :] + np.concatenate([np.zeros((len(pos), 1)), g_dev], axis=1)
+    F_C, W_C = mo.forces_from_atom_weights(pos, *args[1:], C)
+    e2, e3 = relerr(got["F"], F_C), relerr(got["W"], W_C)
+    say(f"[gpu]   E_atom rel {e1:.2e}, F rel {e2:.2e}, W rel {e3:.2e}")
+    assert e1 < 1e-5 and e2 < 1e-4 and e3 < 1e-4
+    e = m.energy_forces_surrogate(pos, w.cell, nb, c, net, forces=False, virial=False)
+    torch.cuda.synchronize()
+    assert np.array_equal(e["E_atom"].double().cpu().numpy(), got["E_atom"]) and e["E"].item() == got["E"][0]
 
 
 def test_surrogate_silent_network_equals_linear_path(sur_case):
