@@ -414,7 +414,6 @@ __device__ __forceinline__ void atom_body(const KArgs<T>& g) {
 #pragma unroll
             for (int mu = 0; mu < NA; ++mu) brow[mu] = acc[mu];
         }
-        const int n_in = g.n_net;
         const int ntile = net_tiles(nw, apw);
         unsigned char* nreg = smem_raw + static_cast<size_t>(nw) * LY.total;
         const int row = wid * apw + al;   // the atom's row in the workgroup's tiles
@@ -474,13 +473,16 @@ __device__ __forceinline__ void atom_body(const KArgs<T>& g) {
             const float y = output(wts, z2, gq);
             input_grad(wts, z1, z2, r, gq, dx);
             if (gq == 0) sY[r] = y;
+            // all 64 gradient columns, without branches: the packed isg is
+            // zero beyond n_in, and those columns are not read
 #pragma unroll
-            for (int s = 0; s < 4; ++s)
+            for (int s = 0; s < 4; ++s) {
+                const f4 sg = *reinterpret_cast<const f4*>(&wts.p->isg[16 * s + 4 * gq]);
+                f4 v;
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int k = 16 * s + 4 * gq + i;
-                    if (k < n_in) sD[r * MAX_IN + k] = dx[s][i] * wts.p->isg[k];
-                }
+                for (int i = 0; i < 4; ++i) v[i] = dx[s][i] * sg[i];
+                *reinterpret_cast<f4*>(&sD[r * MAX_IN + 16 * s + 4 * gq]) = v;
+            }
             wave_sync();
         }
         __syncthreads();

@@ -382,14 +382,14 @@ __global__ __launch_bounds__(PACK_THREADS) void pack_kernel(const float* __restr
     if (i < H * MAX_IN) {
         const int h = i / MAX_IN, k = i - h * MAX_IN;
         const unsigned short b = to_bf16(k < n_in ? theta[h * n_in + k] : 0.0f);
-        out->W1[h * MAX_IN + k] = b;
-        out->W1T[k * H + h] = b;
+        out->W1[net::packed_index(h, k)] = b;
+        out->W1T[net::packed_index(k, h)] = b;
     } else if (i < H * MAX_IN + H * H) {
         const int j = i - H * MAX_IN;
         const int h2 = j / H, h1 = j - h2 * H;
         const unsigned short b = to_bf16(theta[o.o_W2 + j]);
-        out->W2[h2 * H + h1] = b;
-        out->W2T[h1 * H + h2] = b;
+        out->W2[net::packed_index(h2, h1)] = b;
+        out->W2T[net::packed_index(h1, h2)] = b;
     }
     if (blockIdx.x == 0) {
         const int t = threadIdx.x;

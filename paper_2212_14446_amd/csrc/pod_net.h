@@ -65,10 +65,21 @@ __host__ __device__ inline Layout layout(int n_in) {
     return L;
 }
 
+// Place of element (a, b) of a 64 x 64 weight matrix in its packed block.
+// The products of output group a / 16 read, in lane (r, g), the elements
+// (16 A + r, 16 B + 4 g + i) of the four input groups B: they are stored
+// together, 32 bytes per lane and output group, so that a lane's operands
+// for one output group come in two 16-byte loads and a wavefront's loads
+// cover 2 KB contiguously (rows of 64 elements would spread each load over
+// 16 cache lines).
+__host__ __device__ constexpr int packed_index(int a, int b) {
+    return (((a >> 4) * 64 + ((b & 15) >> 2) * 16 + (a & 15)) * 4 + (b >> 4)) * 4 + (b & 3);
+}
+
 // The weights as the products read them, packed once per call in global
 // memory for the per-atom kernel: bfloat16 W1 [h][k] (zero for k >= n_in),
-// its transpose, W2 [h2][h1] and its transpose; FP32 biases, output
-// weights and the standardisation.
+// its transpose, W2 [h2][h1] and its transpose, each in the order of
+// packed_index; FP32 biases, output weights and the standardisation.
 struct alignas(16) Packed {
     unsigned short W1[H * MAX_IN];
     unsigned short W1T[MAX_IN * H];
@@ -78,13 +89,13 @@ struct alignas(16) Packed {
     float b3, pad[3];
 };
 
-// Accessor of a Packed block (rows of 64 elements).
+// Accessor of a Packed block.
 struct PackedW {
     const Packed* __restrict__ p;
-    __device__ __forceinline__ bf4 w1(int h, int k) const { return *reinterpret_cast<const bf4*>(&p->W1[h * MAX_IN + k]); }
-    __device__ __forceinline__ bf4 w1t(int k, int h) const { return *reinterpret_cast<const bf4*>(&p->W1T[k * H + h]); }
-    __device__ __forceinline__ bf4 w2(int a, int b) const { return *reinterpret_cast<const bf4*>(&p->W2[a * H + b]); }
-    __device__ __forceinline__ bf4 w2t(int a, int b) const { return *reinterpret_cast<const bf4*>(&p->W2T[a * H + b]); }
+    __device__ __forceinline__ bf4 w1(int h, int k) const { return *reinterpret_cast<const bf4*>(&p->W1[packed_index(h, k)]); }
+    __device__ __forceinline__ bf4 w1t(int k, int h) const { return *reinterpret_cast<const bf4*>(&p->W1T[packed_index(k, h)]); }
+    __device__ __forceinline__ bf4 w2(int a, int b) const { return *reinterpret_cast<const bf4*>(&p->W2[packed_index(a, b)]); }
+    __device__ __forceinline__ bf4 w2t(int a, int b) const { return *reinterpret_cast<const bf4*>(&p->W2T[packed_index(a, b)]); }
     __device__ __forceinline__ float b1(int i) const { return p->b1[i]; }
     __device__ __forceinline__ float b2(int i) const { return p->b2[i]; }
     __device__ __forceinline__ float w3(int i) const { return p->w3[i]; }
