@@ -435,17 +435,24 @@ __device__ __forceinline__ void atom_body(const KArgs<T>& g) {
             }
             wave_sync();
             if (act) {
-                if (has2)
-                    xrow[m] = to_bf16(static_cast<float>((acc[0] - static_cast<T>(pk->mu[m])) *
-                                                         static_cast<T>(pk->isg[m])));
+                // the lane's standardisation values, requested together (an
+                // absent term reads entry 0 and is not written)
+                const int k2 = has2 ? m : 0;
+                const float mu2 = pk->mu[k2], is2 = pk->isg[k2];
+                float mu3[PA + 1], is3[PA + 1];
+#pragma unroll
+                for (int n = 0; n <= PA; ++n) {
+                    const int k = (has3 && n <= P3) ? off3 - 1 + m * (P3 + 1) + n : 0;
+                    mu3[n] = pk->mu[k];
+                    is3[n] = pk->isg[k];
+                }
+                if (has2) xrow[m] = to_bf16(static_cast<float>((acc[0] - static_cast<T>(mu2)) * static_cast<T>(is2)));
                 if (has3) {
 #pragma unroll
                     for (int n = 0; n <= PA; ++n)
-                        if (n <= P3) {
-                            const int k = off3 - 1 + m * (P3 + 1) + n;
-                            xrow[k] = to_bf16(static_cast<float>((d3[n] - static_cast<T>(pk->mu[k])) *
-                                                                 static_cast<T>(pk->isg[k])));
-                        }
+                        if (n <= P3)
+                            xrow[off3 - 1 + m * (P3 + 1) + n] =
+                                to_bf16(static_cast<float>((d3[n] - static_cast<T>(mu3[n])) * static_cast<T>(is3[n])));
                 }
             }
         }
