@@ -129,9 +129,10 @@ struct InferArgs {
 };
 
 // Forward and input gradient dy/dX, 4 waves per workgroup, one tile of 16
-// atoms per wave and step.
+// atoms per wave and step; held to four wavefronts per SIMD, which the LDS
+// of its weights allows.
 template <typename TX>
-__global__ __launch_bounds__(256) void infer_kernel(InferArgs<TX> a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void infer_kernel(InferArgs<TX> a) {
     __shared__ Weights L;
     load_weights(L, a.theta, a.mu, a.isg, a.n_in);
     __syncthreads();

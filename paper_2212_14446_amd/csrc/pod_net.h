@@ -44,9 +44,10 @@ __device__ __forceinline__ float silu_d(float z) {
 
 __device__ __forceinline__ f4 mfma(bf4 a, bf4 b, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0); }
 
-// Scheduling fence between output tiles: the weight operands of a tile are
-// requested when the tile starts, not all at the top of the network (which
-// would hold every operand of the network in registers at once).
+// Scheduling fence between output groups: the weight operands of a group
+// are requested one group ahead (during the previous group's products), not
+// all at the top of the network (which would hold every operand of the
+// network in registers at once).
 __device__ __forceinline__ void tile_fence() { __builtin_amdgcn_sched_barrier(0); }
 
 // Offsets of the parameter vector theta (FP32): W1 [64][n_in], b1 [64],
@@ -111,25 +112,45 @@ struct PackedW {
 template <class W>
 __device__ __forceinline__ void layers(const W& w, const bf4 (&xb)[4], int r, int g, f4 (&z1)[4], bf4 (&h1b)[4],
                                        f4 (&z2)[4]) {
+    // eight output groups (four of each layer); the operands of group q + 1
+    // are requested before the products of group q
+    bf4 op[4], nx[4];
+    f4 bias, nb;
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (int s = 0; s < 4; ++s) op[s] = w.w1(r, 16 * s + 4 * g);
 #pragma unroll
-        for (int s = 0; s < 4; ++s) acc = mfma(w.w1(16 * t + r, 16 * s + 4 * g), xb[s], acc);
+    for (int i = 0; i < 4; ++i) bias[i] = w.b1(4 * g + i);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            z1[t][i] = acc[i] + w.b1(16 * t + 4 * g + i);
-            h1b[t][i] = static_cast<short>(to_bf16(silu(z1[t][i])));
+    for (int q = 0; q < 8; ++q) {
+        if (q + 1 < 4) {
+#pragma unroll
+            for (int s = 0; s < 4; ++s) nx[s] = w.w1(16 * (q + 1) + r, 16 * s + 4 * g);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) nb[i] = w.b1(16 * (q + 1) + 4 * g + i);
+        } else if (q + 1 < 8) {
+#pragma unroll
+            for (int s = 0; s < 4; ++s) nx[s] = w.w2(16 * (q - 3) + r, 16 * s + 4 * g);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) nb[i] = w.b2(16 * (q - 3) + 4 * g + i);
         }
-        tile_fence();
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
         f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        if (q < 4) {
 #pragma unroll
-        for (int t = 0; t < 4; ++t) acc = mfma(w.w2(16 * u + r, 16 * t + 4 * g), h1b[t], acc);
+            for (int s = 0; s < 4; ++s) acc = mfma(op[s], xb[s], acc);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) z2[u][i] = acc[i] + w.b2(16 * u + 4 * g + i);
+            for (int i = 0; i < 4; ++i) {
+                z1[q][i] = acc[i] + bias[i];
+                h1b[q][i] = static_cast<short>(to_bf16(silu(z1[q][i])));
+            }
+        } else {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) acc = mfma(op[t], h1b[t], acc);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) z2[q - 4][i] = acc[i] + bias[i];
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s) op[s] = nx[s];
+        bias = nb;
         tile_fence();
     }
 }
@@ -154,6 +175,11 @@ __device__ __forceinline__ float output(const W& w, const f4 (&z2)[4], int g) {
 template <class W>
 __device__ __forceinline__ void input_grad(const W& w, const f4 (&z1)[4], const f4 (&z2)[4], int r, int g,
                                            f4 (&dx)[4]) {
+    // eight output groups (four of W2^T, four of W1^T); the operands of
+    // group q + 1 are requested before the products of group q
+    bf4 op[4], nx[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) op[u] = w.w2t(r, 16 * u + 4 * g);
     bf4 dz2b[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u)
@@ -163,20 +189,27 @@ __device__ __forceinline__ void input_grad(const W& w, const f4 (&z1)[4], const 
     tile_fence();
     bf4 dz1b[4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
+    for (int q = 0; q < 8; ++q) {
+        if (q + 1 < 4) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) nx[u] = w.w2t(16 * (q + 1) + r, 16 * u + 4 * g);
+        } else if (q + 1 < 8) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) nx[t] = w.w1t(16 * (q - 3) + r, 16 * t + 4 * g);
+        }
         f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        if (q < 4) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) acc = mfma(w.w2t(16 * t + r, 16 * u + 4 * g), dz2b[u], acc);
+            for (int u = 0; u < 4; ++u) acc = mfma(op[u], dz2b[u], acc);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) dz1b[t][i] = static_cast<short>(to_bf16(acc[i] * silu_d(z1[t][i])));
-        tile_fence();
-    }
+            for (int i = 0; i < 4; ++i) dz1b[q][i] = static_cast<short>(to_bf16(acc[i] * silu_d(z1[q][i])));
+        } else {
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-        f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+            for (int t = 0; t < 4; ++t) acc = mfma(op[t], dz1b[t], acc);
+            dx[q - 4] = acc;
+        }
 #pragma unroll
-        for (int t = 0; t < 4; ++t) acc = mfma(w.w1t(16 * s + r, 16 * t + 4 * g), dz1b[t], acc);
-        dx[s] = acc;
+        for (int s = 0; s < 4; ++s) op[s] = nx[s];
         tile_fence();
     }
 }

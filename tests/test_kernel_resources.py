@@ -21,7 +21,7 @@ RECORDED = {
     "void finalize_kernel<double>(FinArgs<double>)": (0, 8, 28),
     "void finalize_kernel<float>(FinArgs<float>)": (0, 8, 28),
     # the surrogate's per-atom kernel with the network inside (FP32 benchmark model)
-    "void atom_net_kernel<float, 4, true, 3>(KArgs<float>)": (0, 3, 138),
+    "void atom_net_kernel<float, 4, true, 3>(KArgs<float>)": (0, 3, 140),
     "void atom_net_kernel<double, 4, true, 2>(KArgs<double>)": (0, 2, 224),
 }
 
