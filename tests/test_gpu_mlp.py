@@ -389,6 +389,49 @@ def test_surrogate_f32_workgroup_of_several_wavefronts(K, P3, cells):
     assert np.array_equal(e["E_atom"].double().cpu().numpy(), got["E_atom"]) and e["E"].item() == got["E"][0]
 
 
+def test_surrogate_largest_box_f32():
+    """The surrogate benchmark's box, 1,024,000 atoms (FP32 POD, the 2/3-body
+    model with the network inside the per-atom kernel: 102,400 atom groups in
+    workgroups of three wavefronts, the last holding two groups past the end
+    of the list).  Every atom's energy against the descriptor kernel's linear
+    part plus the network kernel's output on the same descriptors: within the
+    FP32 rounding of the linear part (1e-5), where one bfloat16 rounding flip
+    between the two paths would show as ~1e-3; the energy-only launch bit for
+    bit; the total force of the periodic box zero to FP32 rounding."""
+    import torch
+    w = wl.config5_infer()
+    S = wl.SETUP_CFG5_23
+    pos = w.pos.astype(np.float32).astype(np.float64)
+    nl = wl.neighbor_list(pos, w.cell, S.rcut)
+    m = pod.PodModel(pod.setup_from_workload(S), "f32")
+    nb = pod.DeviceNeighbors.from_list(nl)
+    nb.build_reverse(m)
+    say(f"[gpu] surrogate f32 largest box: N={len(pos)} P={nl.n_pairs}")
+    Dd = m.descriptors(pos, w.cell, nb)
+    D = Dd.double().cpu().numpy()
+    n_in = S.M - 1
+    f32 = lambda a: np.asarray(a, dtype=np.float32).astype(np.float64)
+    rng = np.random.default_rng(52)
+    c = f32(rng.normal(size=S.M) / (D.std(0) + 1e-3) * 0.1)
+    theta, _, _, _ = rand_case(1, n_in, 53)
+    mu = f32(D[:, 1:].mean(0))
+    isg = f32(1.0 / (D[:, 1:].std(0) + 1e-6))
+    net = surrogate.Network(n_in, seed=0)
+    f = lambda a: torch.tensor(a, dtype=torch.float32, device="cuda")
+    net.theta, net.mu, net.inv_sigma = f(theta), f(mu), f(isg)
+    o = m.energy_forces_surrogate(pos, w.cell, nb, c, net)
+    y_dev, _ = net.forward(m.h, Dd, x_col=1, ldx=m.M)
+    e = m.energy_forces_surrogate(pos, w.cell, nb, c, net, forces=False, virial=False)
+    torch.cuda.synchronize()
+    E_atom = o["E_atom"].double().cpu().numpy()
+    F = o["F"].double().cpu().numpy()
+    e1 = relerr(E_atom, D @ c + y_dev.double().cpu().numpy())
+    say(f"[gpu]   E_atom rel {e1:.2e} against descriptors + network kernel (every atom)")
+    assert e1 < 1e-5
+    assert np.array_equal(e["E_atom"].double().cpu().numpy(), E_atom)
+    assert np.isfinite(F).all() and np.abs(F.sum(0)).max() <= 1e-4 * np.abs(F).max() * np.sqrt(len(pos))
+
+
 def test_surrogate_silent_network_equals_linear_path(sur_case):
     """w3 = 0, b3 = 0: the surrogate path must reproduce pod_energy_forces
     with the 2/3-body coefficients to FP64 rounding (the network adds exact
