@@ -227,7 +227,8 @@ __device__ __forceinline__ void atom_body(const KArgs<T>& g) {
         if (b < 0 || e < b || e > g.P) eb |= ERR_NEIGH;
         else { beg = b; cnt = e - b; }
     }
-    const int nround = (wave_max(cnt) + K - 1) / K;
+    const int wmax = __builtin_amdgcn_readfirstlane(wave_max(cnt));   // the wavefront's longest neighbour list
+    const int nround = (wmax + K - 1) / K;
     T pi[3] = {T(0), T(0), T(0)};
     if (act) { pi[0] = g.pos[3 * atom + 0]; pi[1] = g.pos[3 * atom + 1]; pi[2] = g.pos[3 * atom + 2]; }
 
@@ -272,7 +273,10 @@ __device__ __forceinline__ void atom_body(const KArgs<T>& g) {
             }
             wave_sync();
             if (act) {
-                for (int s = 0; s < K; ++s) {
+                // slots past the wavefront's longest list (in its last round)
+                // hold R = 0 for every atom: not visited
+                const int ns = wmax - rd * K < K ? wmax - rd * K : K;
+                for (int s = 0; s < ns; ++s) {
                     const T* row = sT + (al * K + s) * SS;
                     accumulate_basis<T, PA>(acc, row[3 + m], row[0], row[1], row[2]);
                 }
